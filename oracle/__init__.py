@@ -1,0 +1,168 @@
+"""CPU oracle for the coined quantum walk (arXiv:1003.3779).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``, never by the product package.
+It shares no code with the HIP path.
+
+The arithmetic lives in ``qw_oracle.c`` (plain complex128 loops, built with
+``-O2 -ffp-contract=off``); this module only marshals numpy arrays through
+ctypes.  State arrays here are complex128 of shape (Ly, Lx, d): position-major
+with the coin index innermost.  A ring of N sites is the torus (1, N).
+
+Functions and the passages they follow (see ``qw_oracle.c`` for the details):
+  coin(kind, d, ...)        coin families named in Sec. 3 after Eq. (7)
+  evolve(psi, ...)          T steps of U = S (I (x) C), Eqs. (2)-(3), (8), (10)
+  evolve_inverse(psi, ...)  T steps of U^-1, unitarity of Eq. (2)
+  prob(psi)                 P(x) = sum_c |psi(x,c)|^2, Eqs. (4)-(6)
+  norm(P)                   sum_x P(x)
+  bin_ring(P, x0, nbins)    symmetric binning of a ring distribution
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qw_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+HADAMARD, SU2, GROVER, HADAMARD2, FOURIER, DENSE = range(6)
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile qw_oracle.c into liboracle.so with gcc (plain C, fp64)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+            _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, i32, dp, ip = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+        lib.orc_coin.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.orc_coin.restype = i32
+        lib.orc_evolve.argtypes = [i64, i64, i32, ip, dp, dp, i64, i32, i64, i64, i64]
+        lib.orc_evolve.restype = i32
+        lib.orc_evolve_inverse.argtypes = [i64, i64, i32, ip, dp, dp, i64]
+        lib.orc_evolve_inverse.restype = i32
+        lib.orc_prob.argtypes = [i64, i32, dp, dp]
+        lib.orc_prob.restype = None
+        lib.orc_norm.argtypes = [i64, dp]
+        lib.orc_norm.restype = ctypes.c_double
+        lib.orc_bin.argtypes = [i64, i64, dp, i32, dp]
+        lib.orc_bin.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def coin(kind: int, d: int, theta: float = 0.0, phi: float = 0.0, chi: float = 0.0,
+         dense: np.ndarray | None = None) -> np.ndarray:
+    """The d x d coin matrix of the given family (complex128)."""
+    lib = _load()
+    out = np.zeros((d, d), dtype=np.complex128)
+    dn = None
+    if dense is not None:
+        dn = np.ascontiguousarray(dense, dtype=np.complex128)
+        if dn.shape != (d, d):
+            raise ValueError("dense coin must be d x d")
+    rc = lib.orc_coin(kind, d, theta, phi, chi, _ptr(dn) if dn is not None else None, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"orc_coin: bad coin kind={kind} d={d}")
+    return out
+
+
+def _disp_array(disp, d):
+    a = np.ascontiguousarray(np.asarray(disp, dtype=np.int32).reshape(d, 2))
+    return a
+
+
+def initial_state(Lx: int, Ly: int, d: int, x0, psi0) -> np.ndarray:
+    """psi_0 = |x0> (x) psi0 as a (Ly, Lx, d) complex128 array."""
+    psi = np.zeros((Ly, Lx, d), dtype=np.complex128)
+    psi[x0[1] % Ly, x0[0] % Lx, :] = np.asarray(psi0, dtype=np.complex128)
+    return psi
+
+
+def evolve(psi: np.ndarray, disp, C: np.ndarray, T: int, windowed: bool = False,
+           x0=(0, 0), t0: int = 0) -> np.ndarray:
+    """T steps of U = S (I (x) C) on a copy of psi (shape (Ly, Lx, d)).
+
+    windowed=True asserts that psi vanishes outside the box of radius t0 about
+    x0 and updates only the light-cone box at each step.
+    """
+    lib = _load()
+    Ly, Lx, d = psi.shape
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    da = _disp_array(disp, d)
+    Cc = np.ascontiguousarray(C, dtype=np.complex128)
+    rc = lib.orc_evolve(Lx, Ly, d, _ptr(da), _ptr(Cc), _ptr(out), int(T), int(bool(windowed)),
+                        int(x0[0]), int(x0[1]), int(t0))
+    if rc != 0:
+        raise RuntimeError("orc_evolve failed")
+    return out
+
+
+def evolve_inverse(psi: np.ndarray, disp, C: np.ndarray, T: int) -> np.ndarray:
+    """T steps of U^-1 = (I (x) C^dagger) S^-1 on a copy of psi."""
+    lib = _load()
+    Ly, Lx, d = psi.shape
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    da = _disp_array(disp, d)
+    Cc = np.ascontiguousarray(C, dtype=np.complex128)
+    rc = lib.orc_evolve_inverse(Lx, Ly, d, _ptr(da), _ptr(Cc), _ptr(out), int(T))
+    if rc != 0:
+        raise RuntimeError("orc_evolve_inverse failed")
+    return out
+
+
+def prob(psi: np.ndarray) -> np.ndarray:
+    """P(x) = sum_c |psi(x,c)|^2 as a (Ly, Lx) float64 array."""
+    lib = _load()
+    Ly, Lx, d = psi.shape
+    p = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.empty((Ly, Lx), dtype=np.float64)
+    lib.orc_prob(Lx * Ly, d, _ptr(p), _ptr(out))
+    return out
+
+
+def norm(P: np.ndarray) -> float:
+    """sum_x P(x), pairwise summation."""
+    lib = _load()
+    p = np.ascontiguousarray(P, dtype=np.float64).ravel()
+    return float(lib.orc_norm(p.size, _ptr(p)))
+
+
+def bin_ring(P: np.ndarray, x0: int, nbins: int = 512) -> np.ndarray:
+    """Symmetric binning of a ring distribution P (length N) about x0."""
+    lib = _load()
+    p = np.ascontiguousarray(P, dtype=np.float64).ravel()
+    out = np.zeros(nbins, dtype=np.float64)
+    rc = lib.orc_bin(p.size, int(x0), _ptr(p), int(nbins), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_bin: bad arguments")
+    return out
+
+
+def walk(Lx: int, Ly: int, disp, C: np.ndarray, x0, psi0, T: int, windowed: bool = True) -> np.ndarray:
+    """psi_T for a walk started at |x0> (x) psi0 (light-cone windowed by default)."""
+    d = C.shape[0]
+    psi = initial_state(Lx, Ly, d, x0, psi0)
+    return evolve(psi, disp, C, T, windowed=windowed, x0=x0, t0=0)
