@@ -1,0 +1,180 @@
+/*
+ * qwalk.h -- C ABI of libqwalk.so, an MI355X (gfx950) engine for the
+ * discrete-time coined quantum walk of Sawerwain & Gielerak, "GPGPU based
+ * simulations for one and two dimensional quantum walks" (arXiv:1003.3779).
+ *
+ * The walk (Sec. 2.1, Eqs. (2)-(3); Sec. 3, Eqs. (8), (10) with every link
+ * intact): one step is U = S (I (x) C) -- the coin C acts on the d-dimensional
+ * coin register of every site, then the shift S moves coin component c from
+ * site x to x + e_c.  As a gather:
+ *     psi'(x, c) = sum_{c'} C[c][c'] psi(x - e_c, c'),
+ * with positions taken modulo the lattice extents (periodic ring / torus).
+ * The run ends with the position distribution P(x) = sum_c |psi(x, c)|^2
+ * (normalisation of Eqs. (4)-(6)).
+ *
+ * Conventions for every entry point:
+ *  - Return value: QW_OK (0) or a negative qw_status.  Nothing aborts; on error
+ *    a message is kept per thread and returned by walk_last_error().
+ *  - Streams: every call enqueues its work on the hipStream_t given at create
+ *    time (NULL = the legacy default stream) and returns without waiting,
+ *    except calls that write to host memory, which synchronise that stream.
+ *  - Pointers are host pointers unless an argument says "device".  Device
+ *    pointers must be valid HIP device allocations on the current device of
+ *    the calling thread when the walk was created.
+ *  - Layouts: a state psi is d planes of V = extent[0] * extent[1] complex
+ *    numbers, plane-major, x fastest: psi[(c * extent[1] + y) * extent[0] + x],
+ *    each complex two doubles (re, im) in complex128 layout.  P(x) is V
+ *    doubles, y-major, x fastest.
+ *  - Ownership: the handle owns everything it allocates; the caller owns
+ *    every buffer it passes in (and, for walk_create_ext, must keep the
+ *    state buffers alive until walk_destroy).
+ */
+#ifndef QWALK_H
+#define QWALK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qw_walk *qw_walk_t;
+
+typedef enum {
+    QW_OK = 0,
+    QW_EINVAL = -1,    /* bad argument (null pointer, size, table, coin not unitary, ...) */
+    QW_ENOMEM = -2,    /* device allocation failed */
+    QW_EHIP = -3,      /* a HIP runtime call failed; the message carries hipGetErrorString */
+    QW_ERANGE = -4,    /* a size is outside what the library supports */
+    QW_ENOTNORM = -5   /* a state is not normalised (| ||psi||^2 - 1 | > 1e-12) */
+} qw_status;
+
+/* Amplitude precision.  QW_C128: complex128 amplitudes, fp64 arithmetic.
+ * QW_C64: complex64 amplitudes and fp32 step arithmetic; P(x), the norm and
+ * the renormalisation scale are always computed in fp64. */
+typedef enum { QW_C128 = 0, QW_C64 = 1 } qw_prec;
+
+/* Coin families.  The paper names Hadamard, Fourier and Grover coins
+ * (Sec. 3, after Eq. (7)) without writing them out; the definitions used:
+ *   QW_COIN_HADAMARD   [[1, 1], [1, -1]] / sqrt 2                     d = 2
+ *   QW_COIN_SU2        [[e^{i phi} cos t, e^{i chi} sin t],
+ *                       [-e^{-i chi} sin t, e^{-i phi} cos t]]         d = 2
+ *   QW_COIN_GROVER     G[a][b] = 2/d - delta_ab                        d = 2, 4
+ *   QW_COIN_HADAMARD2  kron(H, H), component c = 2j + k               d = 4
+ *   QW_COIN_FOURIER    F[a][b] = exp(2 pi i ab / d) / sqrt d           d = 2, 4
+ *   QW_COIN_DENSE      caller's d x d matrix (must be unitary)         d = 2, 4 */
+typedef enum {
+    QW_COIN_HADAMARD = 0,
+    QW_COIN_SU2 = 1,
+    QW_COIN_GROVER = 2,
+    QW_COIN_HADAMARD2 = 3,
+    QW_COIN_FOURIER = 4,
+    QW_COIN_DENSE = 5
+} qw_coin_kind;
+
+/* Lattice: a ring Z_N (dim 1, d = 2) or a torus Z_Lx x Z_Ly (dim 2, d = 4).
+ * disp[c] = (dx, dy) is the displacement e_c of coin component c, each entry
+ * in {-1, 0, 1} (dy = 0 on a ring).  Eq. (8) gives one such table, the
+ * diagonal lattice of Fig. 1c another; any table is accepted. */
+typedef struct {
+    int32_t dim;         /* 1 or 2 */
+    int32_t d;           /* coin dimension: 2 for a ring, 4 for a torus */
+    int64_t extent[2];   /* N (and 1), or Lx, Ly; each in [1, 2^31 - 1] */
+    int32_t disp[4][2];  /* e_c per component; rows >= d ignored */
+} qw_lattice;
+
+typedef struct {
+    int32_t kind;            /* qw_coin_kind */
+    double theta, phi, chi;  /* SU(2) angles, used by QW_COIN_SU2 */
+    const double *dense;     /* host, d*d complex row-major (re, im); QW_COIN_DENSE only */
+} qw_coin;
+
+/* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
+ * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
+ * renorm_tol 1e-7. */
+typedef struct {
+    int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
+                              or 2, 4, 8, 16 (temporal blocking) */
+    int32_t window;        /* 1: update only the light cone of the start site (exact, the
+                              rest is zero); 0: sweep the whole lattice every step */
+    int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
+                              rescale psi by 1/sqrt(n) when |n - 1| > renorm_tol */
+    double renorm_tol;
+} qw_options;
+
+typedef struct {
+    int64_t t;                /* steps taken (forward minus inverse) */
+    int64_t renorm_checks;    /* norm checks run */
+    int64_t renorms;          /* rescalings applied (read back from the device) */
+    double last_norm;         /* norm seen by the latest check (read back from the device) */
+    int64_t launches;         /* kernel launches issued by walk_step / walk_step_inverse */
+    int64_t updates;          /* site*coin updates performed (window-limited) */
+} qw_stats;
+
+/* Create a walk in the state |x0> (x) psi0 at t = 0.
+ *  lattice, coin: see above.  The coin must be unitary to 1e-12 (max-abs of
+ *      C^dagger C - I), else QW_EINVAL.
+ *  psi0: host, d complex (re, im) doubles; | ||psi0||^2 - 1 | <= 1e-12, else
+ *      QW_ENOTNORM.
+ *  x0: host, 2 int64 (x0[1] ignored on a ring), reduced modulo the extents.
+ *  prec: qw_prec.  stream: a hipStream_t or NULL.
+ *  out: receives the handle.  Allocates two state buffers of
+ *      walk_state_bytes() each plus a small fp64 scratch area. */
+int walk_create(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
+                const int64_t *x0, int32_t prec, void *stream, qw_walk_t *out);
+
+/* As walk_create, but the two state buffers (device, walk_state_bytes() each,
+ * 256-byte aligned) are the caller's, e.g. torch tensors; the handle never
+ * frees them. */
+int walk_create_ext(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
+                    const int64_t *x0, int32_t prec, void *stream, void *state_a,
+                    void *state_b, qw_walk_t *out);
+
+/* Bytes of one state buffer for this lattice and precision (d * V complex). */
+int walk_state_bytes(const qw_lattice *lattice, int32_t prec, size_t *bytes);
+
+/* Advance the walk by T >= 0 steps of U (Eq. (2)). Asynchronous. */
+int walk_step(qw_walk_t w, int64_t T);
+
+/* Apply T >= 0 steps of U^-1 = (I (x) C^dagger) S^-1. Asynchronous. */
+int walk_step_inverse(qw_walk_t w, int64_t T);
+
+/* P(x) = sum_c |psi(x, c)|^2 in fp64, c ascending, for every site.
+ * out: V doubles; a device pointer if out_on_device != 0 (asynchronous),
+ * else a host pointer (synchronises the stream). */
+int walk_probabilities(qw_walk_t w, double *out, int32_t out_on_device);
+
+/* n = sum_x P(x), the squared 2-norm of psi, reduced in fp64 on the device
+ * (deterministic two-pass reduction).  out: host double.  Synchronises. */
+int walk_norm(qw_walk_t w, double *out);
+
+/* Copy psi_t out as complex128 in the layout above (complex64 states are
+ * widened).  out: 2 * d * V doubles, device if out_on_device, else host
+ * (then synchronises). */
+int walk_get_state(qw_walk_t w, double *out, int32_t out_on_device);
+
+/* Replace psi by a caller state (complex128, layout above; narrowed to
+ * complex64 for QW_C64).  The state must be normalised to 1e-12 (checked in
+ * fp64 on the device; synchronises), else QW_ENOTNORM.  The light-cone window
+ * is switched to the whole lattice; t is kept. */
+int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device);
+
+int walk_set_options(qw_walk_t w, const qw_options *opt);
+int walk_get_options(qw_walk_t w, qw_options *opt);
+/* Steps taken so far. */
+int walk_time(qw_walk_t w, int64_t *t);
+/* Counters; synchronises the stream to read the device-side renorm counters. */
+int walk_stats(qw_walk_t w, qw_stats *out);
+
+/* Release the handle and what it allocated (not caller buffers).  Waits for
+ * the handle's pending work first.  NULL is accepted. */
+int walk_destroy(qw_walk_t w);
+
+/* Message of the latest failing call on this thread ("" if none). */
+const char *walk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QWALK_H */

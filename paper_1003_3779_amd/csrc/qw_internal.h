@@ -1,0 +1,83 @@
+// qw_internal.h -- types shared by the host runtime (qw_api.hip) and the
+// kernel launchers (qw_kernels.hip) of libqwalk.so.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qw {
+
+enum Prec { C128 = 0, C64 = 1 };
+enum CoinImpl { COIN_DENSE = 0, COIN_GROVER4 = 1, COIN_HH4 = 2 };
+// Displacement tables with a specialised temporally blocked 2D kernel.
+enum Table { TABLE_OTHER = 0, TABLE_PAIR = 1, TABLE_EQ8 = 2, TABLE_DIAG = 3 };
+
+// A box of sites on the periodic lattice: x in [x0, x0 + wx), y in [y0, y0 + wy),
+// both taken modulo the extents; x0 < Lx, y0 < Ly, wx <= Lx, wy <= Ly.
+struct Box {
+    int32_t x0, wx, y0, wy;
+};
+
+// Everything a kernel needs to know about the lattice.
+struct Geom {
+    int64_t ps;        // plane stride in complex elements (= Lx * Ly)
+    int32_t Lx, Ly;
+    int32_t d;
+    int32_t ex[4], ey[4];  // displacement e_c of component c
+};
+
+// A d x d coin matrix in fp64 (row-major), converted per precision in the launchers.
+struct CoinF64 {
+    double re[16], im[16];
+};
+
+// Device scratch of one walk (fp64): reduction partials, the norm and the
+// renormalisation counter.
+constexpr int kRedBlocks = 1024;  // blocks of the first reduction pass
+struct Scratch {
+    double partial[kRedBlocks];
+    double norm;        // result of the latest reduction
+    double last_check;  // norm seen by the latest renormalisation check
+    unsigned long long renorms;
+    unsigned long long pad;
+};
+
+// ---- launchers (qw_kernels.hip); all return a hipError_t ----
+hipError_t launch_fill_zero(void *buf, size_t bytes, hipStream_t s);
+hipError_t launch_place(int prec, void *state, const Geom &g, int64_t x0, int64_t y0,
+                        const double *psi0, hipStream_t s);
+// one step of U over the output box (in -> out)
+hipError_t launch_step(int prec, int coin_impl, const void *in, void *out, const Geom &g,
+                       const Box &out_box, const CoinF64 &C, hipStream_t s);
+// one step of U^-1 over the output box; Cdag is C^dagger
+hipError_t launch_step_inverse(int prec, const void *in, void *out, const Geom &g,
+                               const Box &out_box, const CoinF64 &Cdag, hipStream_t s);
+// K steps of a ring of N = g.Lx sites held whole by one workgroup
+hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
+                             const CoinF64 &C, int64_t K, hipStream_t s);
+int ring_whole_max_sites(int prec);
+// K steps of a ring, wave-sized register tiles over the output window box
+hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
+                             const Box &out_box, const CoinF64 &C, int K, hipStream_t s);
+// K steps on a torus with the row-streaming register kernel
+hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out,
+                           const Geom &g, const Box &out_box, const CoinF64 &C, int K,
+                           hipStream_t s);
+bool stream2d_supported(int prec, int table, int K);
+// P(x) (if P != nullptr) and the fp64 norm into scratch->norm.  psi_box: the box
+// outside which psi is zero.
+hipError_t launch_prob_norm(int prec, const void *state, const Geom &g, const Box &psi_box,
+                            double *P, Scratch *scr, hipStream_t s);
+// norm of the state (no shift needed: S is a permutation) into scratch->norm
+hipError_t launch_norm(int prec, const void *state, const Geom &g, const Box &box,
+                       Scratch *scr, hipStream_t s);
+// conditional rescale by 1/sqrt(scratch->norm) when |norm - 1| > tol
+hipError_t launch_renorm(int prec, void *state, const Geom &g, const Box &box, double tol,
+                         Scratch *scr, hipStream_t s);
+// psi (complex128, plane-major) <-> pre-shift state
+hipError_t launch_get_state(int prec, const void *state, const Geom &g, double *out,
+                            hipStream_t s);
+hipError_t launch_set_state(int prec, void *state, const Geom &g, const double *in,
+                            Scratch *scr, hipStream_t s);
+
+}  // namespace qw

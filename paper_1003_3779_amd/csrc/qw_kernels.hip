@@ -1,0 +1,924 @@
+// qw_kernels.hip -- HIP kernels for gfx950 (CDNA4) of the coined quantum walk.
+//
+// State representation.  The walk is U = S (I (x) C) (Sec. 2.1, Eq. (2)):
+// coin, then shift.  Kernels keep the *pre-shift* state a_t, defined by
+//     psi_t = S a_t,   i.e.  psi_t(x, c) = a_t(x - e_c, c),
+// so that one step becomes
+//     a_{t+1}(y, c) = sum_{c'} C[c][c'] a_t(y - e_{c'}, c').
+// Each output site reads one value per coin plane, every plane from its own
+// fixed neighbour (a uniform shift of the whole plane, so loads stay
+// coalesced), mixes them with the d x d coin in registers and writes d
+// values: one complex read and one complex write per site*coin update.  The
+// arithmetic of one step is the same expression as the gather form of
+// Eq. (10) with intact links,
+//     psi_{t+1}(x, c) = a_{t+1}(x - e_c, c) = sum_{c'} C[c][c'] psi_t(x - e_c, c'),
+// only the place where the result is stored differs.  The start state is
+// a_0(x0 - e_c, c) = psi_0(c); P(x) reads a(x - e_c, c).
+//
+// Memory layout: d planes of V = Lx * Ly complex numbers (double2 / float2,
+// interleaved re/im), plane-major, x fastest.  Two such buffers ping-pong.
+//
+// Light cone: a walker moves at most one site per axis per step (the "line"
+// walk of Sec. 3 and its cost model, Eqs. (13)-(18)), so amplitudes outside
+// a box growing by one site per step are exactly zero.  Kernels take the
+// box they must write; both buffers are zero outside the boxes ever written.
+#include "qw_internal.h"
+
+#include <math.h>
+
+namespace qw {
+namespace {
+
+template <typename R> struct VT;
+template <> struct VT<double> { using T = double2; };
+template <> struct VT<float> { using T = float2; };
+template <typename R> using cv = typename VT<R>::T;
+
+template <typename R> struct CoinR {
+    R re[16];
+    R im[16];
+};
+
+template <typename R> CoinR<R> to_coin(const CoinF64 &c) {
+    CoinR<R> o;
+    for (int i = 0; i < 16; ++i) {
+        o.re[i] = (R)c.re[i];
+        o.im[i] = (R)c.im[i];
+    }
+    return o;
+}
+
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename R> __device__ __forceinline__ cv<R> czero() {
+    cv<R> z;
+    z.x = (R)0;
+    z.y = (R)0;
+    return z;
+}
+template <typename R> __device__ __forceinline__ cv<R> cadd(cv<R> a, cv<R> b) {
+    cv<R> r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename R> __device__ __forceinline__ cv<R> csub(cv<R> a, cv<R> b) {
+    cv<R> r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename R> __device__ __forceinline__ cv<R> cscale(cv<R> a, R s) {
+    cv<R> r;
+    r.x = a.x * s;
+    r.y = a.y * s;
+    return r;
+}
+// (cr + i ci) * v.  The fused multiply-adds are written out so that every
+// kernel rounds a coin application identically (blocked == unblocked, bit
+// for bit), whatever the compiler's contraction choices.
+template <typename R> __device__ __forceinline__ cv<R> cmul(R cr, R ci, cv<R> v) {
+    cv<R> r;
+    r.x = fmaR(cr, v.x, -(ci * v.y));
+    r.y = fmaR(cr, v.y, ci * v.x);
+    return r;
+}
+// acc + (cr + i ci) * v
+template <typename R> __device__ __forceinline__ cv<R> cmac(cv<R> acc, R cr, R ci, cv<R> v) {
+    acc.x = fmaR(cr, v.x, acc.x);
+    acc.x = fmaR(-ci, v.y, acc.x);
+    acc.y = fmaR(cr, v.y, acc.y);
+    acc.y = fmaR(ci, v.x, acc.y);
+    return acc;
+}
+
+// ---- the coin on one site's d gathered values (components in ascending order) ----
+template <typename R, int D, int COIN> struct Coin;
+
+template <typename R, int D> struct Coin<R, D, COIN_DENSE> {
+    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &C) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            cv<R> acc = cmul<R>(C.re[c * D], C.im[c * D], g[0]);
+#pragma unroll
+            for (int k = 1; k < D; ++k) acc = cmac<R>(acc, C.re[c * D + k], C.im[c * D + k], g[k]);
+            o[c] = acc;
+        }
+    }
+};
+// Grover, d = 4: G = J/2 - I, so (G g)_c = (g0 + g1 + g2 + g3)/2 - g_c.
+template <typename R> struct Coin<R, 4, COIN_GROVER4> {
+    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &) {
+        cv<R> s = cscale<R>(cadd<R>(cadd<R>(g[0], g[1]), cadd<R>(g[2], g[3])), (R)0.5);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] = csub<R>(s, g[c]);
+    }
+};
+// H (x) H, d = 4, c = 2j + k: two butterfly levels and a factor 1/2.
+template <typename R> struct Coin<R, 4, COIN_HH4> {
+    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &) {
+        cv<R> u0 = cadd<R>(g[0], g[1]), u1 = csub<R>(g[0], g[1]);
+        cv<R> u2 = cadd<R>(g[2], g[3]), u3 = csub<R>(g[2], g[3]);
+        o[0] = cscale<R>(cadd<R>(u0, u2), (R)0.5);
+        o[1] = cscale<R>(cadd<R>(u1, u3), (R)0.5);
+        o[2] = cscale<R>(csub<R>(u0, u2), (R)0.5);
+        o[3] = cscale<R>(csub<R>(u1, u3), (R)0.5);
+    }
+};
+
+__device__ __forceinline__ int wrapi(int v, int L) {
+    v = v < 0 ? v + L : v;
+    return v >= L ? v - L : v;
+}
+
+// ---- cross-lane moves of one complex value within a wave64 ----
+// from_left: lane i receives lane i-1's value; from_right: lane i receives
+// lane i+1's value.  The edge lanes receive their own value (they are halo).
+template <typename R> __device__ __forceinline__ cv<R> from_left(cv<R> v) {
+    cv<R> r;
+    r.x = __shfl_up(v.x, 1, 64);
+    r.y = __shfl_up(v.y, 1, 64);
+    return r;
+}
+template <typename R> __device__ __forceinline__ cv<R> from_right(cv<R> v) {
+    cv<R> r;
+    r.x = __shfl_down(v.x, 1, 64);
+    r.y = __shfl_down(v.y, 1, 64);
+    return r;
+}
+
+// =====================================================================
+// fill / place
+// =====================================================================
+// zero n16 16-byte words, then (tail8 != 0) one trailing 8-byte word
+__global__ void k_fill_zero(uint4 *p, size_t n16, int tail8) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint4 z = make_uint4(0, 0, 0, 0);
+    for (; i < n16; i += stride) p[i] = z;
+    if (tail8 && blockIdx.x == 0 && threadIdx.x == 0) *(uint2 *)(p + n16) = make_uint2(0, 0);
+}
+
+struct Psi0 {
+    double re[4], im[4];
+};
+
+template <typename R>
+__global__ void k_place(cv<R> *a, Geom g, int x0, int y0, Psi0 p) {
+    int c = threadIdx.x;
+    if (c >= g.d) return;
+    int x = wrapi(x0 - g.ex[c], g.Lx), y = wrapi(y0 - g.ey[c], g.Ly);
+    cv<R> v;
+    v.x = (R)p.re[c];
+    v.y = (R)p.im[c];
+    a[(int64_t)c * g.ps + (int64_t)y * g.Lx + x] = v;
+}
+
+// =====================================================================
+// one step (k = 1): one thread per output site of the box
+// =====================================================================
+template <typename R, int D, int COIN>
+__global__ __launch_bounds__(256) void k_step(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                              Geom g, Box b, CoinR<R> C) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= b.wx) return;
+    int x = b.x0 + i;
+    x = x >= g.Lx ? x - g.Lx : x;
+    int sx[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) sx[c] = wrapi(x - g.ex[c], g.Lx);
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        cv<R> v[D], o[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            int sy = wrapi(y - g.ey[c], g.Ly);
+            v[c] = in[(int64_t)c * g.ps + (int64_t)sy * g.Lx + sx[c]];
+        }
+        Coin<R, D, COIN>::apply(v, o, C);
+        const int64_t o0 = (int64_t)y * g.Lx + x;
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[(int64_t)c * g.ps + o0] = o[c];
+    }
+}
+
+// one step of U^-1: a_{t-1}(y, c) = sum_{c'} Cdag[c][c'] a_t(y + e_c, c')
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_step_inv(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                  Geom g, Box b, CoinR<R> Cd) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= b.wx) return;
+    int x = b.x0 + i;
+    x = x >= g.Lx ? x - g.Lx : x;
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        const int64_t o0 = (int64_t)y * g.Lx + x;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            int sx = wrapi(x + g.ex[c], g.Lx), sy = wrapi(y + g.ey[c], g.Ly);
+            int64_t s0 = (int64_t)sy * g.Lx + sx;
+            cv<R> acc = cmul<R>(Cd.re[c * D], Cd.im[c * D], in[s0]);
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+                acc = cmac<R>(acc, Cd.re[c * D + k], Cd.im[c * D + k], in[(int64_t)k * g.ps + s0]);
+            out[(int64_t)c * g.ps + o0] = acc;
+        }
+    }
+}
+
+// =====================================================================
+// a whole ring in one workgroup: K steps, state in registers
+// =====================================================================
+// Thread j holds sites [j*M, j*M + cnt_j) of both planes (component 0 moves
+// right, component 1 left on the ring tables; general e_c = +-1 handled by
+// the host choosing this kernel only for the table ((+1,0),(-1,0))).  Per
+// step each thread publishes its last component-0 value and first
+// component-1 value in LDS (double-buffered, so one barrier per step); the
+// ring closes through thread nl-1 <-> thread 0.
+template <typename R, int M>
+__global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                     int N, int64_t ps, int64_t K, CoinR<R> C) {
+    __shared__ cv<R> L0[2][1024];
+    __shared__ cv<R> L1[2][1024];
+    const int j = threadIdx.x;
+    const int nl = (N + M - 1) / M;
+    const bool active = j < nl;
+    const int cnt = active ? min(M, N - j * M) : 0;
+    const int jl = j == 0 ? nl - 1 : j - 1;
+    const int jr = j + 1 >= nl ? 0 : j + 1;
+    cv<R> a0[M], a1[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        a0[m] = czero<R>();
+        a1[m] = czero<R>();
+        if (m < cnt) {
+            a0[m] = in[j * M + m];
+            a1[m] = in[ps + j * M + m];
+        }
+    }
+    const R c00r = C.re[0], c00i = C.im[0], c01r = C.re[1], c01i = C.im[1];
+    const R c10r = C.re[2], c10i = C.im[2], c11r = C.re[3], c11i = C.im[3];
+    for (int64_t s = 0; s < K; ++s) {
+        const int p = (int)(s & 1);
+        if (active) {
+            cv<R> last = a0[0];
+#pragma unroll
+            for (int m = 1; m < M; ++m)
+                if (m < cnt) last = a0[m];
+            L0[p][j] = last;
+            L1[p][j] = a1[0];
+        }
+        __syncthreads();
+        if (active) {
+            const cv<R> left = L0[p][jl], right = L1[p][jr];
+            cv<R> n0[M], n1[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+                const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
+                n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                a0[m] = n0[m];
+                a1[m] = n1[m];
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        if (m < cnt) {
+            out[j * M + m] = a0[m];
+            out[ps + j * M + m] = a1[m];
+        }
+}
+
+// =====================================================================
+// a long ring: K steps per launch in wave-sized register tiles
+// =====================================================================
+// Each wave loads 64*M consecutive sites (M per lane) of both planes, steps
+// them K times in registers -- the lane-boundary values move by one lane per
+// step -- and writes back the 64*M - 2K sites whose light cone stayed inside
+// the tile.  Requires N >= 64*M so that a tile never meets itself.
+template <typename R, int M, int K>
+__global__ __launch_bounds__(256) void k_ring_tiles(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                    int N, int64_t ps, Box b, CoinR<R> C) {
+    constexpr int TW = 64 * M - 2 * K;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int o0 = wave * TW;  // first output offset of this tile within the box
+    if (o0 >= b.wx) return;    // wave-uniform: no barriers in this kernel
+    int base = b.x0 + o0 - K + lane * M;
+    base %= N;
+    base = base < 0 ? base + N : base;
+    cv<R> a0[M], a1[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int x = base + m;
+        x = x >= N ? x - N : x;
+        a0[m] = in[x];
+        a1[m] = in[ps + x];
+    }
+    const R c00r = C.re[0], c00i = C.im[0], c01r = C.re[1], c01i = C.im[1];
+    const R c10r = C.re[2], c10i = C.im[2], c11r = C.re[3], c11i = C.im[3];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const cv<R> left = from_left<R>(a0[M - 1]);
+        const cv<R> right = from_right<R>(a1[0]);
+        cv<R> n0[M], n1[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+            const cv<R> g1 = m == M - 1 ? right : a1[m == M - 1 ? m : m + 1];
+            n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
+            n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            a0[m] = n0[m];
+            a1[m] = n1[m];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int q = lane * M + m;
+        if (q >= K && q < 64 * M - K && o0 + q - K < b.wx) {
+            int x = base + m;
+            x = x >= N ? x - N : x;
+            out[x] = a0[m];
+            out[ps + x] = a1[m];
+        }
+    }
+}
+
+// =====================================================================
+// torus: K steps per launch, row-streaming register kernel
+// =====================================================================
+// One wave owns a strip of 64*M columns (M adjacent columns per lane) and
+// walks down a segment of rows.  Time level s (0 = input) lives in
+// registers as a three-row window; at stream iteration i the wave loads input
+// row r_i = y_seg - K + i and computes level s at row r_i - s for every s, so
+// each level consumes the three newest rows of the level below (rows r-1, r,
+// r+1 for the components that move along y) while x-moves take one lane of
+// neighbour exchange.  After K levels, row r_i - K is final and the columns
+// whose cone stayed inside the strip (64*M - 2K of them) go to HBM: the state
+// makes one HBM round trip per K steps.  The three row slots rotate with the
+// iteration index; unrolling the stream loop by three makes every slot index
+// a compile-time constant so the whole window stays in VGPRs.
+// displacement e_c = (tab_ex, tab_ey) of the tables with a specialised kernel
+__host__ __device__ constexpr int tab_ex(int table, int c) {
+    return table == TABLE_PAIR ? (c == 0 ? 1 : (c == 1 ? -1 : 0))
+         : table == TABLE_EQ8  ? (c == 1 ? 1 : (c == 2 ? -1 : 0))
+                               : (c < 2 ? 1 : -1);  // TABLE_DIAG
+}
+__host__ __device__ constexpr int tab_ey(int table, int c) {
+    return table == TABLE_PAIR ? (c == 2 ? 1 : (c == 3 ? -1 : 0))
+         : table == TABLE_EQ8  ? (c == 0 ? 1 : (c == 3 ? -1 : 0))
+                               : ((c & 1) == 0 ? 1 : -1);  // TABLE_DIAG
+}
+
+template <typename R, int K, int M> struct StreamRegs {
+    cv<R> v[K][3][4][M];  // [level][row slot][component][column]
+};
+
+template <typename R, int K, int M, int TABLE, int COIN, int PH>
+__device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, const cv<R> *__restrict__ in,
+                                            cv<R> *__restrict__ out, const Geom &g, const int (&xcol)[M],
+                                            const bool (&store_col)[M], int row_in, int row_out,
+                                            bool do_store, const CoinR<R> &C) {
+    // slot PH receives the newest row, slot (PH+2)%3 holds the row before it
+    // (the row being computed at the next level), slot (PH+1)%3 the oldest.
+    constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
+    cv<R> cur[4][M];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            cur[c][m] = in[(int64_t)c * g.ps + (int64_t)row_in * g.Lx + xcol[m]];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < M; ++m) st.v[s][NEW][c][m] = cur[c][m];
+        // gather for the row in slot MID of level s
+        cv<R> gth[4][M];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int ey = tab_ey(TABLE, c), ex = tab_ex(TABLE, c);
+            const int slot = ey > 0 ? OLD : (ey < 0 ? NEW : MID);
+            if (ex == 0) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) gth[c][m] = st.v[s][slot][c][m];
+            } else if (ex > 0) {
+                const cv<R> nb = from_left<R>(st.v[s][slot][c][M - 1]);
+#pragma unroll
+                for (int m = 0; m < M; ++m) gth[c][m] = m == 0 ? nb : st.v[s][slot][c][m == 0 ? 0 : m - 1];
+            } else {
+                const cv<R> nb = from_right<R>(st.v[s][slot][c][0]);
+#pragma unroll
+                for (int m = 0; m < M; ++m) gth[c][m] = m == M - 1 ? nb : st.v[s][slot][c][m == M - 1 ? m : m + 1];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cv<R> gi[4], go[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gi[c] = gth[c][m];
+            Coin<R, 4, COIN>::apply(gi, go, C);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cur[c][m] = go[c];
+        }
+    }
+    if (do_store) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (store_col[m]) out[(int64_t)c * g.ps + (int64_t)row_out * g.Lx + xcol[m]] = cur[c][m];
+    }
+}
+
+template <typename R, int K, int M, int TABLE, int COIN>
+__global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                  Geom g, Box b, int seg_rows, int nstrips, CoinR<R> C) {
+    constexpr int TW = 64 * M - 2 * K;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int strip = wave % nstrips, seg = wave / nstrips;
+    const int r0 = seg * seg_rows;  // first output row offset of this segment
+    if (r0 >= b.wy) return;         // wave-uniform exit; no barriers in this kernel
+    const int nrows = min(seg_rows, b.wy - r0);
+    const int c0 = strip * TW;      // first output column offset of this strip
+    int xcol[M];
+    bool store_col[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int q = lane * M + m;
+        int x = (b.x0 + c0 - K + q) % g.Lx;
+        xcol[m] = x < 0 ? x + g.Lx : x;
+        store_col[m] = q >= K && q < 64 * M - K && c0 + q - K < b.wx;
+    }
+    StreamRegs<R, K, M> st;
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int m = 0; m < M; ++m) st.v[s][r][c][m] = czero<R>();
+    const int niter = nrows + 2 * K;
+    int row_in = (b.y0 + r0 - K) % g.Ly;
+    row_in = row_in < 0 ? row_in + g.Ly : row_in;
+    int row_out = (b.y0 + r0 - 2 * K) % g.Ly;  // advanced in step with row_in
+    row_out = row_out < 0 ? row_out + g.Ly : row_out;
+    for (int i = 0; i < niter; i += 3) {
+        stream_iter<R, K, M, TABLE, COIN, 0>(st, in, out, g, xcol, store_col, row_in, row_out,
+                                             i >= 2 * K && i < niter, C);
+        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        stream_iter<R, K, M, TABLE, COIN, 1>(st, in, out, g, xcol, store_col, row_in, row_out,
+                                             i + 1 >= 2 * K && i + 1 < niter, C);
+        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        stream_iter<R, K, M, TABLE, COIN, 2>(st, in, out, g, xcol, store_col, row_in, row_out,
+                                             i + 2 >= 2 * K && i + 2 < niter, C);
+        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+    }
+}
+
+// =====================================================================
+// reductions (fp64): P(x), the norm, renormalisation
+// =====================================================================
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block of 256 threads -> one value in thread 0 (fixed order: deterministic)
+__device__ __forceinline__ double block_sum256(double v) {
+    __shared__ double ws[4];
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) ws[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ double abs2(cv<R> v) {
+    const double re = (double)v.x, im = (double)v.y;
+    return re * re + im * im;
+}
+
+// P(x) = sum_c |a(x - e_c, c)|^2 over the box; block partial sums of P.
+// Blocks: grid (gx, gy); block (bx, by) takes box rows by, by+gy, ... and
+// columns bx*256 + tid, + gx*256, ...
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_prob(const cv<R> *__restrict__ a, Geom g, Box b,
+                                              double *__restrict__ P, double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        for (int i = blockIdx.x * 256 + threadIdx.x; i < b.wx; i += gridDim.x * 256) {
+            int x = b.x0 + i;
+            x = x >= g.Lx ? x - g.Lx : x;
+            double p = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                int sx = wrapi(x - g.ex[c], g.Lx), sy = wrapi(y - g.ey[c], g.Ly);
+                p += abs2<R>(a[(int64_t)c * g.ps + (int64_t)sy * g.Lx + sx]);
+            }
+            if (P) P[(int64_t)y * g.Lx + x] = p;
+            acc += p;
+        }
+    }
+    const double s = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__ partial, int n,
+                                                      double *__restrict__ out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+    const double s = block_sum256(acc);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// Rescale by 1/sqrt(n) (scale in fp64) when |n - 1| > tol; n from scratch.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_renorm(cv<R> *__restrict__ a, Geom g, Box b, double tol,
+                                                Scratch *__restrict__ scr) {
+    const double n = scr->norm;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        scr->last_check = n;
+        if (fabs(n - 1.0) > tol) scr->renorms += 1ull;
+    }
+    if (!(fabs(n - 1.0) > tol)) return;
+    const double sc = 1.0 / sqrt(n);
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        for (int i = blockIdx.x * 256 + threadIdx.x; i < b.wx; i += gridDim.x * 256) {
+            int x = b.x0 + i;
+            x = x >= g.Lx ? x - g.Lx : x;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                cv<R> &v = a[(int64_t)c * g.ps + (int64_t)y * g.Lx + x];
+                v.x = (R)((double)v.x * sc);
+                v.y = (R)((double)v.y * sc);
+            }
+        }
+    }
+}
+
+// psi(x, c) = a(x - e_c, c), widened to complex128, plane-major.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_get_state(const cv<R> *__restrict__ a, Geom g, double2 *__restrict__ out) {
+    for (int y = blockIdx.y; y < g.Ly; y += gridDim.y)
+        for (int x = blockIdx.x * 256 + threadIdx.x; x < g.Lx; x += gridDim.x * 256) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                int sx = wrapi(x - g.ex[c], g.Lx), sy = wrapi(y - g.ey[c], g.Ly);
+                cv<R> v = a[(int64_t)c * g.ps + (int64_t)sy * g.Lx + sx];
+                out[(int64_t)c * g.ps + (int64_t)y * g.Lx + x] = make_double2((double)v.x, (double)v.y);
+            }
+        }
+}
+
+// a(y, c) = psi(y + e_c, c) from complex128 input; block partial sums of |psi|^2 (fp64).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_set_state(cv<R> *__restrict__ a, Geom g, const double2 *__restrict__ in,
+                                                   double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int y = blockIdx.y; y < g.Ly; y += gridDim.y)
+        for (int x = blockIdx.x * 256 + threadIdx.x; x < g.Lx; x += gridDim.x * 256) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                int sx = wrapi(x + g.ex[c], g.Lx), sy = wrapi(y + g.ey[c], g.Ly);
+                double2 v = in[(int64_t)c * g.ps + (int64_t)sy * g.Lx + sx];
+                acc += v.x * v.x + v.y * v.y;
+                cv<R> w;
+                w.x = (R)v.x;
+                w.y = (R)v.y;
+                a[(int64_t)c * g.ps + (int64_t)y * g.Lx + x] = w;
+            }
+        }
+    const double s = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// grid for box-shaped reductions: at most kRedBlocks blocks
+void red_grid(int wx, int wy, dim3 &grid) {
+    int gx = (wx + 255) / 256;
+    gx = gx < 1 ? 1 : (gx > kRedBlocks ? kRedBlocks : gx);
+    int gy = kRedBlocks / gx;
+    gy = gy < 1 ? 1 : gy;
+    gy = gy > wy ? (wy < 1 ? 1 : wy) : gy;
+    grid = dim3(gx, gy, 1);
+}
+
+dim3 step_grid(const Box &b) {
+    int gy = b.wy < 65535 ? b.wy : 65535;
+    return dim3((b.wx + 255) / 256, gy < 1 ? 1 : gy, 1);
+}
+
+}  // namespace
+
+// =====================================================================
+// launchers
+// =====================================================================
+hipError_t launch_fill_zero(void *buf, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    // every buffer of the library is a multiple of 8 bytes
+    if (bytes % 8) return hipErrorInvalidValue;
+    size_t n16 = bytes / 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint4 *)buf, n16, (int)((bytes % 16) / 8));
+    return hipGetLastError();
+}
+
+hipError_t launch_place(int prec, void *state, const Geom &g, int64_t x0, int64_t y0, const double *psi0,
+                        hipStream_t s) {
+    Psi0 p;
+    for (int c = 0; c < 4; ++c) {
+        p.re[c] = c < g.d ? psi0[2 * c] : 0.0;
+        p.im[c] = c < g.d ? psi0[2 * c + 1] : 0.0;
+    }
+    if (prec == C128)
+        hipLaunchKernelGGL(k_place<double>, dim3(1), dim3(64), 0, s, (double2 *)state, g, (int)x0, (int)y0, p);
+    else
+        hipLaunchKernelGGL(k_place<float>, dim3(1), dim3(64), 0, s, (float2 *)state, g, (int)x0, (int)y0, p);
+    return hipGetLastError();
+}
+
+template <typename R, int D, int COIN>
+static void step_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<R, D, COIN>), step_grid(b), dim3(256), 0, s, (const cv<R> *)in, (cv<R> *)out, g, b,
+                       to_coin<R>(C));
+}
+
+hipError_t launch_step(int prec, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                       const CoinF64 &C, hipStream_t s) {
+    if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
+    if (g.d == 2) {
+        if (prec == C128) step_t<double, 2, COIN_DENSE>(in, out, g, b, C, s);
+        else step_t<float, 2, COIN_DENSE>(in, out, g, b, C, s);
+    } else {
+        if (prec == C128) {
+            if (coin_impl == COIN_GROVER4) step_t<double, 4, COIN_GROVER4>(in, out, g, b, C, s);
+            else if (coin_impl == COIN_HH4) step_t<double, 4, COIN_HH4>(in, out, g, b, C, s);
+            else step_t<double, 4, COIN_DENSE>(in, out, g, b, C, s);
+        } else {
+            if (coin_impl == COIN_GROVER4) step_t<float, 4, COIN_GROVER4>(in, out, g, b, C, s);
+            else if (coin_impl == COIN_HH4) step_t<float, 4, COIN_HH4>(in, out, g, b, C, s);
+            else step_t<float, 4, COIN_DENSE>(in, out, g, b, C, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_inverse(int prec, const void *in, void *out, const Geom &g, const Box &b,
+                               const CoinF64 &Cd, hipStream_t s) {
+    if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
+    const dim3 grid = step_grid(b);
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_step_inv<double, 2>), grid, dim3(256), 0, s, (const double2 *)in, (double2 *)out, g,
+                               b, to_coin<double>(Cd));
+        else
+            hipLaunchKernelGGL((k_step_inv<float, 2>), grid, dim3(256), 0, s, (const float2 *)in, (float2 *)out, g, b,
+                               to_coin<float>(Cd));
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_step_inv<double, 4>), grid, dim3(256), 0, s, (const double2 *)in, (double2 *)out, g,
+                               b, to_coin<double>(Cd));
+        else
+            hipLaunchKernelGGL((k_step_inv<float, 4>), grid, dim3(256), 0, s, (const float2 *)in, (float2 *)out, g, b,
+                               to_coin<float>(Cd));
+    }
+    return hipGetLastError();
+}
+
+// sites per thread of the whole-ring kernel, smallest that fits N in 1024 threads
+static int ring_whole_m(int prec, int64_t N) {
+    const int maxm = prec == C128 ? 4 : 8;
+    for (int m = 1; m <= maxm; m *= 2)
+        if (N <= 1024LL * m) return m;
+    return 0;
+}
+int ring_whole_max_sites(int prec) { return 1024 * (prec == C128 ? 4 : 8); }
+
+template <typename R, int M>
+static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K, hipStream_t s) {
+    const int nl = (g.Lx + M - 1) / M;
+    const int threads = ((nl + 63) / 64) * 64;
+    hipLaunchKernelGGL((k_ring_whole<R, M>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out, g.Lx,
+                       g.ps, K, to_coin<R>(C));
+}
+
+hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
+                             hipStream_t s) {
+    const int m = ring_whole_m(prec, g.Lx);
+    if (m == 0) return hipErrorInvalidValue;
+    if (prec == C128) {
+        switch (m) {
+        case 1: ring_whole_t<double, 1>(in, out, g, C, K, s); break;
+        case 2: ring_whole_t<double, 2>(in, out, g, C, K, s); break;
+        default: ring_whole_t<double, 4>(in, out, g, C, K, s); break;
+        }
+    } else {
+        switch (m) {
+        case 1: ring_whole_t<float, 1>(in, out, g, C, K, s); break;
+        case 2: ring_whole_t<float, 2>(in, out, g, C, K, s); break;
+        case 4: ring_whole_t<float, 4>(in, out, g, C, K, s); break;
+        default: ring_whole_t<float, 8>(in, out, g, C, K, s); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int M, int K>
+static void ring_tiles_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s) {
+    constexpr int TW = 64 * M - 2 * K;
+    const int waves = (b.wx + TW - 1) / TW;
+    const int blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_ring_tiles<R, M, K>), dim3(blocks), dim3(256), 0, s, (const cv<R> *)in, (cv<R> *)out,
+                       g.Lx, g.ps, b, to_coin<R>(C));
+}
+
+hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
+                             int K, hipStream_t s) {
+    if (b.wx <= 0) return hipSuccess;
+    // M = 8 sites per lane: tiles of 512 sites; requires N >= 512
+    if (g.Lx < 512) return hipErrorInvalidValue;
+    if (prec == C128) {
+        switch (K) {
+        case 4: ring_tiles_t<double, 8, 4>(in, out, g, b, C, s); break;
+        case 8: ring_tiles_t<double, 8, 8>(in, out, g, b, C, s); break;
+        case 16: ring_tiles_t<double, 8, 16>(in, out, g, b, C, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (K) {
+        case 4: ring_tiles_t<float, 8, 4>(in, out, g, b, C, s); break;
+        case 8: ring_tiles_t<float, 8, 8>(in, out, g, b, C, s); break;
+        case 16: ring_tiles_t<float, 8, 16>(in, out, g, b, C, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int K, int M, int TABLE, int COIN>
+static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s) {
+    constexpr int TW = 64 * M - 2 * K;
+    const int nstrips = (b.wx + TW - 1) / TW;
+    // rows per segment: enough waves to fill the chip (~2 per SIMD), but
+    // segments no shorter than 4K rows (the 2K-row re-read stays <= 50%)
+    const long target_waves = 2048;
+    long segs = (target_waves + nstrips - 1) / nstrips;
+    int seg_rows = (int)((b.wy + segs - 1) / segs);
+    if (seg_rows < 4 * K) seg_rows = 4 * K;
+    const int nseg = (b.wy + seg_rows - 1) / seg_rows;
+    const long waves = (long)nstrips * nseg;
+    const long blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C));
+}
+
+template <typename R, int K, int M, int TABLE>
+static void stream_coin(int coin_impl, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
+                        hipStream_t s) {
+    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4>(in, out, g, b, C, s);
+    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4>(in, out, g, b, C, s);
+    else stream_t<R, K, M, TABLE, COIN_DENSE>(in, out, g, b, C, s);
+}
+
+template <typename R, int K, int M>
+static bool stream_table(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                         const CoinF64 &C, hipStream_t s) {
+    switch (table) {
+    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR>(coin_impl, in, out, g, b, C, s); return true;
+    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8>(coin_impl, in, out, g, b, C, s); return true;
+    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG>(coin_impl, in, out, g, b, C, s); return true;
+    default: return false;
+    }
+}
+
+bool stream2d_supported(int prec, int table, int K) {
+    if (table == TABLE_OTHER) return false;
+    if (prec == C128) return K == 4 || K == 8;
+    return K == 4 || K == 8 || K == 16;
+}
+
+hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
+                           const Box &b, const CoinF64 &C, int K, hipStream_t s) {
+    if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
+    if (!stream2d_supported(prec, table, K)) return hipErrorInvalidValue;
+    // a strip must not meet itself across the periodic x boundary
+    bool ok = false;
+    if (prec == C128) {
+        if (g.Lx < 64) return hipErrorInvalidValue;
+        if (K == 4) ok = stream_table<double, 4, 1>(table, coin_impl, in, out, g, b, C, s);
+        else ok = stream_table<double, 8, 1>(table, coin_impl, in, out, g, b, C, s);
+    } else {
+        if (g.Lx < 64) return hipErrorInvalidValue;
+        if (K == 4) ok = stream_table<float, 4, 1>(table, coin_impl, in, out, g, b, C, s);
+        else if (K == 8) ok = stream_table<float, 8, 1>(table, coin_impl, in, out, g, b, C, s);
+        else ok = stream_table<float, 16, 1>(table, coin_impl, in, out, g, b, C, s);
+    }
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_prob_norm(int prec, const void *state, const Geom &g, const Box &b, double *P, Scratch *scr,
+                            hipStream_t s) {
+    dim3 grid;
+    red_grid(b.wx, b.wy, grid);
+    const int nparts = grid.x * grid.y;
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_prob<double, 2>), grid, dim3(256), 0, s, (const double2 *)state, g, b, P, scr->partial);
+        else
+            hipLaunchKernelGGL((k_prob<float, 2>), grid, dim3(256), 0, s, (const float2 *)state, g, b, P, scr->partial);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_prob<double, 4>), grid, dim3(256), 0, s, (const double2 *)state, g, b, P, scr->partial);
+        else
+            hipLaunchKernelGGL((k_prob<float, 4>), grid, dim3(256), 0, s, (const float2 *)state, g, b, P, scr->partial);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const double *)scr->partial, nparts, &scr->norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(int prec, const void *state, const Geom &g, const Box &b, Scratch *scr, hipStream_t s) {
+    return launch_prob_norm(prec, state, g, b, nullptr, scr, s);
+}
+
+hipError_t launch_renorm(int prec, void *state, const Geom &g, const Box &b, double tol, Scratch *scr,
+                         hipStream_t s) {
+    dim3 grid;
+    red_grid(b.wx, b.wy, grid);
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_renorm<double, 2>), grid, dim3(256), 0, s, (double2 *)state, g, b, tol, scr);
+        else
+            hipLaunchKernelGGL((k_renorm<float, 2>), grid, dim3(256), 0, s, (float2 *)state, g, b, tol, scr);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_renorm<double, 4>), grid, dim3(256), 0, s, (double2 *)state, g, b, tol, scr);
+        else
+            hipLaunchKernelGGL((k_renorm<float, 4>), grid, dim3(256), 0, s, (float2 *)state, g, b, tol, scr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state(int prec, const void *state, const Geom &g, double *out, hipStream_t s) {
+    dim3 grid;
+    red_grid(g.Lx, g.Ly, grid);
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_get_state<double, 2>), grid, dim3(256), 0, s, (const double2 *)state, g, (double2 *)out);
+        else
+            hipLaunchKernelGGL((k_get_state<float, 2>), grid, dim3(256), 0, s, (const float2 *)state, g, (double2 *)out);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_get_state<double, 4>), grid, dim3(256), 0, s, (const double2 *)state, g, (double2 *)out);
+        else
+            hipLaunchKernelGGL((k_get_state<float, 4>), grid, dim3(256), 0, s, (const float2 *)state, g, (double2 *)out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(int prec, void *state, const Geom &g, const double *in, Scratch *scr, hipStream_t s) {
+    dim3 grid;
+    red_grid(g.Lx, g.Ly, grid);
+    const int nparts = grid.x * grid.y;
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_set_state<double, 2>), grid, dim3(256), 0, s, (double2 *)state, g, (const double2 *)in, scr->partial);
+        else
+            hipLaunchKernelGGL((k_set_state<float, 2>), grid, dim3(256), 0, s, (float2 *)state, g, (const double2 *)in, scr->partial);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_set_state<double, 4>), grid, dim3(256), 0, s, (double2 *)state, g, (const double2 *)in, scr->partial);
+        else
+            hipLaunchKernelGGL((k_set_state<float, 4>), grid, dim3(256), 0, s, (float2 *)state, g, (const double2 *)in, scr->partial);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const double *)scr->partial, nparts, &scr->norm);
+    return hipGetLastError();
+}
+
+}  // namespace qw

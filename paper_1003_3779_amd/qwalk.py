@@ -1,0 +1,266 @@
+"""ctypes binding of libqwalk.so (C ABI in include/qwalk.h).
+
+Argument marshalling only: every step of the walk runs in the library's HIP
+kernels.  Names follow the C entry points.  Device buffers may be given as
+torch tensors (their ``data_ptr()`` is passed) and streams as
+``torch.cuda.Stream`` objects (their ``cuda_stream`` handle is passed); torch
+is plumbing here, never compute.
+
+There is no fallback: if ``libqwalk.so`` is missing or cannot be loaded, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+QW_OK, QW_EINVAL, QW_ENOMEM, QW_EHIP, QW_ERANGE, QW_ENOTNORM = 0, -1, -2, -3, -4, -5
+QW_C128, QW_C64 = 0, 1
+HADAMARD, SU2, GROVER, HADAMARD2, FOURIER, DENSE = range(6)
+
+_STATUS_NAMES = {0: "QW_OK", -1: "QW_EINVAL", -2: "QW_ENOMEM", -3: "QW_EHIP", -4: "QW_ERANGE", -5: "QW_ENOTNORM"}
+
+# every symbol the header declares (checked by the tests)
+ABI_SYMBOLS = (
+    "walk_create", "walk_create_ext", "walk_state_bytes", "walk_step", "walk_step_inverse",
+    "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
+    "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
+)
+
+
+class QWError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("d", ctypes.c_int32), ("extent", ctypes.c_int64 * 2),
+                ("disp", (ctypes.c_int32 * 2) * 4)]
+
+
+class Coin(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("theta", ctypes.c_double), ("phi", ctypes.c_double),
+                ("chi", ctypes.c_double), ("dense", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("block_depth", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("renorm_checks", ctypes.c_int64), ("renorms", ctypes.c_int64),
+                ("last_norm", ctypes.c_double), ("launches", ctypes.c_int64), ("updates", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Open libqwalk.so (built in-tree by ``build.build_library``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libqwalk.so is not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "walk_create": [P, P, P, P, I32, P, P],
+        "walk_create_ext": [P, P, P, P, I32, P, P, P, P],
+        "walk_state_bytes": [P, I32, P],
+        "walk_step": [P, I64],
+        "walk_step_inverse": [P, I64],
+        "walk_probabilities": [P, P, I32],
+        "walk_norm": [P, P],
+        "walk_get_state": [P, P, I32],
+        "walk_set_state": [P, P, I32],
+        "walk_set_options": [P, P],
+        "walk_get_options": [P, P],
+        "walk_time": [P, P],
+        "walk_stats": [P, P],
+        "walk_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.walk_last_error.argtypes = []
+    lib.walk_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != QW_OK:
+        msg = load().walk_last_error().decode(errors="replace")
+        raise QWError(rc, msg)
+
+
+def _ptr_of(buf):
+    """Device pointer of a torch tensor, or an int address."""
+    if buf is None:
+        return None
+    if hasattr(buf, "data_ptr"):
+        return ctypes.c_void_p(buf.data_ptr())
+    return ctypes.c_void_p(int(buf))
+
+
+def _stream_of(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def make_lattice(extent, disp) -> Lattice:
+    disp = [tuple(int(v) for v in e) for e in disp]
+    d = len(disp)
+    lat = Lattice()
+    lat.dim = 1 if d == 2 else 2
+    lat.d = d
+    lat.extent[0] = int(extent[0])
+    lat.extent[1] = int(extent[1]) if len(extent) > 1 else 1
+    for c, (dx, dy) in enumerate(disp):
+        lat.disp[c][0] = dx
+        lat.disp[c][1] = dy
+    return lat
+
+
+class Walk:
+    """One walk: ``walk_create`` ... ``walk_destroy`` on a handle."""
+
+    def __init__(self, extent, disp, coin_kind: int, psi0, x0, prec: int = QW_C128,
+                 theta: float = 0.0, phi: float = 0.0, chi: float = 0.0, dense=None,
+                 stream=None, state_buffers=None, dim: int | None = None):
+        lib = load()
+        self._lib = lib
+        self.lattice = make_lattice(extent, disp)
+        if dim is not None:
+            self.lattice.dim = dim
+        self.d = self.lattice.d
+        self.V = int(self.lattice.extent[0]) * (int(self.lattice.extent[1]) if self.lattice.dim == 2 else 1)
+        self.Lx = int(self.lattice.extent[0])
+        self.Ly = int(self.lattice.extent[1]) if self.lattice.dim == 2 else 1
+        self.prec = prec
+        self._dense = None
+        coin = Coin()
+        coin.kind = coin_kind
+        coin.theta, coin.phi, coin.chi = theta, phi, chi
+        if dense is not None:
+            dn = np.ascontiguousarray(np.asarray(dense, dtype=np.complex128))
+            self._dense = dn
+            coin.dense = dn.ctypes.data
+        p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+        x0a = (ctypes.c_int64 * 2)(int(x0[0]), int(x0[1]) if len(x0) > 1 else 0)
+        h = ctypes.c_void_p()
+        self._keep = state_buffers
+        if state_buffers is None:
+            rc = lib.walk_create(ctypes.byref(self.lattice), ctypes.byref(coin), p0.ctypes.data, x0a, prec,
+                                 _stream_of(stream), ctypes.byref(h))
+        else:
+            a, b = state_buffers
+            rc = lib.walk_create_ext(ctypes.byref(self.lattice), ctypes.byref(coin), p0.ctypes.data, x0a, prec,
+                                     _stream_of(stream), _ptr_of(a), _ptr_of(b), ctypes.byref(h))
+        _check(rc)
+        self.h = h
+
+    # -- ABI calls --
+    def step(self, T: int):
+        _check(self._lib.walk_step(self.h, int(T)))
+
+    def step_inverse(self, T: int):
+        _check(self._lib.walk_step_inverse(self.h, int(T)))
+
+    def probabilities(self, out=None) -> np.ndarray | None:
+        """P(x) as a (Ly, Lx) float64 host array, or into a device tensor ``out``."""
+        if out is not None:
+            _check(self._lib.walk_probabilities(self.h, _ptr_of(out), 1))
+            return None
+        P = np.empty((self.Ly, self.Lx), dtype=np.float64)
+        _check(self._lib.walk_probabilities(self.h, P.ctypes.data, 0))
+        return P
+
+    def norm(self) -> float:
+        v = ctypes.c_double()
+        _check(self._lib.walk_norm(self.h, ctypes.byref(v)))
+        return v.value
+
+    def get_state(self, out=None) -> np.ndarray | None:
+        """psi as a (d, Ly, Lx) complex128 host array (or into a device tensor)."""
+        if out is not None:
+            _check(self._lib.walk_get_state(self.h, _ptr_of(out), 1))
+            return None
+        s = np.empty((self.d, self.Ly, self.Lx), dtype=np.complex128)
+        _check(self._lib.walk_get_state(self.h, s.ctypes.data, 0))
+        return s
+
+    def set_state(self, psi):
+        """psi: (d, Ly, Lx) complex128 host array, or a device tensor of the same bytes."""
+        if hasattr(psi, "data_ptr"):
+            _check(self._lib.walk_set_state(self.h, _ptr_of(psi), 1))
+            return
+        s = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+        if s.size != self.d * self.V:
+            raise ValueError("state has the wrong size")
+        _check(self._lib.walk_set_state(self.h, s.ctypes.data, 0))
+
+    def set_options(self, block_depth: int | None = None, window: int | None = None,
+                    renorm_every: int | None = None, renorm_tol: float | None = None):
+        o = self.get_options()
+        if block_depth is not None:
+            o.block_depth = block_depth
+        if window is not None:
+            o.window = window
+        if renorm_every is not None:
+            o.renorm_every = renorm_every
+        if renorm_tol is not None:
+            o.renorm_tol = renorm_tol
+        _check(self._lib.walk_set_options(self.h, ctypes.byref(o)))
+
+    def get_options(self) -> Options:
+        o = Options()
+        _check(self._lib.walk_get_options(self.h, ctypes.byref(o)))
+        return o
+
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        _check(self._lib.walk_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(self._lib.walk_stats(self.h, ctypes.byref(s)))
+        return s
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            rc = self._lib.walk_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def state_bytes(extent, disp, prec: int) -> int:
+    lat = make_lattice(extent, disp)
+    n = ctypes.c_size_t()
+    _check(load().walk_state_bytes(ctypes.byref(lat), prec, ctypes.byref(n)))
+    return n.value

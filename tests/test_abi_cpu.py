@@ -1,0 +1,153 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device.
+
+No call here reaches a HIP runtime function (validation fails first), so these
+run without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1003_3779_amd import build, inputs, qwalk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qwalk.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(build.LIB_PATH):
+        build.build_library()
+    return qwalk.load()
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(walk_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_lists_the_binding_symbols():
+    assert header_functions() == sorted(qwalk.ABI_SYMBOLS)
+
+
+def test_library_exports_every_header_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_no_oracle_symbols_in_library(lib):
+    for name in ("orc_evolve", "orc_coin", "orc_prob"):
+        with pytest.raises(AttributeError):
+            getattr(lib, name)
+
+
+def _lat(extent, disp, dim=None):
+    lat = qwalk.make_lattice(extent, disp)
+    if dim is not None:
+        lat.dim = dim
+    return lat
+
+
+def _create(lib, lat, kind=qwalk.HADAMARD, psi0=None, dense=None, prec=qwalk.QW_C128, theta=0.0):
+    coin = qwalk.Coin()
+    coin.kind = kind
+    coin.theta = theta
+    keep = None
+    if dense is not None:
+        keep = np.ascontiguousarray(dense, dtype=np.complex128)
+        coin.dense = keep.ctypes.data
+    if psi0 is None:
+        psi0 = inputs.PSI0_LR if lat is None or lat.d == 2 else inputs.PSI0_GROVER_LOC
+    p0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+    x0 = (ctypes.c_int64 * 2)(0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.walk_create(ctypes.byref(lat) if lat is not None else None, ctypes.byref(coin), p0.ctypes.data, x0,
+                         prec, None, ctypes.byref(h))
+    return rc, lib.walk_last_error().decode()
+
+
+def test_null_lattice(lib):
+    rc, msg = _create(lib, None)
+    assert rc == qwalk.QW_EINVAL and "lattice" in msg
+
+
+def test_bad_dimension_and_coin_dim(lib):
+    lat = _lat((16,), inputs.RING)
+    lat.dim = 3
+    assert _create(lib, lat)[0] == qwalk.QW_EINVAL
+    lat = _lat((16, 16), inputs.PAIR)
+    lat.d = 2
+    assert _create(lib, lat)[0] == qwalk.QW_EINVAL
+
+
+def test_bad_displacement(lib):
+    lat = _lat((16, 16), inputs.PAIR)
+    lat.disp[2][1] = 2
+    rc, msg = _create(lib, lat, kind=qwalk.GROVER)
+    assert rc == qwalk.QW_EINVAL and "displacement" in msg
+    lat = _lat((16,), ((1, 1), (-1, 0)))
+    assert _create(lib, lat)[0] == qwalk.QW_EINVAL
+
+
+def test_too_large(lib):
+    lat = _lat((1 << 16, 1 << 16), inputs.PAIR)
+    rc, msg = _create(lib, lat, kind=qwalk.GROVER)
+    assert rc == qwalk.QW_ERANGE
+
+
+def test_non_unitary_coin(lib):
+    lat = _lat((16,), inputs.RING)
+    bad = np.array([[1.0, 0.1], [0.0, 1.0]], dtype=np.complex128)
+    rc, msg = _create(lib, lat, kind=qwalk.DENSE, dense=bad)
+    assert rc == qwalk.QW_EINVAL and "unitary" in msg
+    # a unitary matrix off by 1e-9 is rejected too (tolerance 1e-12)
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2) * (1 + 1e-9)
+    assert _create(lib, lat, kind=qwalk.DENSE, dense=H)[0] == qwalk.QW_EINVAL
+
+
+def test_wrong_coin_for_dimension(lib):
+    lat = _lat((16, 16), inputs.PAIR)
+    assert _create(lib, lat, kind=qwalk.HADAMARD)[0] == qwalk.QW_EINVAL
+    lat = _lat((16,), inputs.RING)
+    assert _create(lib, lat, kind=qwalk.HADAMARD2)[0] == qwalk.QW_EINVAL
+    assert _create(lib, lat, kind=99)[0] == qwalk.QW_EINVAL
+
+
+def test_unnormalised_start(lib):
+    lat = _lat((16,), inputs.RING)
+    rc, msg = _create(lib, lat, psi0=np.array([1.0, 1e-6]))
+    assert rc == qwalk.QW_ENOTNORM
+
+
+def test_null_handles(lib):
+    assert lib.walk_step(None, 1) == qwalk.QW_EINVAL
+    assert lib.walk_norm(None, None) == qwalk.QW_EINVAL
+    assert lib.walk_destroy(None) == qwalk.QW_OK
+    assert lib.walk_create(None, None, None, None, 0, None, None) == qwalk.QW_EINVAL
+
+
+def test_state_bytes(lib):
+    n = ctypes.c_size_t()
+    lat = _lat((4096, 4096), inputs.PAIR)
+    assert lib.walk_state_bytes(ctypes.byref(lat), qwalk.QW_C128, ctypes.byref(n)) == 0
+    assert n.value == 4096 * 4096 * 4 * 16
+    assert lib.walk_state_bytes(ctypes.byref(lat), qwalk.QW_C64, ctypes.byref(n)) == 0
+    assert n.value == 4096 * 4096 * 4 * 8
+    assert lib.walk_state_bytes(ctypes.byref(lat), 7, ctypes.byref(n)) == qwalk.QW_EINVAL
+
+
+def test_ext_buffers_checked(lib):
+    lat = _lat((16,), inputs.RING)
+    coin = qwalk.Coin()
+    coin.kind = qwalk.HADAMARD
+    p0 = np.ascontiguousarray(inputs.PSI0_LR)
+    x0 = (ctypes.c_int64 * 2)(0, 0)
+    h = ctypes.c_void_p()
+    assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None, None, None,
+                               ctypes.byref(h)) == qwalk.QW_EINVAL
+    assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None,
+                               ctypes.c_void_p(4096 + 8), ctypes.c_void_p(8192), ctypes.byref(h)) == qwalk.QW_EINVAL
