@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the coined quantum walk on one MI355X.
+
+A step is one whole walk of the benchmark workload through the C ABI:
+walk_reset (the start state |x0> (x) psi0, both buffers cleared), walk_step(T)
+(fused coin+shift kernels, temporal blocking, light-cone window, the
+renormalisation policy of the precision), walk_probabilities into a device
+buffer and walk_norm (fp64 reductions).  Inputs live in HBM for the whole
+timed region.
+
+Workload (default): 2D Grover walk on the 4096 x 4096 torus, pair-ordered
+displacements (+x, -x, +y, -y), start (|0> - |1> - |2> + |3>)/2 at the centre,
+T = 2048 steps, complex128.
+
+Output: one JSON line (metric, value, roofline of the dominant kernel measured
+with HIP events inside the timed region, and the CPU oracle timed on a bounded
+sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+METRIC = "site·coin updates/s & HBM GB/s"
+UNIT = "site·coin updates/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grover2d", choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d"])
+    ap.add_argument("--prec", default=None, choices=["c128", "c64"])
+    ap.add_argument("--depth", type=int, default=0, help="steps per launch (0 = library default)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=640)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="instead of the walk: time a plain device-to-device copy of BYTES bytes "
+                         "(reference for HBM counters and bandwidth)")
+    return ap.parse_args()
+
+
+def copy_reference(nbytes: int):
+    """A plain copy kernel of known size: torch's elementwise copy of nbytes."""
+    import torch
+    n = nbytes // 16
+    a = torch.ones(n, 2, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes": n * 16, "ms": ms, "GBps_read_plus_write": 2 * n * 16 / (ms * 1e-3) / 1e9}),
+          flush=True)
+
+
+def traffic_from_profile(kernel_sha: str):
+    """Measured HBM bytes per launch of the dominant kernel (rocprofv3 PMC),
+    if the committed summary was taken on this exact kernel source."""
+    path = os.path.join(ROOT, "profiles", "stream2d_grover4096_c128_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", "qw_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1003_3779_amd import inputs, qwalk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_ref:
+        copy_reference(args.copy_ref)
+        return
+    cfg = inputs.config(args.workload)
+    prec_name = args.prec or cfg["prec"]
+    prec = qwalk.QW_C128 if prec_name == "c128" else qwalk.QW_C64
+    ext, disp, T, x0, psi0 = cfg["extent"], cfg["disp"], cfg["T"], cfg["x0"], cfg["psi0"]
+    if cfg["dim"] == 1:
+        ext = (ext[0],)
+    V = ext[0] * (ext[1] if len(ext) > 1 else 1)
+    d = len(disp)
+
+    w = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=prec)
+    if args.depth:
+        w.set_options(block_depth=args.depth)
+    P = torch.empty(V, dtype=torch.float64, device="cuda")
+
+    def one_walk():
+        w.reset(psi0, x0)
+        w.step(T)
+        w.probabilities(out=P)
+        return w.norm()                      # synchronises the stream
+
+    print(f"# bench: workload={args.workload} prec={prec_name} T={T} V={V} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        one_walk()
+    w.set_options(profile=1)
+    w.profile(reset=True)
+    u0 = w.stats().updates
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norms = []
+    for _ in range(args.steps):
+        norms.append(one_walk())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    u1 = w.stats().updates
+    prof = w.profile(reset=True)
+    w.set_options(profile=0)
+    elapsed = t1 - t0
+    updates_per_walk = (u1 - u0) / args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = updates_per_walk * args.steps / elapsed
+    esz = 16 if prec == qwalk.QW_C128 else 8
+    P_host = P.view(ext[1] if len(ext) > 1 else 1, ext[0]).cpu().numpy()
+    origin_p = float(P_host[x0[1] if len(x0) > 1 else 0, x0[0]])
+
+    # dominant kernel of the timed region
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    pk = prof[dom]
+    launches = max(pk["launches"], 1)
+    bytes_per_launch = (pk["bytes_read"] + pk["bytes_written"]) / launches
+    avg_ms = pk["ms"] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    sha = kernel_source_sha()
+    traffic = traffic_from_profile(sha) if (dom == "stream2d" and args.workload == "grover2d"
+                                            and prec == qwalk.QW_C128 and not args.depth) else None
+    roofline = {
+        "bound": "hbm", "kernel": dom,
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": traffic,
+        "launches": pk["launches"], "avg_launch_ms": round(avg_ms, 5),
+        "alg_bytes_per_launch": round(bytes_per_launch),
+        "kernel_share_of_step": round(pk["ms"] / (elapsed * 1e3), 4),
+    }
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == qwalk.QW_C128 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {'x'.join(str(e) for e in ext)} "
+                               f"{'ring' if cfg['dim'] == 1 else 'torus'}, T={T}, {prec_name}",
+                   "lattice": list(ext), "T": T, "coin_dim": d, "precision": prec_name,
+                   "block_depth": args.depth or "library default", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "updates_per_walk": updates_per_walk,
+        "dense_equiv_updates_per_s": V * d * T * args.steps / elapsed,
+        "hbm_effective_GBps": value * 2 * esz / 1e9,
+        "norm_error": max(abs(n - 1.0) for n in norms),
+        "origin_probability": origin_p,
+    }
+
+    if not args.no_extras and args.workload.startswith("grover2d"):
+        extras = {}
+        # unblocked kernel, for the HBM roofline of one step per launch
+        w.set_options(block_depth=1, profile=1)
+        w.profile(reset=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        one_walk()
+        tb = time.perf_counter()
+        p1 = w.profile(reset=True)["step"]
+        a1 = (p1["bytes_read"] + p1["bytes_written"]) / (p1["ms"] * 1e-3) / 1e9
+        extras["one_step_kernel"] = {"ms_per_walk": round(1e3 * (tb - ta), 3), "achieved_GBps": round(a1, 1),
+                                     "frac": round(a1 / HBM_PEAK_GBPS, 4), "launches": p1["launches"]}
+        w.set_options(block_depth=args.depth, profile=0)
+        # the same walk in complex64 (fp64 reductions, renormalisation every 64 steps)
+        other = qwalk.QW_C64 if prec == qwalk.QW_C128 else qwalk.QW_C128
+        w2 = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=other)
+        w2.reset(psi0, x0)
+        w2.step(T)
+        w2.norm()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        n2 = []
+        for _ in range(3):
+            w2.reset(psi0, x0)
+            w2.step(T)
+            w2.probabilities(out=P)
+            n2.append(w2.norm())
+        tb = time.perf_counter()
+        st2 = w2.stats()
+        P2 = P.view(ext[1], ext[0]).cpu().numpy()
+        extras["c64" if other == qwalk.QW_C64 else "c128"] = {
+            "ms_per_walk": round(1e3 * (tb - ta) / 3, 3),
+            "updates_per_s": updates_per_walk * 3 / (tb - ta),
+            "norm_error": max(abs(n - 1.0) for n in n2),
+            "renorms_applied": st2.renorms,
+            "max_abs_dP_vs_c128_run": float(np.max(np.abs(P2 - P_host))) if other == qwalk.QW_C64 else None,
+        }
+        w2.destroy()
+        out["extras"] = extras
+
+    if not args.no_cpu_baseline and cfg["dim"] == 2:
+        import oracle
+        Ts = args.cpu_sample_steps
+        Lx, Ly = ext
+        okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2}[cfg["coin"]]
+        C = oracle.coin(okind, 4)
+        psi_init = oracle.initial_state(Lx, Ly, 4, x0, psi0)
+        tc0 = time.perf_counter()
+        psi_o = oracle.evolve(psi_init, disp, C, Ts, windowed=True, x0=x0, t0=0)
+        tc1 = time.perf_counter()
+        del psi_init
+        # the oracle's window at step s (s = 1..Ts) is the box of radius s about x0
+        upd = sum(min(2 * r + 1, Lx) * min(2 * r + 1, Ly) for r in range(1, Ts + 1)) * 4
+        Po = oracle.prob(psi_o)
+        del psi_o
+        # the GPU on the same sample, in both precisions, against the oracle
+        errs = {}
+        for pn, pc in (("c128", qwalk.QW_C128), ("c64", qwalk.QW_C64)):
+            wg = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=pc)
+            wg.step(Ts)
+            Pg = wg.probabilities()
+            wg.destroy()
+            errs[pn] = float(np.max(np.abs(Pg - Po)))
+        out["cpu_baseline"] = {
+            "value": upd / (tc1 - tc0), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"light-cone windowed oracle (plain C, fp64, 1 thread), same torus and start, "
+                      f"first {Ts} of {T} steps ({upd:.3e} site*coin updates, {tc1 - tc0:.1f} s)",
+        }
+        out["max_abs_dP_vs_oracle"] = {"T": Ts, **errs}
+
+    w.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

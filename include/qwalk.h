@@ -92,7 +92,7 @@ typedef struct {
 
 /* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
  * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
- * renorm_tol 1e-7. */
+ * renorm_tol 1e-7, profile 0. */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
                               or 2, 4, 8, 16 (temporal blocking) */
@@ -101,7 +101,27 @@ typedef struct {
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
                               rescale psi by 1/sqrt(n) when |n - 1| > renorm_tol */
     double renorm_tol;
+    int32_t profile;       /* 1: bracket every step-kernel launch with HIP events on the
+                              walk's stream (read back by walk_profile) */
+    int32_t reserved;
 } qw_options;
+
+/* Step kernels, as reported by walk_profile. */
+enum {
+    QW_KERNEL_STEP = 0,        /* one step per launch, one thread per site */
+    QW_KERNEL_RING_WHOLE = 1,  /* a whole ring in one workgroup, many steps per launch */
+    QW_KERNEL_RING_TILES = 2,  /* ring in wave-sized register tiles, K steps per launch */
+    QW_KERNEL_STREAM2D = 3,    /* torus, row-streaming register kernel, K steps per launch */
+    QW_KERNEL_KINDS = 4
+};
+
+typedef struct {
+    int64_t launches;
+    double ms;              /* sum of HIP-event durations of those launches */
+    double bytes_read;      /* HBM bytes the launches read by construction (state incl. halo) */
+    double bytes_written;   /* HBM bytes the launches wrote */
+    double updates;         /* site*coin updates of the walk those launches advanced */
+} qw_kernel_profile;
 
 typedef struct {
     int64_t t;                /* steps taken (forward minus inverse) */
@@ -130,6 +150,11 @@ int walk_create(const qw_lattice *lattice, const qw_coin *coin, const double *ps
 int walk_create_ext(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
                     const int64_t *x0, int32_t prec, void *stream, void *state_a,
                     void *state_b, qw_walk_t *out);
+
+/* Put the walk back to |x0> (x) psi0 at t = 0 without reallocating (same
+ * lattice, coin, precision and options).  psi0 and x0 as for walk_create;
+ * QW_ENOTNORM if psi0 is not normalised.  Asynchronous. */
+int walk_reset(qw_walk_t w, const double *psi0, const int64_t *x0);
 
 /* Bytes of one state buffer for this lattice and precision (d * V complex). */
 int walk_state_bytes(const qw_lattice *lattice, int32_t prec, size_t *bytes);
@@ -166,6 +191,11 @@ int walk_get_options(qw_walk_t w, qw_options *opt);
 int walk_time(qw_walk_t w, int64_t *t);
 /* Counters; synchronises the stream to read the device-side renorm counters. */
 int walk_stats(qw_walk_t w, qw_stats *out);
+
+/* Per-kernel timing of the launches made while qw_options.profile was 1:
+ * out receives QW_KERNEL_KINDS entries (indexed by the QW_KERNEL_* values).
+ * Synchronises the stream.  reset != 0 clears the accumulators afterwards. */
+int walk_profile(qw_walk_t w, qw_kernel_profile *out, int32_t reset);
 
 /* Release the handle and what it allocated (not caller buffers).  Waits for
  * the handle's pending work first.  NULL is accepted. */

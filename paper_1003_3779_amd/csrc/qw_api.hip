@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 using namespace qw;
 
@@ -199,6 +200,15 @@ struct qw_walk {
     qw_options opt;
     int64_t since_check = 0;
     int64_t checks = 0, launches = 0, updates = 0;
+    // profiling: event pairs pending read-back, a pool of spare events, totals per kernel kind
+    struct Pending {
+        hipEvent_t a, b;
+        int kind;
+        double bytes_read, bytes_written, updates;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    qw_kernel_profile prof[QW_KERNEL_KINDS];
 };
 
 namespace {
@@ -270,11 +280,52 @@ int default_depth(const qw_walk *w) {
     return 8;
 }
 
+hipEvent_t take_event(qw_walk *w) {
+    if (!w->spare.empty()) {
+        hipEvent_t e = w->spare.back();
+        w->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Opens a profiled launch: records the start event when profiling is on.
+struct Timed {
+    qw_walk *w;
+    hipEvent_t a = nullptr;
+    explicit Timed(qw_walk *w_) : w(w_) {
+        if (w->opt.profile) {
+            a = take_event(w);
+            if (a) (void)hipEventRecord(a, w->stream);
+        }
+    }
+    void done(int kind, const LaunchInfo &li, double updates) {
+        if (!a) return;
+        hipEvent_t b = take_event(w);
+        if (!b) {
+            w->spare.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, w->stream);
+        w->pending.push_back({a, b, kind, li.bytes_read, li.bytes_written, updates});
+        a = nullptr;
+    }
+};
+
 // one unblocked step
 int step1(qw_walk *w) {
     grow_forward(w, 1);
     const Box b = state_box(w);
-    QW_HIP(launch_step(w->prec, w->coin_impl, cur_buf(w), oth_buf(w), w->g, b, w->C, w->stream), "step kernel");
+    LaunchInfo li;
+    Timed tm(w);
+    QW_HIP(launch_step(w->prec, w->coin_impl, cur_buf(w), oth_buf(w), w->g, b, w->C, w->stream, &li),
+           "step kernel");
+    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d);
     w->cur ^= 1;
     w->launches++;
     w->updates += box_sites(b) * w->d;
@@ -289,11 +340,16 @@ int stepK(qw_walk *w, int K, bool ring) {
         upd += box_sites(state_box(w)) * w->d;
     }
     const Box b = state_box(w);
+    LaunchInfo li;
+    Timed tm(w);
     if (ring)
-        QW_HIP(launch_ring_tiles(w->prec, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream), "ring tile kernel");
+        QW_HIP(launch_ring_tiles(w->prec, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream, &li),
+               "ring tile kernel");
     else
-        QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream),
+        QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream,
+                               &li),
                "2D streaming kernel");
+    tm.done(ring ? QW_KERNEL_RING_TILES : QW_KERNEL_STREAM2D, li, (double)upd);
     w->cur ^= 1;
     w->launches++;
     w->updates += upd;
@@ -307,7 +363,10 @@ int run_forward(qw_walk *w, int64_t n) {
         // the whole ring in one workgroup: all n steps in one launch (every
         // site is computed; the light-cone box stays exact bookkeeping)
         grow_forward(w, n);
-        QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream), "ring kernel");
+        LaunchInfo li;
+        Timed tm(w);
+        QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li), "ring kernel");
+        tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n);
         w->cur ^= 1;
         w->launches++;
         w->updates += (int64_t)w->g.Lx * w->d * n;
@@ -342,6 +401,64 @@ int norm_check(qw_walk *w) {
     return QW_OK;
 }
 
+// origin x0 (reduced modulo the extents) and the support box of a_0:
+// a_0 is psi_0 placed at x0 - e_c
+void set_origin(qw_walk *w, const int64_t *x0) {
+    const int64_t L[2] = {w->g.Lx, w->g.Ly};
+    for (int ax = 0; ax < 2; ++ax) {
+        int64_t v = x0[ax] % L[ax];
+        w->x0[ax] = v < 0 ? v + L[ax] : v;
+        int mn = 0, mx = 0;
+        for (int c = 0; c < w->d; ++c) {
+            const int e = ax == 0 ? w->g.ex[c] : w->g.ey[c];
+            mn = std::min(mn, e);
+            mx = std::max(mx, e);
+        }
+        w->emin[ax] = mn;
+        w->emax[ax] = mx;
+        w->lo[ax] = -mx;
+        w->hi[ax] = -mn;
+        w->full[ax] = false;
+    }
+    if (w->dim == 1) {
+        w->x0[1] = 0;
+        w->lo[1] = w->hi[1] = 0;
+        w->full[1] = true;
+    }
+    for (int ax = 0; ax < 2; ++ax) normalise_axis(w, ax);
+}
+
+int check_psi0(const double *psi0, int d) {
+    if (!psi0) return fail(QW_EINVAL, "psi0 is NULL");
+    double nn = 0.0;
+    for (int c = 0; c < d; ++c) {
+        if (!isfinite(psi0[2 * c]) || !isfinite(psi0[2 * c + 1])) return fail(QW_EINVAL, "psi0 has a non-finite entry");
+        nn += psi0[2 * c] * psi0[2 * c] + psi0[2 * c + 1] * psi0[2 * c + 1];
+    }
+    if (!(fabs(nn - 1.0) <= 1e-12)) return fail(QW_ENOTNORM, "psi0 is not normalised (||psi0||^2 = %.17g)", nn);
+    return QW_OK;
+}
+
+// resolve the profiled launches recorded so far into the per-kernel totals
+int drain_profile(qw_walk *w) {
+    if (w->pending.empty()) return QW_OK;
+    QW_HIP(hipStreamSynchronize(w->stream), "stream synchronise");
+    for (auto &p : w->pending) {
+        float ms = 0.0f;
+        QW_HIP(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime");
+        qw_kernel_profile &k = w->prof[p.kind];
+        k.launches += 1;
+        k.ms += ms;
+        k.bytes_read += p.bytes_read;
+        k.bytes_written += p.bytes_written;
+        k.updates += p.updates;
+        w->spare.push_back(p.a);
+        w->spare.push_back(p.b);
+    }
+    w->pending.clear();
+    return QW_OK;
+}
+
 int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
                   void *stream, void *sa, void *sb, qw_walk_t *out) {
     if (!out) return fail(QW_EINVAL, "out handle pointer is NULL");
@@ -349,18 +466,13 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     int rc = validate_lattice(l);
     if (rc) return rc;
     if (!coin) return fail(QW_EINVAL, "coin is NULL");
-    if (!psi0) return fail(QW_EINVAL, "psi0 is NULL");
     if (!x0) return fail(QW_EINVAL, "x0 is NULL");
     if (prec != QW_C128 && prec != QW_C64) return fail(QW_EINVAL, "precision must be QW_C128 or QW_C64");
     CoinF64 C;
     rc = build_coin(coin, l->d, C);
     if (rc) return rc;
-    double nn = 0.0;
-    for (int c = 0; c < l->d; ++c) {
-        if (!isfinite(psi0[2 * c]) || !isfinite(psi0[2 * c + 1])) return fail(QW_EINVAL, "psi0 has a non-finite entry");
-        nn += psi0[2 * c] * psi0[2 * c] + psi0[2 * c + 1] * psi0[2 * c + 1];
-    }
-    if (!(fabs(nn - 1.0) <= 1e-12)) return fail(QW_ENOTNORM, "psi0 is not normalised (||psi0||^2 = %.17g)", nn);
+    rc = check_psi0(psi0, l->d);
+    if (rc) return rc;
 
     qw_walk *w = new (std::nothrow) qw_walk();
     if (!w) return fail(QW_ENOMEM, "host allocation failed");
@@ -387,29 +499,10 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     w->opt.window = 1;
     w->opt.renorm_every = prec == QW_C64 ? 64 : 0;
     w->opt.renorm_tol = 1e-7;
-    const int64_t L[2] = {w->g.Lx, w->g.Ly};
-    for (int ax = 0; ax < 2; ++ax) {
-        int64_t v = x0[ax] % L[ax];
-        w->x0[ax] = v < 0 ? v + L[ax] : v;
-        int mn = 0, mx = 0;
-        for (int c = 0; c < l->d; ++c) {
-            const int e = ax == 0 ? w->g.ex[c] : w->g.ey[c];
-            mn = std::min(mn, e);
-            mx = std::max(mx, e);
-        }
-        w->emin[ax] = mn;
-        w->emax[ax] = mx;
-        // a_0 is psi_0 at x0 - e_c
-        w->lo[ax] = -mx;
-        w->hi[ax] = -mn;
-        w->full[ax] = false;
-    }
-    if (l->dim == 1) {
-        w->x0[1] = 0;
-        w->lo[1] = w->hi[1] = 0;
-        w->full[1] = true;
-    }
-    for (int ax = 0; ax < 2; ++ax) normalise_axis(w, ax);
+    w->opt.profile = 0;
+    w->opt.reserved = 0;
+    for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
+    set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
 
     int dev = 0;
@@ -489,6 +582,35 @@ int walk_create_ext(const qw_lattice *l, const qw_coin *coin, const double *psi0
         return fail(QW_EINVAL, "state buffers must be 256-byte aligned");
     if (state_a == state_b) return fail(QW_EINVAL, "the two state buffers must differ");
     return create_common(l, coin, psi0, x0, prec, stream, state_a, state_b, out);
+}
+
+int walk_reset(qw_walk_t w, const double *psi0, const int64_t *x0) {
+    if (!w) return fail(QW_EINVAL, "walk handle is NULL");
+    if (!x0) return fail(QW_EINVAL, "x0 is NULL");
+    int rc = check_psi0(psi0, w->d);
+    if (rc) return rc;
+    DeviceGuard dg(w->device);
+    set_origin(w, x0);
+    w->cur = 0;
+    w->t = 0;
+    w->since_check = 0;
+    QW_HIP(launch_fill_zero(w->buf[0], w->state_bytes, w->stream), "fill kernel");
+    QW_HIP(launch_fill_zero(w->buf[1], w->state_bytes, w->stream), "fill kernel");
+    QW_HIP(launch_place(w->prec, w->buf[0], w->g, w->x0[0], w->x0[1], psi0, w->stream), "place kernel");
+    return QW_OK;
+}
+
+int walk_profile(qw_walk_t w, qw_kernel_profile *out, int32_t reset) {
+    if (!w) return fail(QW_EINVAL, "walk handle is NULL");
+    if (!out) return fail(QW_EINVAL, "output pointer is NULL");
+    DeviceGuard dg(w->device);
+    int rc = drain_profile(w);
+    if (rc) return rc;
+    for (int k = 0; k < QW_KERNEL_KINDS; ++k) {
+        out[k] = w->prof[k];
+        if (reset) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
+    }
+    return QW_OK;
 }
 
 int walk_step(qw_walk_t w, int64_t T) {
@@ -635,6 +757,7 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
     if (o->window != 0 && o->window != 1) return fail(QW_EINVAL, "window must be 0 or 1");
     if (o->renorm_every < 0) return fail(QW_EINVAL, "renorm_every must be >= 0");
     if (!(o->renorm_tol >= 0.0)) return fail(QW_EINVAL, "renorm_tol must be >= 0");
+    if (o->profile != 0 && o->profile != 1) return fail(QW_EINVAL, "profile must be 0 or 1");
     w->opt = *o;
     w->since_check = 0;
     return QW_OK;
@@ -678,6 +801,11 @@ int walk_destroy(qw_walk_t w) {
         for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
     (void)hipFree(w->scr);
     if (w->pbuf) (void)hipFree(w->pbuf);
+    for (auto &p : w->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : w->spare) (void)hipEventDestroy(e);
     delete w;
     if (e != hipSuccess) return hip_fail(e, "stream synchronise in walk_destroy");
     return QW_OK;

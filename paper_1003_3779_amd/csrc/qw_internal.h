@@ -42,27 +42,33 @@ struct Scratch {
     unsigned long long pad;
 };
 
+// HBM bytes a launch moves by construction (state reads incl. halo, writes)
+struct LaunchInfo {
+    double bytes_read = 0.0, bytes_written = 0.0;
+};
+
 // ---- launchers (qw_kernels.hip); all return a hipError_t ----
 hipError_t launch_fill_zero(void *buf, size_t bytes, hipStream_t s);
 hipError_t launch_place(int prec, void *state, const Geom &g, int64_t x0, int64_t y0,
                         const double *psi0, hipStream_t s);
 // one step of U over the output box (in -> out)
 hipError_t launch_step(int prec, int coin_impl, const void *in, void *out, const Geom &g,
-                       const Box &out_box, const CoinF64 &C, hipStream_t s);
+                       const Box &out_box, const CoinF64 &C, hipStream_t s, LaunchInfo *info);
 // one step of U^-1 over the output box; Cdag is C^dagger
 hipError_t launch_step_inverse(int prec, const void *in, void *out, const Geom &g,
                                const Box &out_box, const CoinF64 &Cdag, hipStream_t s);
 // K steps of a ring of N = g.Lx sites held whole by one workgroup
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
-                             const CoinF64 &C, int64_t K, hipStream_t s);
+                             const CoinF64 &C, int64_t K, hipStream_t s, LaunchInfo *info);
 int ring_whole_max_sites(int prec);
 // K steps of a ring, wave-sized register tiles over the output window box
 hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
-                             const Box &out_box, const CoinF64 &C, int K, hipStream_t s);
+                             const Box &out_box, const CoinF64 &C, int K, hipStream_t s,
+                             LaunchInfo *info);
 // K steps on a torus with the row-streaming register kernel
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out,
                            const Geom &g, const Box &out_box, const CoinF64 &C, int K,
-                           hipStream_t s);
+                           hipStream_t s, LaunchInfo *info);
 bool stream2d_supported(int prec, int table, int K);
 // P(x) (if P != nullptr) and the fp64 norm into scratch->norm.  psi_box: the box
 // outside which psi is zero.

@@ -670,8 +670,13 @@ static void step_t(const void *in, void *out, const Geom &g, const Box &b, const
 }
 
 hipError_t launch_step(int prec, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
-                       const CoinF64 &C, hipStream_t s) {
+                       const CoinF64 &C, hipStream_t s, LaunchInfo *info) {
     if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
+    if (info) {
+        const double bytes = (double)b.wx * b.wy * g.d * (prec == C128 ? 16.0 : 8.0);
+        info->bytes_read = bytes;
+        info->bytes_written = bytes;
+    }
     if (g.d == 2) {
         if (prec == C128) step_t<double, 2, COIN_DENSE>(in, out, g, b, C, s);
         else step_t<float, 2, COIN_DENSE>(in, out, g, b, C, s);
@@ -729,9 +734,14 @@ static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64
 }
 
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
-                             hipStream_t s) {
+                             hipStream_t s, LaunchInfo *info) {
     const int m = ring_whole_m(prec, g.Lx);
     if (m == 0) return hipErrorInvalidValue;
+    if (info) {
+        const double bytes = (double)g.Lx * 2 * (prec == C128 ? 16.0 : 8.0);
+        info->bytes_read = bytes;
+        info->bytes_written = bytes;
+    }
     if (prec == C128) {
         switch (m) {
         case 1: ring_whole_t<double, 1>(in, out, g, C, K, s); break;
@@ -750,31 +760,36 @@ hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
 }
 
 template <typename R, int M, int K>
-static void ring_tiles_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s) {
+static void ring_tiles_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s,
+                         LaunchInfo *info) {
     constexpr int TW = 64 * M - 2 * K;
     const int waves = (b.wx + TW - 1) / TW;
+    if (info) {
+        info->bytes_read = (double)waves * 64 * M * 2 * sizeof(cv<R>);
+        info->bytes_written = (double)b.wx * 2 * sizeof(cv<R>);
+    }
     const int blocks = (waves + 3) / 4;
     hipLaunchKernelGGL((k_ring_tiles<R, M, K>), dim3(blocks), dim3(256), 0, s, (const cv<R> *)in, (cv<R> *)out,
                        g.Lx, g.ps, b, to_coin<R>(C));
 }
 
 hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
-                             int K, hipStream_t s) {
+                             int K, hipStream_t s, LaunchInfo *info) {
     if (b.wx <= 0) return hipSuccess;
     // M = 8 sites per lane: tiles of 512 sites; requires N >= 512
     if (g.Lx < 512) return hipErrorInvalidValue;
     if (prec == C128) {
         switch (K) {
-        case 4: ring_tiles_t<double, 8, 4>(in, out, g, b, C, s); break;
-        case 8: ring_tiles_t<double, 8, 8>(in, out, g, b, C, s); break;
-        case 16: ring_tiles_t<double, 8, 16>(in, out, g, b, C, s); break;
+        case 4: ring_tiles_t<double, 8, 4>(in, out, g, b, C, s, info); break;
+        case 8: ring_tiles_t<double, 8, 8>(in, out, g, b, C, s, info); break;
+        case 16: ring_tiles_t<double, 8, 16>(in, out, g, b, C, s, info); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (K) {
-        case 4: ring_tiles_t<float, 8, 4>(in, out, g, b, C, s); break;
-        case 8: ring_tiles_t<float, 8, 8>(in, out, g, b, C, s); break;
-        case 16: ring_tiles_t<float, 8, 16>(in, out, g, b, C, s); break;
+        case 4: ring_tiles_t<float, 8, 4>(in, out, g, b, C, s, info); break;
+        case 8: ring_tiles_t<float, 8, 8>(in, out, g, b, C, s, info); break;
+        case 16: ring_tiles_t<float, 8, 16>(in, out, g, b, C, s, info); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -782,7 +797,8 @@ hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
 }
 
 template <typename R, int K, int M, int TABLE, int COIN>
-static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s) {
+static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s,
+                     LaunchInfo *info) {
     constexpr int TW = 64 * M - 2 * K;
     const int nstrips = (b.wx + TW - 1) / TW;
     // rows per segment: enough waves to fill the chip (~2 per SIMD), but
@@ -794,25 +810,30 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
     const int nseg = (b.wy + seg_rows - 1) / seg_rows;
     const long waves = (long)nstrips * nseg;
     const long blocks = (waves + 3) / 4;
+    if (info) {
+        // every strip loads 64*M columns of every row of its segments plus 2K halo rows per segment
+        info->bytes_read = (double)nstrips * 64 * M * ((double)b.wy + 2.0 * K * nseg) * 4 * sizeof(cv<R>);
+        info->bytes_written = (double)b.wx * b.wy * 4 * sizeof(cv<R>);
+    }
     hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN>), dim3((unsigned)blocks), dim3(256), 0, s,
                        (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C));
 }
 
 template <typename R, int K, int M, int TABLE>
 static void stream_coin(int coin_impl, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
-                        hipStream_t s) {
-    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4>(in, out, g, b, C, s);
-    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4>(in, out, g, b, C, s);
-    else stream_t<R, K, M, TABLE, COIN_DENSE>(in, out, g, b, C, s);
+                        hipStream_t s, LaunchInfo *info) {
+    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4>(in, out, g, b, C, s, info);
+    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4>(in, out, g, b, C, s, info);
+    else stream_t<R, K, M, TABLE, COIN_DENSE>(in, out, g, b, C, s, info);
 }
 
 template <typename R, int K, int M>
 static bool stream_table(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
-                         const CoinF64 &C, hipStream_t s) {
+                         const CoinF64 &C, hipStream_t s, LaunchInfo *info) {
     switch (table) {
-    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR>(coin_impl, in, out, g, b, C, s); return true;
-    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8>(coin_impl, in, out, g, b, C, s); return true;
-    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG>(coin_impl, in, out, g, b, C, s); return true;
+    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR>(coin_impl, in, out, g, b, C, s, info); return true;
+    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8>(coin_impl, in, out, g, b, C, s, info); return true;
+    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG>(coin_impl, in, out, g, b, C, s, info); return true;
     default: return false;
     }
 }
@@ -824,20 +845,20 @@ bool stream2d_supported(int prec, int table, int K) {
 }
 
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
-                           const Box &b, const CoinF64 &C, int K, hipStream_t s) {
+                           const Box &b, const CoinF64 &C, int K, hipStream_t s, LaunchInfo *info) {
     if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
     if (!stream2d_supported(prec, table, K)) return hipErrorInvalidValue;
     // a strip must not meet itself across the periodic x boundary
     bool ok = false;
     if (prec == C128) {
         if (g.Lx < 64) return hipErrorInvalidValue;
-        if (K == 4) ok = stream_table<double, 4, 1>(table, coin_impl, in, out, g, b, C, s);
-        else ok = stream_table<double, 8, 1>(table, coin_impl, in, out, g, b, C, s);
+        if (K == 4) ok = stream_table<double, 4, 1>(table, coin_impl, in, out, g, b, C, s, info);
+        else ok = stream_table<double, 8, 1>(table, coin_impl, in, out, g, b, C, s, info);
     } else {
         if (g.Lx < 64) return hipErrorInvalidValue;
-        if (K == 4) ok = stream_table<float, 4, 1>(table, coin_impl, in, out, g, b, C, s);
-        else if (K == 8) ok = stream_table<float, 8, 1>(table, coin_impl, in, out, g, b, C, s);
-        else ok = stream_table<float, 16, 1>(table, coin_impl, in, out, g, b, C, s);
+        if (K == 4) ok = stream_table<float, 4, 1>(table, coin_impl, in, out, g, b, C, s, info);
+        else if (K == 8) ok = stream_table<float, 8, 1>(table, coin_impl, in, out, g, b, C, s, info);
+        else ok = stream_table<float, 16, 1>(table, coin_impl, in, out, g, b, C, s, info);
     }
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();

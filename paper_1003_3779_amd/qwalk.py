@@ -29,7 +29,9 @@ ABI_SYMBOLS = (
     "walk_create", "walk_create_ext", "walk_state_bytes", "walk_step", "walk_step_inverse",
     "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
     "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
+    "walk_reset", "walk_profile",
 )
+KERNEL_NAMES = ("step", "ring_whole", "ring_tiles", "stream2d")
 
 
 class QWError(RuntimeError):
@@ -50,7 +52,13 @@ class Coin(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("block_depth", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double)]
+                ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes_read", ctypes.c_double),
+                ("bytes_written", ctypes.c_double), ("updates", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -86,6 +94,8 @@ def load():
         "walk_time": [P, P],
         "walk_stats": [P, P],
         "walk_destroy": [P],
+        "walk_reset": [P, P, P],
+        "walk_profile": [P, P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -212,9 +222,27 @@ class Walk:
             raise ValueError("state has the wrong size")
         _check(self._lib.walk_set_state(self.h, s.ctypes.data, 0))
 
+    def reset(self, psi0, x0):
+        p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+        x0a = (ctypes.c_int64 * 2)(int(x0[0]), int(x0[1]) if len(x0) > 1 else 0)
+        _check(self._lib.walk_reset(self.h, p0.ctypes.data, x0a))
+
+    def profile(self, reset: bool = False) -> dict:
+        """Per-kernel totals of the launches timed while the profile option was on."""
+        arr = (KernelProfile * len(KERNEL_NAMES))()
+        _check(self._lib.walk_profile(self.h, arr, int(bool(reset))))
+        out = {}
+        for name, k in zip(KERNEL_NAMES, arr):
+            out[name] = {"launches": k.launches, "ms": k.ms, "bytes_read": k.bytes_read,
+                         "bytes_written": k.bytes_written, "updates": k.updates}
+        return out
+
     def set_options(self, block_depth: int | None = None, window: int | None = None,
-                    renorm_every: int | None = None, renorm_tol: float | None = None):
+                    renorm_every: int | None = None, renorm_tol: float | None = None,
+                    profile: int | None = None):
         o = self.get_options()
+        if profile is not None:
+            o.profile = int(profile)
         if block_depth is not None:
             o.block_depth = block_depth
         if window is not None:
