@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--workload", default="grover2d", choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d"])
     ap.add_argument("--prec", default=None, choices=["c128", "c64"])
     ap.add_argument("--depth", type=int, default=0, help="steps per launch (0 = library default)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=640)
+    ap.add_argument("--cpu-sample-steps", type=int, default=900)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
