@@ -204,6 +204,70 @@ int walk_destroy(qw_walk_t w);
 /* Message of the latest failing call on this thread ("" if none). */
 const char *walk_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent ring walks in one persistent launch.
+ *
+ * Walk i runs on a ring of N[i] sites with the SU(2) coin of angles
+ * (theta, phi, chi) = angles[3i..3i+2], start coin state psi0[4i..4i+3]
+ * (complex (re, im) pairs in (R, L) order, normalised to 1e-12) at site x0[i]
+ * (x0 = NULL: N[i]/2), for T[i] steps of U (Sec. 2.1, Eq. 2; ring table
+ * e_0 = +1, e_1 = -1).  Each run leaves, per walk, the moments of P about the
+ * start site (sum P, sum P dx, sum P dx^2 with dx the signed ring offset in
+ * (-N/2, N/2]), optionally nbins symmetric bins of P (offsets -k*w..-(k-1)*w-1
+ * to bin h-k, (k-1)*w+1..k*w to bin h+k-1, the start site half to bins h-1
+ * and h; h = nbins/2, w = floor((N-1)/2 / h)) and optionally every full P(x).
+ * Walks run longest-first from an atomic queue; a run is one replay of a
+ * captured hipGraph (queue reset + the persistent kernel).  With stream NULL
+ * the batch uses a private stream and calls return only when done.
+ * ------------------------------------------------------------------------ */
+typedef struct qw_batch *qw_batch_t;
+
+typedef struct {
+    int32_t nbins;               /* bins per walk: 0 (none) or even and <= 1024 */
+    int32_t keep_probabilities;  /* 1: keep every walk's full P(x) for walk_batch_probabilities */
+    int32_t tiled_variant;       /* rings too long for one workgroup's registers: 0 = tuned
+                                    (cache) or default; 1..4 = force (tile sites, steps per
+                                    block) = (256, 8), (256, 16), (512, 8), (512, 16) */
+    int32_t no_graph;            /* 1: launch directly instead of replaying a hipGraph */
+} qw_batch_opts;
+
+typedef struct {
+    int64_t n;                 /* walks */
+    int32_t grid;              /* persistent workgroups */
+    int32_t graph;             /* 1 once a hipGraph has been captured */
+    int64_t whole_ring_walks;  /* walks held whole in one workgroup's registers */
+    double est_updates;        /* site*coin updates of one run (light cone; whole rings in full) */
+    double last_run_ms;        /* HIP-event time of the latest walk_batch_run */
+    int32_t bucket_cfg[3];     /* tiled variant (0..3) per size bucket N <= 1e4, <= 1e5, larger */
+    int32_t bucket_tile_sites[3];
+    int32_t bucket_depth[3];
+    int32_t reserved;
+} qw_batch_info;
+
+/* Validate and upload the walk table; allocate per-walk outputs and the slot
+ * buffers of the persistent workgroups.  N, T: n int64; angles: 3n doubles;
+ * psi0: 4n doubles; x0: n int64 or NULL; opts may be NULL (all zero). */
+int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const double *angles,
+                      const double *psi0, const int64_t *x0, int32_t prec,
+                      const qw_batch_opts *opts, void *stream, qw_batch_t *out);
+/* Run every walk of the batch (asynchronous on the batch's stream). */
+int walk_batch_run(qw_batch_t b);
+/* n x 3 doubles: sum P, sum P dx, sum P dx^2 per walk. */
+int walk_batch_moments(qw_batch_t b, double *out, int32_t out_on_device);
+/* n x nbins floats (the bins are summed in fp64, stored as fp32). */
+int walk_batch_binned(qw_batch_t b, float *out, int32_t out_on_device);
+/* sum_i N[i] doubles: walk i's P(x) at offset N[0] + ... + N[i-1]. */
+int walk_batch_probabilities(qw_batch_t b, double *out, int32_t out_on_device);
+int walk_batch_info(qw_batch_t b, qw_batch_info *out);
+/* Autotuner: per size bucket, time every tiled variant on `samples` walks of
+ * the bucket (spread over their work) and keep the fastest; save != 0 writes
+ * the choice to the tuning cache ($QWALK_TUNE_CACHE, else
+ * ~/.cache/qwalk_tune.txt), read by later walk_batch_create calls on the same
+ * device and precision.  Overwrites outputs until the next walk_batch_run. */
+int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save);
+int walk_batch_destroy(qw_batch_t b);
+const char *walk_batch_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

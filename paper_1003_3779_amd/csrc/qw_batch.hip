@@ -1,0 +1,915 @@
+// qw_batch.hip -- many independent ring walks (each with its own N, T, SU(2)
+// coin, start coin state and start site) in one persistent launch.
+//
+// Each workgroup (512 threads, 8 waves) pops walks from an atomic queue that
+// the host ordered longest-first (LPT) and runs each popped walk to the end:
+//  * a ring of N <= 512*M_max sites is held whole in registers (M sites per
+//    thread), neighbour values cross thread boundaries through LDS with one
+//    barrier per step -- no memory traffic inside the walk;
+//  * a longer ring lives in this workgroup's two slot buffers in HBM and is
+//    advanced K steps at a time in wave tiles of 64*MT sites over its light
+//    cone (the same register tile step as the single-walk ring kernel);
+//  * at the end P(x) = |a(x-1,0)|^2 + |a(x+1,1)|^2 (fp64) gives the walk's
+//    moments (sum P, sum P dx, sum P dx^2 about the start site), its symmetric
+//    bins and, optionally, the full distribution.
+// The walk's steps are the ring case of U = S (I (x) C) (Sec. 2.1, Eq. 2;
+// component 0 moves +1, component 1 moves -1, as in the segment kernel of
+// Fig. 2).  The grid exits once the queue is empty: every wave reaches the
+// exit test after its last walk.
+#include "qwalk.h"
+#include "qw_device.h"
+#include "qw_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace qw {
+namespace {
+
+constexpr int kBT = 512;          // threads per batch workgroup
+constexpr int kWaves = kBT / 64;
+constexpr int kMaxBins = 1024;
+constexpr int kNumCfg = 4;        // tiled-path variants (MT, K)
+constexpr int kCfgMT[kNumCfg] = {4, 4, 8, 8};
+constexpr int kCfgK[kNumCfg] = {8, 16, 8, 16};
+
+struct WalkDesc {
+    int32_t N, T, x0, cfg;  // cfg < 0: whole-ring path with m sites per thread; else tiled variant
+    int32_t m, pad;
+    int64_t p_off;          // offset of this walk's P in the full-distribution output
+    double cre[4], cim[4];  // coin, row-major
+    double pre[2], pim[2];  // start coin state
+};
+
+struct BatchArgs {
+    const WalkDesc *walks;
+    const int32_t *order;   // queue position -> walk index (tiled walks first)
+    int32_t n;
+    int32_t n_tiled;
+    int32_t nbins;
+    unsigned int *queue;    // [0], [1]: next position in the tiled / whole part
+    void *slots;            // per-workgroup slot buffers: 2 buffers x 2 planes x slot_elems
+    int64_t slot_elems;
+    double *moments;        // n x 3
+    float *bins;            // n x nbins (or null)
+    double *P;              // full distributions (or null)
+};
+
+template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, Coin2<R> &cn) {
+    cn.c00r = (R)w.cre[0]; cn.c00i = (R)w.cim[0];
+    cn.c01r = (R)w.cre[1]; cn.c01i = (R)w.cim[1];
+    cn.c10r = (R)w.cre[2]; cn.c10i = (R)w.cim[2];
+    cn.c11r = (R)w.cre[3]; cn.c11i = (R)w.cim[3];
+}
+
+__device__ __forceinline__ int wrapN(int64_t v, int N) {
+    int64_t r = v % N;
+    return (int)(r < 0 ? r + N : r);
+}
+
+// signed offset of site x from x0 on a ring of N sites, in (-N/2, N/2]
+__device__ __forceinline__ int ring_offset(int x, int x0, int N) {
+    int dx = x - x0;
+    dx = dx < 0 ? dx + N : dx;
+    return dx > N / 2 ? dx - N : dx;
+}
+
+// Accumulates one site of P into the moments and the bins.  Bins follow the
+// symmetric split: with h = nbins/2 and w = floor((N-1)/2 / h) sites per bin,
+// offsets -k*w .. -(k-1)*w-1 go to bin h-k, offsets (k-1)*w+1 .. k*w to bin
+// h+k-1, the start site half to each of bins h-1 and h.
+struct SiteAcc {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    __device__ __forceinline__ void add(double p, int dx, int N, int nbins, double *s_bins) {
+        const double fx = (double)dx;
+        s0 += p;
+        s1 += p * fx;
+        s2 += p * fx * fx;
+        if (nbins > 0 && p != 0.0) {
+            const int h = nbins >> 1;
+            const int wb = ((N - 1) / 2) / h;
+            if (wb >= 1) {
+                if (dx == 0) {
+                    atomicAdd(&s_bins[h - 1], 0.5 * p);
+                    atomicAdd(&s_bins[h], 0.5 * p);
+                } else if (dx < 0) {
+                    const int k = (-dx - 1) / wb;
+                    if (k < h) atomicAdd(&s_bins[h - 1 - k], p);
+                } else {
+                    const int k = (dx - 1) / wb;
+                    if (k < h) atomicAdd(&s_bins[h + k], p);
+                }
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// sum over the workgroup in a fixed order -> valid in thread 0
+__device__ __forceinline__ void wg_reduce3(SiteAcc &acc, double (*s_red)[kWaves]) {
+    const double a = wave_sum64(acc.s0), b = wave_sum64(acc.s1), c = wave_sum64(acc.s2);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][w] = a;
+        s_red[1][w] = b;
+        s_red[2][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+        for (int i = 0; i < kWaves; ++i) {
+            r0 += s_red[0][i];
+            r1 += s_red[1][i];
+            r2 += s_red[2][i];
+        }
+        acc.s0 = r0;
+        acc.s1 = r1;
+        acc.s2 = r2;
+    }
+}
+
+template <typename R> __device__ __forceinline__ double abs2d(cv<R> v) {
+    const double re = (double)v.x, im = (double)v.y;
+    return re * re + im * im;
+}
+
+// ---------------------------------------------------------------- whole ring
+template <typename R, int M>
+__device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A, cv<R> (*L0)[kBT], cv<R> (*L1)[kBT],
+                           double *s_bins, SiteAcc &acc) {
+    const int N = w.N;
+    const int j = threadIdx.x;
+    const int nl = (N + M - 1) / M;
+    const bool active = j < nl;
+    const int cnt = active ? min(M, N - j * M) : 0;
+    const int jl = j == 0 ? nl - 1 : j - 1;
+    const int jr = j + 1 >= nl ? 0 : j + 1;
+    Coin2<R> cn;
+    load_coin<R>(w, cn);
+    // a_0: component 0 at x0 - 1, component 1 at x0 + 1
+    const int p0 = wrapN((int64_t)w.x0 - 1, N), p1 = wrapN((int64_t)w.x0 + 1, N);
+    cv<R> a0[M], a1[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int x = j * M + m;
+        a0[m] = czero<R>();
+        a1[m] = czero<R>();
+        if (m < cnt && x == p0) { a0[m].x = (R)w.pre[0]; a0[m].y = (R)w.pim[0]; }
+        if (m < cnt && x == p1) { a1[m].x = (R)w.pre[1]; a1[m].y = (R)w.pim[1]; }
+    }
+    // T steps, then one more exchange round for P (parity continues)
+    for (int s = 0; s <= w.T; ++s) {
+        const int p = s & 1;
+        if (active) {
+            cv<R> last = a0[0];
+#pragma unroll
+            for (int m = 1; m < M; ++m)
+                if (m < cnt) last = a0[m];
+            L0[p][j] = last;
+            L1[p][j] = a1[0];
+        }
+        __syncthreads();
+        if (active) {
+            const cv<R> left = L0[p][jl], right = L1[p][jr];
+            if (s < w.T) {
+                // in place, ascending m: a0[m-1] is carried, a1[m+1] is still old
+                cv<R> prev = left;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const cv<R> g0 = prev;
+                    const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                    prev = a0[m];
+                    cn.apply(g0, g1, a0[m], a1[m]);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (m < cnt) {
+                        const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+                        const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                        const double pr = abs2d<R>(g0) + abs2d<R>(g1);
+                        const int x = j * M + m;
+                        acc.add(pr, ring_offset(x, w.x0, N), N, A.nbins, s_bins);
+                        if (A.P) A.P[w.p_off + x] = pr;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- tiled ring
+// one step of one site range [o, o + n) of the output box, straight from memory
+template <typename R>
+__device__ __forceinline__ void one_step_range(const cv<R> *in0, const cv<R> *in1, cv<R> *out0, cv<R> *out1,
+                                               int N, int start, int width, const Coin2<R> &cn) {
+    for (int i = threadIdx.x; i < width; i += kBT) {
+        int x = start + i;
+        x = x >= N ? x - N : x;
+        const int xl = x == 0 ? N - 1 : x - 1, xr = x + 1 == N ? 0 : x + 1;
+        cv<R> o0, o1;
+        cn.apply(in0[xl], in1[xr], o0, o1);
+        out0[x] = o0;
+        out1[x] = o1;
+    }
+}
+
+template <typename R, int MT, int K>
+__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, double *s_bins, SiteAcc &acc) {
+    const int N = w.N;
+    const int64_t se = A.slot_elems;
+    cv<R> *const base = (cv<R> *)A.slots + (int64_t)blockIdx.x * 4 * se;  // [buffer][plane][site]
+    Coin2<R> cn;
+    load_coin<R>(w, cn);
+    // zero both buffers over the region the walk can reach (cone plus halo)
+    const int64_t reach = (int64_t)w.T + K + 2;
+    const int zw = (int)std::min<int64_t>(N, 2 * reach + 1);
+    const int zs = zw == N ? 0 : wrapN((int64_t)w.x0 - reach, N);
+    for (int i = threadIdx.x; i < zw; i += kBT) {
+        int x = zs + i;
+        x = x >= N ? x - N : x;
+        const cv<R> z = czero<R>();
+        base[x] = z;
+        base[se + x] = z;
+        base[2 * se + x] = z;
+        base[3 * se + x] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cv<R> v;
+        v.x = (R)w.pre[0]; v.y = (R)w.pim[0];
+        base[wrapN((int64_t)w.x0 - 1, N)] = v;
+        v.x = (R)w.pre[1]; v.y = (R)w.pim[1];
+        base[se + wrapN((int64_t)w.x0 + 1, N)] = v;
+    }
+    __syncthreads();
+    // support of a_t relative to x0: [-1 - t, 1 + t]
+    int cur = 0;
+    int64_t half = 1;  // box half-width
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int TW = 64 * MT - 2 * K;
+    int t = 0;
+    while (t < w.T) {
+        const int k = (w.T - t) >= K ? K : 1;
+        half += k;
+        const int width = (int)std::min<int64_t>(N, 2 * half + 1);
+        const int start = width == N ? 0 : wrapN((int64_t)w.x0 - half, N);
+        const cv<R> *i0 = base + (int64_t)cur * 2 * se, *i1 = i0 + se;
+        cv<R> *o0 = base + (int64_t)(cur ^ 1) * 2 * se, *o1 = o0 + se;
+        if (k == K) {
+            const int ntiles = (width + TW - 1) / TW;
+            for (int tile = wave; tile < ntiles; tile += kWaves) {
+                const int tb = wrapN((int64_t)start + (int64_t)tile * TW - K + lane * MT, N);
+                cv<R> a0[MT], a1[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    int x = tb + m;
+                    x = x >= N ? x - N : x;
+                    a0[m] = i0[x];
+                    a1[m] = i1[x];
+                }
+                ring_tile_steps<R, MT, K>(a0, a1, cn);
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    const int q = lane * MT + m;
+                    if (q >= K && q < 64 * MT - K && tile * TW + q - K < width) {
+                        int x = tb + m;
+                        x = x >= N ? x - N : x;
+                        o0[x] = a0[m];
+                        o1[x] = a1[m];
+                    }
+                }
+            }
+        } else {
+            one_step_range<R>(i0, i1, o0, o1, N, start, width, cn);
+        }
+        __syncthreads();
+        cur ^= 1;
+        t += k;
+    }
+    // P over the box of psi (support of a grown by one), zeros elsewhere
+    const int64_t ph = half + 1;
+    const int pw = (int)std::min<int64_t>(N, 2 * ph + 1);
+    const int ps = pw == N ? 0 : wrapN((int64_t)w.x0 - ph, N);
+    const cv<R> *a0 = base + (int64_t)cur * 2 * se, *a1 = a0 + se;
+    for (int i = threadIdx.x; i < pw; i += kBT) {
+        int x = ps + i;
+        x = x >= N ? x - N : x;
+        const int xl = x == 0 ? N - 1 : x - 1, xr = x + 1 == N ? 0 : x + 1;
+        const double pr = abs2d<R>(a0[xl]) + abs2d<R>(a1[xr]);
+        acc.add(pr, ring_offset(x, w.x0, N), N, A.nbins, s_bins);
+        if (A.P) A.P[w.p_off + x] = pr;
+    }
+    if (A.P && pw < N) {
+        for (int i = threadIdx.x; i < N - pw; i += kBT) {
+            int x = ps + pw + i;
+            x = x >= N ? x - N : x;
+            A.P[w.p_off + x] = 0.0;
+        }
+    }
+}
+
+template <typename R> __device__ __forceinline__ void finish_walk(const BatchArgs &A, int wi, SiteAcc &acc,
+                                                                   double *s_bins, double (*s_red)[kWaves]) {
+    wg_reduce3(acc, s_red);  // contains the barrier that orders the bin atomics
+    if (threadIdx.x == 0) {
+        A.moments[3 * (int64_t)wi + 0] = acc.s0;
+        A.moments[3 * (int64_t)wi + 1] = acc.s1;
+        A.moments[3 * (int64_t)wi + 2] = acc.s2;
+    }
+    if (A.bins)
+        for (int i = threadIdx.x; i < A.nbins; i += kBT) A.bins[(int64_t)wi * A.nbins + i] = (float)s_bins[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0.0;
+    __syncthreads();
+}
+
+// The queue holds the tiled walks first (positions [0, n_tiled)), then the
+// walks held whole (positions [n_tiled, n)), each part longest-first.  A
+// workgroup drains the first part, then the second: two loops in sequence, so
+// the register budgets of the two paths never overlap.
+template <typename R, int MMAX>
+__global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
+    __shared__ int s_q;
+    __shared__ cv<R> L0[2][kBT];
+    __shared__ cv<R> L1[2][kBT];
+    __shared__ double s_bins[kMaxBins];
+    __shared__ double s_red[3][kWaves];
+    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0.0;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = (int)atomicAdd(&A.queue[0], 1u);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= A.n_tiled) break;  // uniform across the workgroup
+        const int wi = A.order[q];
+        const WalkDesc w = A.walks[wi];
+        SiteAcc acc;
+        switch (w.cfg) {
+        case 0: walk_tiled<R, kCfgMT[0], kCfgK[0]>(w, A, s_bins, acc); break;
+        case 1: walk_tiled<R, kCfgMT[1], kCfgK[1]>(w, A, s_bins, acc); break;
+        case 2: walk_tiled<R, kCfgMT[2], kCfgK[2]>(w, A, s_bins, acc); break;
+        default: walk_tiled<R, kCfgMT[3], kCfgK[3]>(w, A, s_bins, acc); break;
+        }
+        finish_walk<R>(A, wi, acc, s_bins, s_red);
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_q = A.n_tiled + (int)atomicAdd(&A.queue[1], 1u);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= A.n) break;
+        const int wi = A.order[q];
+        const WalkDesc w = A.walks[wi];
+        SiteAcc acc;
+        switch (w.m) {
+#define QW_WHOLE_CASE(MM) \
+        case MM: if (MM <= MMAX) walk_whole<R, (MM <= MMAX ? MM : 1)>(w, A, L0, L1, s_bins, acc); break;
+        QW_WHOLE_CASE(1) QW_WHOLE_CASE(2) QW_WHOLE_CASE(3) QW_WHOLE_CASE(4)
+        QW_WHOLE_CASE(5) QW_WHOLE_CASE(6) QW_WHOLE_CASE(7) QW_WHOLE_CASE(8)
+        QW_WHOLE_CASE(9) QW_WHOLE_CASE(10) QW_WHOLE_CASE(11) QW_WHOLE_CASE(12)
+        QW_WHOLE_CASE(13) QW_WHOLE_CASE(14) QW_WHOLE_CASE(15) QW_WHOLE_CASE(16)
+#undef QW_WHOLE_CASE
+        default: break;
+        }
+        finish_walk<R>(A, wi, acc, s_bins, s_red);
+    }
+}
+
+__global__ void k_queue_reset(unsigned int *q) {
+    q[0] = 0u;
+    q[1] = 0u;
+}
+
+constexpr int kMaxMC128 = 4;   // whole-ring sites per thread (register budget)
+constexpr int kMaxMC64 = 9;
+
+}  // namespace
+}  // namespace qw
+
+using namespace qw;
+
+// ================================================================ host side
+namespace {
+
+thread_local std::string g_berr;
+
+int bfail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_berr = buf;
+    return code;
+}
+
+#define QB_HIP(call, what)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return bfail(QW_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
+    } while (0)
+
+int size_bucket(int64_t N) {
+    if (N <= 10000) return 0;
+    if (N <= 100000) return 1;
+    return 2;
+}
+
+std::string tune_cache_path() {
+    const char *p = getenv("QWALK_TUNE_CACHE");
+    if (p && *p) return p;
+    const char *h = getenv("HOME");
+    return std::string(h && *h ? h : "/tmp") + "/.cache/qwalk_tune.txt";
+}
+
+// cache lines: "<device> <prec> <bucket> <cfg>"
+std::map<std::string, int> read_cache() {
+    std::map<std::string, int> m;
+    FILE *f = fopen(tune_cache_path().c_str(), "r");
+    if (!f) return m;
+    char dev[256];
+    int prec, bucket, cfg;
+    while (fscanf(f, "%255s %d %d %d", dev, &prec, &bucket, &cfg) == 4)
+        if (cfg >= 0 && cfg < kNumCfg) m[std::string(dev) + "/" + std::to_string(prec) + "/" + std::to_string(bucket)] = cfg;
+    fclose(f);
+    return m;
+}
+
+void write_cache(const std::map<std::string, int> &m) {
+    std::string path = tune_cache_path();
+    std::string dir = path.substr(0, path.find_last_of('/'));
+    if (!dir.empty()) {
+        std::string cmd = dir;  // create the directory without a shell
+        for (size_t i = 1; i <= cmd.size(); ++i)
+            if (i == cmd.size() || cmd[i] == '/') {
+                std::string sub = cmd.substr(0, i);
+                (void)mkdir(sub.c_str(), 0755);
+            }
+    }
+    FILE *f = fopen(path.c_str(), "w");
+    if (!f) return;
+    for (auto &kv : m) {
+        std::string k = kv.first;
+        size_t a = k.find('/'), b = k.find('/', a + 1);
+        fprintf(f, "%s %s %s %d\n", k.substr(0, a).c_str(), k.substr(a + 1, b - a - 1).c_str(), k.substr(b + 1).c_str(),
+                kv.second);
+    }
+    fclose(f);
+}
+
+std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string s = p.gcnArchName;
+    for (auto &c : s)
+        if (c == ' ' || c == '/' || c == ':') c = '_';
+    return s + "_cu" + std::to_string(p.multiProcessorCount);
+}
+
+}  // namespace
+
+struct qw_batch {
+    int prec = QW_C64;
+    int64_t n = 0;
+    int nbins = 0;
+    bool keep = false, use_graph = true;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<WalkDesc> walks;     // host copy
+    std::vector<int32_t> order;
+    std::vector<int64_t> p_off;
+    int64_t total_sites = 0;
+    int64_t n_tiled = 0;
+    WalkDesc *d_walks = nullptr;
+    int32_t *d_order = nullptr;
+    unsigned int *d_queue = nullptr;
+    void *d_slots = nullptr;
+    int64_t slot_elems = 0;
+    double *d_moments = nullptr;
+    float *d_bins = nullptr;
+    double *d_P = nullptr;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int bucket_cfg[3] = {3, 3, 3};
+    double last_ms = 0.0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool own_stream = false;
+};
+
+namespace {
+
+void free_batch(qw_batch *b) {
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_walks);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_queue);
+    (void)hipFree(b->d_slots);
+    (void)hipFree(b->d_moments);
+    (void)hipFree(b->d_bins);
+    (void)hipFree(b->d_P);
+    for (auto e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, int32_t n, int32_t n_tiled) {
+    BatchArgs A;
+    A.walks = walks;
+    A.order = order;
+    A.n = n;
+    A.n_tiled = n_tiled;
+    A.nbins = b->nbins;
+    A.queue = b->d_queue;
+    A.slots = b->d_slots;
+    A.slot_elems = b->slot_elems;
+    A.moments = b->d_moments;
+    A.bins = b->d_bins;
+    A.P = b->keep ? b->d_P : nullptr;
+    return A;
+}
+
+hipError_t enqueue(qw_batch *b, const BatchArgs &A, int grid) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, b->stream, b->d_queue);
+    if (b->prec == QW_C128)
+        hipLaunchKernelGGL((k_batch<double, kMaxMC128>), dim3(grid), dim3(kBT), 0, b->stream, A);
+    else
+        hipLaunchKernelGGL((k_batch<float, kMaxMC64>), dim3(grid), dim3(kBT), 0, b->stream, A);
+    return hipGetLastError();
+}
+
+int persistent_grid(int prec, int64_t n) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    hipError_t e;
+    if (prec == QW_C128)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<double, kMaxMC128>, kBT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<float, kMaxMC64>, kBT, 0);
+    if (e != hipSuccess || per < 1) {
+        (void)hipGetLastError();
+        per = 1;
+    }
+    int64_t g = (int64_t)cus * per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, n));
+}
+
+// estimated site*coin updates of one walk (whole ring: every site every step)
+double walk_work(const WalkDesc &w) {
+    if (w.cfg < 0) return 2.0 * w.N * (double)w.T;
+    const double T = w.T, N = w.N;
+    const double tc = std::max(0.0, std::min(T, (N - 3.0) / 2.0));  // steps before the cone wraps
+    return 2.0 * ((tc * (tc + 4.0)) + (T - tc) * N);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *walk_batch_last_error(void) { return g_berr.c_str(); }
+
+int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const double *angles, const double *psi0,
+                      const int64_t *x0, int32_t prec, const qw_batch_opts *opts, void *stream, qw_batch_t *out) {
+    if (!out) return bfail(QW_EINVAL, "out handle pointer is NULL");
+    *out = nullptr;
+    if (n < 1) return bfail(QW_EINVAL, "batch needs at least one walk (n = %lld)", (long long)n);
+    if (n > (1LL << 30)) return bfail(QW_ERANGE, "batch too large");
+    if (!N || !T || !angles || !psi0) return bfail(QW_EINVAL, "N, T, angles and psi0 must not be NULL");
+    if (prec != QW_C128 && prec != QW_C64) return bfail(QW_EINVAL, "precision must be QW_C128 or QW_C64");
+    qw_batch_opts o;
+    memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    if (o.nbins < 0 || o.nbins > kMaxBins || (o.nbins & 1))
+        return bfail(QW_EINVAL, "nbins must be 0 or even and <= %d (got %d)", kMaxBins, o.nbins);
+    if (o.tiled_variant < 0 || o.tiled_variant > kNumCfg)
+        return bfail(QW_EINVAL, "tiled_variant must be 0 (tuned) or 1..%d", kNumCfg);
+    qw_batch *b = new (std::nothrow) qw_batch();
+    if (!b) return bfail(QW_ENOMEM, "host allocation failed");
+    b->prec = prec;
+    b->n = n;
+    b->nbins = o.nbins;
+    b->keep = o.keep_probabilities != 0;
+    b->use_graph = o.no_graph == 0;
+    b->stream = (hipStream_t)stream;
+    const int mmax = prec == QW_C128 ? kMaxMC128 : kMaxMC64;
+    b->walks.resize(n);
+    b->p_off.resize(n);
+    int64_t maxN_tiled = 0, off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        WalkDesc &w = b->walks[i];
+        memset(&w, 0, sizeof w);
+        if (N[i] < 1 || N[i] > 2147483647LL) {
+            free_batch(b);
+            return bfail(QW_EINVAL, "walk %lld: N must be in [1, 2^31 - 1]", (long long)i);
+        }
+        if (T[i] < 0 || T[i] > 2147483647LL) {
+            free_batch(b);
+            return bfail(QW_EINVAL, "walk %lld: T must be in [0, 2^31 - 1]", (long long)i);
+        }
+        const double th = angles[3 * i], ph = angles[3 * i + 1], ch = angles[3 * i + 2];
+        if (!isfinite(th) || !isfinite(ph) || !isfinite(ch)) {
+            free_batch(b);
+            return bfail(QW_EINVAL, "walk %lld: coin angles must be finite", (long long)i);
+        }
+        double nn = 0.0;
+        for (int k = 0; k < 4; ++k) nn += psi0[4 * i + k] * psi0[4 * i + k];
+        if (!(fabs(nn - 1.0) <= 1e-12)) {
+            free_batch(b);
+            return bfail(QW_ENOTNORM, "walk %lld: start coin state not normalised (%.17g)", (long long)i, nn);
+        }
+        w.N = (int32_t)N[i];
+        w.T = (int32_t)T[i];
+        int64_t xs = x0 ? x0[i] : N[i] / 2;
+        xs %= N[i];
+        w.x0 = (int32_t)(xs < 0 ? xs + N[i] : xs);
+        // SU(2) coin [[e^{i phi} cos t, e^{i chi} sin t], [-e^{-i chi} sin t, e^{-i phi} cos t]]
+        const double ct = cos(th), st = sin(th);
+        w.cre[0] = cos(ph) * ct;  w.cim[0] = sin(ph) * ct;
+        w.cre[1] = cos(ch) * st;  w.cim[1] = sin(ch) * st;
+        w.cre[2] = -cos(ch) * st; w.cim[2] = sin(ch) * st;
+        w.cre[3] = cos(ph) * ct;  w.cim[3] = -sin(ph) * ct;
+        w.pre[0] = psi0[4 * i];     w.pim[0] = psi0[4 * i + 1];
+        w.pre[1] = psi0[4 * i + 2]; w.pim[1] = psi0[4 * i + 3];
+        const int64_t m = (N[i] + kBT - 1) / kBT;
+        if (m <= mmax) {
+            w.cfg = -1;
+            w.m = (int32_t)m;
+        } else {
+            w.cfg = 0;  // variant assigned below, once the tuning cache is read
+            w.m = 0;
+            maxN_tiled = std::max<int64_t>(maxN_tiled, N[i]);
+        }
+        w.p_off = off;
+        b->p_off[i] = off;
+        off += N[i];
+    }
+    b->total_sites = off;
+    // everything above is host-side validation; the device is touched from here on
+    if (!b->stream) {
+        // a graph cannot be captured on the legacy default stream: use a private one
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return bfail(QW_EHIP, "hipStreamCreate failed");
+        }
+        b->own_stream = true;
+    }
+    (void)hipGetDevice(&b->device);
+    {
+        // tuned configuration per size bucket
+        auto cache = read_cache();
+        const std::string dk = device_key();
+        for (int bk = 0; bk < 3; ++bk) {
+            auto it = cache.find(dk + "/" + std::to_string(prec) + "/" + std::to_string(bk));
+            if (it != cache.end()) b->bucket_cfg[bk] = it->second;
+            if (o.tiled_variant > 0) b->bucket_cfg[bk] = o.tiled_variant - 1;
+        }
+        for (auto &w : b->walks)
+            if (w.cfg >= 0) w.cfg = b->bucket_cfg[size_bucket(w.N)];
+    }
+    // longest first
+    b->order.resize(n);
+    for (int64_t i = 0; i < n; ++i) b->order[i] = (int32_t)i;
+    std::vector<double> work(n);
+    for (int64_t i = 0; i < n; ++i) work[i] = walk_work(b->walks[i]);
+    // tiled walks first, then the walks held whole; each part longest-first
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t a, int32_t c) {
+        const bool ta = b->walks[a].cfg >= 0, tc = b->walks[c].cfg >= 0;
+        if (ta != tc) return ta;
+        return work[a] > work[c];
+    });
+    b->n_tiled = 0;
+    for (int64_t i = 0; i < n; ++i) b->n_tiled += b->walks[i].cfg >= 0;
+    for (int64_t i = 0; i < n; ++i) b->walks[i].p_off = b->p_off[i];
+
+    b->grid = persistent_grid(prec, n);
+    b->slot_elems = maxN_tiled;
+    const size_t esz = prec == QW_C128 ? 16 : 8;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **p, size_t bytes) {
+        if (bytes == 0) return true;
+        e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return false;
+        }
+        return true;
+    };
+    bool ok = alloc((void **)&b->d_walks, sizeof(WalkDesc) * n) && alloc((void **)&b->d_order, sizeof(int32_t) * n) &&
+              alloc((void **)&b->d_queue, 256) && alloc(&b->d_slots, (size_t)b->grid * 4 * maxN_tiled * esz) &&
+              alloc((void **)&b->d_moments, sizeof(double) * 3 * n) &&
+              (b->nbins == 0 || alloc((void **)&b->d_bins, sizeof(float) * b->nbins * n)) &&
+              (!b->keep || alloc((void **)&b->d_P, sizeof(double) * off));
+    if (!ok) {
+        const std::string msg = hipGetErrorString(e);
+        free_batch(b);
+        return bfail(QW_ENOMEM, "device allocation for the batch failed: %s", msg.c_str());
+    }
+    if (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
+        free_batch(b);
+        return bfail(QW_EHIP, "hipEventCreate failed");
+    }
+    e = hipMemcpyAsync(b->d_walks, b->walks.data(), sizeof(WalkDesc) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return bfail(QW_EHIP, "upload of the walk table: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return QW_OK;
+}
+
+int walk_batch_run(qw_batch_t b) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    const BatchArgs A = make_args(b, b->d_walks, b->d_order, (int32_t)b->n, (int32_t)b->n_tiled);
+    QB_HIP(hipEventRecord(b->ev[0], b->stream), "hipEventRecord");
+    if (b->use_graph) {
+        if (!b->gexec) {
+            QB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            hipError_t e = enqueue(b, A, b->grid);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return bfail(QW_EHIP, "graph capture of the batch launch: %s",
+                             hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            b->graph = g;
+            QB_HIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+        QB_HIP(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
+    } else {
+        QB_HIP(enqueue(b, A, b->grid), "batch kernel launch");
+    }
+    QB_HIP(hipEventRecord(b->ev[1], b->stream), "hipEventRecord");
+    return QW_OK;
+}
+
+int walk_batch_moments(qw_batch_t b, double *out, int32_t on_device) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    if (!out) return bfail(QW_EINVAL, "output pointer is NULL");
+    QB_HIP(hipMemcpyAsync(out, b->d_moments, sizeof(double) * 3 * b->n,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream),
+           "copy of the moments");
+    if (!on_device || b->own_stream) QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    return QW_OK;
+}
+
+int walk_batch_binned(qw_batch_t b, float *out, int32_t on_device) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    if (!out) return bfail(QW_EINVAL, "output pointer is NULL");
+    if (b->nbins == 0) return bfail(QW_EINVAL, "the batch was created without bins (nbins = 0)");
+    QB_HIP(hipMemcpyAsync(out, b->d_bins, sizeof(float) * b->nbins * b->n,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream),
+           "copy of the bins");
+    if (!on_device || b->own_stream) QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    return QW_OK;
+}
+
+int walk_batch_probabilities(qw_batch_t b, double *out, int32_t on_device) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    if (!out) return bfail(QW_EINVAL, "output pointer is NULL");
+    if (!b->keep) return bfail(QW_EINVAL, "the batch was created without keep_probabilities");
+    QB_HIP(hipMemcpyAsync(out, b->d_P, sizeof(double) * b->total_sites,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream),
+           "copy of the distributions");
+    if (!on_device || b->own_stream) QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    return QW_OK;
+}
+
+int walk_batch_info(qw_batch_t b, qw_batch_info *out) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    if (!out) return bfail(QW_EINVAL, "output pointer is NULL");
+    QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, b->ev[0], b->ev[1]) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = -1.0f;
+    }
+    out->n = b->n;
+    out->grid = b->grid;
+    out->graph = b->gexec != nullptr;
+    int64_t whole = 0;
+    double work = 0.0;
+    for (auto &w : b->walks) {
+        whole += w.cfg < 0;
+        work += walk_work(w);
+    }
+    out->whole_ring_walks = whole;
+    out->est_updates = work;
+    out->last_run_ms = ms;
+    for (int k = 0; k < 3; ++k) {
+        out->bucket_cfg[k] = b->bucket_cfg[k];
+        out->bucket_tile_sites[k] = 64 * kCfgMT[b->bucket_cfg[k]];
+        out->bucket_depth[k] = kCfgK[b->bucket_cfg[k]];
+    }
+    return QW_OK;
+}
+
+int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save) {
+    if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
+    if (samples < 1) samples = 8;
+    // per bucket: the tiled walks of the bucket, a spread sample by work
+    std::vector<int32_t> bucket_walks[3];
+    for (int64_t i = 0; i < b->n; ++i)
+        if (b->walks[i].cfg >= 0) bucket_walks[size_bucket(b->walks[i].N)].push_back((int32_t)i);
+    for (int bk = 0; bk < 3; ++bk) {
+        auto &v = bucket_walks[bk];
+        if (v.empty()) continue;
+        std::sort(v.begin(), v.end(), [&](int32_t a, int32_t c) { return walk_work(b->walks[a]) > walk_work(b->walks[c]); });
+        std::vector<int32_t> pick;
+        const int64_t ns = std::min<int64_t>(samples, (int64_t)v.size());
+        for (int64_t s = 0; s < ns; ++s) pick.push_back(v[(size_t)(s * (int64_t)v.size() / ns)]);
+        double best_ms = 1e300;
+        int best = b->bucket_cfg[bk];
+        std::vector<WalkDesc> tw(pick.size());
+        std::vector<int32_t> torder(pick.size());
+        WalkDesc *dw = nullptr;
+        int32_t *dord = nullptr;
+        QB_HIP(hipMalloc((void **)&dw, sizeof(WalkDesc) * pick.size()), "hipMalloc");
+        if (hipMalloc((void **)&dord, sizeof(int32_t) * pick.size()) != hipSuccess) {
+            (void)hipFree(dw);
+            return bfail(QW_ENOMEM, "hipMalloc for tuning failed");
+        }
+        for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+            for (size_t s = 0; s < pick.size(); ++s) {
+                tw[s] = b->walks[pick[s]];
+                tw[s].cfg = cfg;
+                torder[s] = (int32_t)s;
+            }
+            hipError_t e = hipMemcpyAsync(dw, tw.data(), sizeof(WalkDesc) * tw.size(), hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dord, torder.data(), sizeof(int32_t) * torder.size(), hipMemcpyHostToDevice, b->stream);
+            // the tuning runs write moments/bins/P of walk indices 0..ns-1 of the tuning table,
+            // which alias the first walks of the batch: outputs are recomputed by the next run
+            const BatchArgs A = make_args(b, dw, dord, (int32_t)pick.size(), (int32_t)pick.size());
+            const int grid = std::min<int>(b->grid, (int)pick.size());
+            float ms = 0.0f;
+            if (e == hipSuccess) e = enqueue(b, A, grid);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
+            if (e == hipSuccess) e = enqueue(b, A, grid);
+            if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b->ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev[0], b->ev[1]);
+            if (e != hipSuccess) {
+                (void)hipFree(dw);
+                (void)hipFree(dord);
+                return bfail(QW_EHIP, "tuning run: %s", hipGetErrorString(e));
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cfg;
+            }
+        }
+        (void)hipFree(dw);
+        (void)hipFree(dord);
+        b->bucket_cfg[bk] = best;
+        for (auto i : v) b->walks[i].cfg = best;
+    }
+    QB_HIP(hipMemcpyAsync(b->d_walks, b->walks.data(), sizeof(WalkDesc) * b->n, hipMemcpyHostToDevice, b->stream),
+           "upload of the walk table");
+    QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    if (save) {
+        auto cache = read_cache();
+        const std::string dk = device_key();
+        for (int bk = 0; bk < 3; ++bk)
+            if (!bucket_walks[bk].empty())
+                cache[dk + "/" + std::to_string(b->prec) + "/" + std::to_string(bk)] = b->bucket_cfg[bk];
+        write_cache(cache);
+    }
+    return QW_OK;
+}
+
+int walk_batch_destroy(qw_batch_t b) {
+    if (!b) return QW_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    free_batch(b);
+    if (e != hipSuccess) return bfail(QW_EHIP, "stream synchronise in walk_batch_destroy: %s", hipGetErrorString(e));
+    return QW_OK;
+}
+
+}  // extern "C"

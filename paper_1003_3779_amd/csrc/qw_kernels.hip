@@ -23,130 +23,12 @@
 // a box growing by one site per step are exactly zero.  Kernels take the
 // box they must write; both buffers are zero outside the boxes ever written.
 #include "qw_internal.h"
+#include "qw_device.h"
 
 #include <math.h>
 
 namespace qw {
 namespace {
-
-template <typename R> struct VT;
-template <> struct VT<double> { using T = double2; };
-template <> struct VT<float> { using T = float2; };
-template <typename R> using cv = typename VT<R>::T;
-
-template <typename R> struct CoinR {
-    R re[16];
-    R im[16];
-};
-
-template <typename R> CoinR<R> to_coin(const CoinF64 &c) {
-    CoinR<R> o;
-    for (int i = 0; i < 16; ++i) {
-        o.re[i] = (R)c.re[i];
-        o.im[i] = (R)c.im[i];
-    }
-    return o;
-}
-
-__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-template <typename R> __device__ __forceinline__ cv<R> czero() {
-    cv<R> z;
-    z.x = (R)0;
-    z.y = (R)0;
-    return z;
-}
-template <typename R> __device__ __forceinline__ cv<R> cadd(cv<R> a, cv<R> b) {
-    cv<R> r;
-    r.x = a.x + b.x;
-    r.y = a.y + b.y;
-    return r;
-}
-template <typename R> __device__ __forceinline__ cv<R> csub(cv<R> a, cv<R> b) {
-    cv<R> r;
-    r.x = a.x - b.x;
-    r.y = a.y - b.y;
-    return r;
-}
-template <typename R> __device__ __forceinline__ cv<R> cscale(cv<R> a, R s) {
-    cv<R> r;
-    r.x = a.x * s;
-    r.y = a.y * s;
-    return r;
-}
-// (cr + i ci) * v.  The fused multiply-adds are written out so that every
-// kernel rounds a coin application identically (blocked == unblocked, bit
-// for bit), whatever the compiler's contraction choices.
-template <typename R> __device__ __forceinline__ cv<R> cmul(R cr, R ci, cv<R> v) {
-    cv<R> r;
-    r.x = fmaR(cr, v.x, -(ci * v.y));
-    r.y = fmaR(cr, v.y, ci * v.x);
-    return r;
-}
-// acc + (cr + i ci) * v
-template <typename R> __device__ __forceinline__ cv<R> cmac(cv<R> acc, R cr, R ci, cv<R> v) {
-    acc.x = fmaR(cr, v.x, acc.x);
-    acc.x = fmaR(-ci, v.y, acc.x);
-    acc.y = fmaR(cr, v.y, acc.y);
-    acc.y = fmaR(ci, v.x, acc.y);
-    return acc;
-}
-
-// ---- the coin on one site's d gathered values (components in ascending order) ----
-template <typename R, int D, int COIN> struct Coin;
-
-template <typename R, int D> struct Coin<R, D, COIN_DENSE> {
-    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &C) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            cv<R> acc = cmul<R>(C.re[c * D], C.im[c * D], g[0]);
-#pragma unroll
-            for (int k = 1; k < D; ++k) acc = cmac<R>(acc, C.re[c * D + k], C.im[c * D + k], g[k]);
-            o[c] = acc;
-        }
-    }
-};
-// Grover, d = 4: G = J/2 - I, so (G g)_c = (g0 + g1 + g2 + g3)/2 - g_c.
-template <typename R> struct Coin<R, 4, COIN_GROVER4> {
-    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &) {
-        cv<R> s = cscale<R>(cadd<R>(cadd<R>(g[0], g[1]), cadd<R>(g[2], g[3])), (R)0.5);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) o[c] = csub<R>(s, g[c]);
-    }
-};
-// H (x) H, d = 4, c = 2j + k: two butterfly levels and a factor 1/2.
-template <typename R> struct Coin<R, 4, COIN_HH4> {
-    __device__ __forceinline__ static void apply(const cv<R> *g, cv<R> *o, const CoinR<R> &) {
-        cv<R> u0 = cadd<R>(g[0], g[1]), u1 = csub<R>(g[0], g[1]);
-        cv<R> u2 = cadd<R>(g[2], g[3]), u3 = csub<R>(g[2], g[3]);
-        o[0] = cscale<R>(cadd<R>(u0, u2), (R)0.5);
-        o[1] = cscale<R>(cadd<R>(u1, u3), (R)0.5);
-        o[2] = cscale<R>(csub<R>(u0, u2), (R)0.5);
-        o[3] = cscale<R>(csub<R>(u1, u3), (R)0.5);
-    }
-};
-
-__device__ __forceinline__ int wrapi(int v, int L) {
-    v = v < 0 ? v + L : v;
-    return v >= L ? v - L : v;
-}
-
-// ---- cross-lane moves of one complex value within a wave64 ----
-// from_left: lane i receives lane i-1's value; from_right: lane i receives
-// lane i+1's value.  The edge lanes receive their own value (they are halo).
-template <typename R> __device__ __forceinline__ cv<R> from_left(cv<R> v) {
-    cv<R> r;
-    r.x = __shfl_up(v.x, 1, 64);
-    r.y = __shfl_up(v.y, 1, 64);
-    return r;
-}
-template <typename R> __device__ __forceinline__ cv<R> from_right(cv<R> v) {
-    cv<R> r;
-    r.x = __shfl_down(v.x, 1, 64);
-    r.y = __shfl_down(v.y, 1, 64);
-    return r;
-}
 
 // =====================================================================
 // fill / place
@@ -323,26 +205,9 @@ __global__ __launch_bounds__(256) void k_ring_tiles(const cv<R> *__restrict__ in
         a0[m] = in[x];
         a1[m] = in[ps + x];
     }
-    const R c00r = C.re[0], c00i = C.im[0], c01r = C.re[1], c01i = C.im[1];
-    const R c10r = C.re[2], c10i = C.im[2], c11r = C.re[3], c11i = C.im[3];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const cv<R> left = from_left<R>(a0[M - 1]);
-        const cv<R> right = from_right<R>(a1[0]);
-        cv<R> n0[M], n1[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
-            const cv<R> g1 = m == M - 1 ? right : a1[m == M - 1 ? m : m + 1];
-            n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
-            n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
-        }
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            a0[m] = n0[m];
-            a1[m] = n1[m];
-        }
-    }
+    Coin2<R> cn;
+    cn.load(C);
+    ring_tile_steps<R, M, K>(a0, a1, cn);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int q = lane * M + m;

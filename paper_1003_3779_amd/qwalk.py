@@ -30,6 +30,9 @@ ABI_SYMBOLS = (
     "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
     "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
     "walk_reset", "walk_profile",
+    "walk_batch_create", "walk_batch_run", "walk_batch_moments", "walk_batch_binned",
+    "walk_batch_probabilities", "walk_batch_info", "walk_batch_tune", "walk_batch_destroy",
+    "walk_batch_last_error",
 )
 KERNEL_NAMES = ("step", "ring_whole", "ring_tiles", "stream2d")
 
@@ -59,6 +62,19 @@ class Options(ctypes.Structure):
 class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes_read", ctypes.c_double),
                 ("bytes_written", ctypes.c_double), ("updates", ctypes.c_double)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("nbins", ctypes.c_int32), ("keep_probabilities", ctypes.c_int32),
+                ("tiled_variant", ctypes.c_int32), ("no_graph", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("grid", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("whole_ring_walks", ctypes.c_int64), ("est_updates", ctypes.c_double),
+                ("last_run_ms", ctypes.c_double), ("bucket_cfg", ctypes.c_int32 * 3),
+                ("bucket_tile_sites", ctypes.c_int32 * 3), ("bucket_depth", ctypes.c_int32 * 3),
+                ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -96,13 +112,23 @@ def load():
         "walk_destroy": [P],
         "walk_reset": [P, P, P],
         "walk_profile": [P, P, I32],
+        "walk_batch_create": [I64, P, P, P, P, P, I32, P, P, P],
+        "walk_batch_run": [P],
+        "walk_batch_moments": [P, P, I32],
+        "walk_batch_binned": [P, P, I32],
+        "walk_batch_probabilities": [P, P, I32],
+        "walk_batch_info": [P, P],
+        "walk_batch_tune": [P, I32, I32],
+        "walk_batch_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
-    lib.walk_last_error.argtypes = []
-    lib.walk_last_error.restype = ctypes.c_char_p
+    for name in ("walk_last_error", "walk_batch_last_error"):
+        f = getattr(lib, name)
+        f.argtypes = []
+        f.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -292,3 +318,79 @@ def state_bytes(extent, disp, prec: int) -> int:
     n = ctypes.c_size_t()
     _check(load().walk_state_bytes(ctypes.byref(lat), prec, ctypes.byref(n)))
     return n.value
+
+
+def _bcheck(rc: int):
+    if rc != QW_OK:
+        msg = load().walk_batch_last_error().decode(errors="replace")
+        raise QWError(rc, msg)
+
+
+class Batch:
+    """Independent ring walks in one persistent launch (walk_batch_*)."""
+
+    def __init__(self, N, T, angles, psi0, x0=None, prec: int = QW_C64, nbins: int = 0,
+                 keep_probabilities: bool = False, tiled_variant: int = 0, no_graph: bool = False,
+                 stream=None):
+        lib = load()
+        self._lib = lib
+        self.N = np.ascontiguousarray(np.asarray(N, dtype=np.int64))
+        self.T = np.ascontiguousarray(np.asarray(T, dtype=np.int64))
+        n = self.N.size
+        ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).reshape(n, 3))
+        p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128).reshape(n, 2))
+        xa = None if x0 is None else np.ascontiguousarray(np.asarray(x0, dtype=np.int64))
+        self.n, self.nbins, self.keep = n, nbins, keep_probabilities
+        o = BatchOpts(nbins, int(bool(keep_probabilities)), int(tiled_variant), int(bool(no_graph)))
+        h = ctypes.c_void_p()
+        _bcheck(lib.walk_batch_create(n, self.N.ctypes.data, self.T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
+                                      None if xa is None else xa.ctypes.data, prec, ctypes.byref(o),
+                                      _stream_of(stream), ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        _bcheck(self._lib.walk_batch_run(self.h))
+
+    def moments(self) -> np.ndarray:
+        out = np.empty((self.n, 3), dtype=np.float64)
+        _bcheck(self._lib.walk_batch_moments(self.h, out.ctypes.data, 0))
+        return out
+
+    def binned(self, out=None):
+        if out is not None:
+            _bcheck(self._lib.walk_batch_binned(self.h, _ptr_of(out), 1))
+            return None
+        b = np.empty((self.n, self.nbins), dtype=np.float32)
+        _bcheck(self._lib.walk_batch_binned(self.h, b.ctypes.data, 0))
+        return b
+
+    def probabilities(self) -> list:
+        flat = np.empty(int(self.N.sum()), dtype=np.float64)
+        _bcheck(self._lib.walk_batch_probabilities(self.h, flat.ctypes.data, 0))
+        return np.split(flat, np.cumsum(self.N)[:-1])
+
+    def info(self) -> BatchInfo:
+        i = BatchInfo()
+        _bcheck(self._lib.walk_batch_info(self.h, ctypes.byref(i)))
+        return i
+
+    def tune(self, samples: int = 8, save: bool = False):
+        _bcheck(self._lib.walk_batch_tune(self.h, int(samples), int(bool(save))))
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            rc = self._lib.walk_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            _bcheck(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

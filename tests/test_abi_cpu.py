@@ -151,3 +151,29 @@ def test_ext_buffers_checked(lib):
                                ctypes.byref(h)) == qwalk.QW_EINVAL
     assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None,
                                ctypes.c_void_p(4096 + 8), ctypes.c_void_p(8192), ctypes.byref(h)) == qwalk.QW_EINVAL
+
+
+def _batch_create(lib, N, T, angles, psi0, nbins=0, prec=qwalk.QW_C64):
+    N = np.ascontiguousarray(N, dtype=np.int64)
+    T = np.ascontiguousarray(T, dtype=np.int64)
+    a = np.ascontiguousarray(angles, dtype=np.float64)
+    p = np.ascontiguousarray(psi0, dtype=np.complex128)
+    o = qwalk.BatchOpts(nbins, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.walk_batch_create(N.size, N.ctypes.data, T.ctypes.data, a.ctypes.data, p.ctypes.data, None, prec,
+                               ctypes.byref(o), None, ctypes.byref(h))
+    return rc, lib.walk_batch_last_error().decode()
+
+
+def test_batch_validation(lib):
+    ok_a = [[0.3, 0.1, 0.2]]
+    ok_p = [inputs.PSI0_LR]
+    assert _batch_create(lib, [0], [5], ok_a, ok_p)[0] == qwalk.QW_EINVAL          # N < 1
+    assert _batch_create(lib, [11], [-1], ok_a, ok_p)[0] == qwalk.QW_EINVAL        # T < 0
+    assert _batch_create(lib, [11], [5], [[np.nan, 0, 0]], ok_p)[0] == qwalk.QW_EINVAL
+    assert _batch_create(lib, [11], [5], ok_a, [[1.0, 0.1]])[0] == qwalk.QW_ENOTNORM
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, nbins=3)[0] == qwalk.QW_EINVAL  # odd bins
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, nbins=4096)[0] == qwalk.QW_EINVAL
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, prec=9)[0] == qwalk.QW_EINVAL
+    assert lib.walk_batch_run(None) == qwalk.QW_EINVAL
+    assert lib.walk_batch_destroy(None) == qwalk.QW_OK

@@ -1,0 +1,127 @@
+"""Parity of the batched persistent launch (walk_batch_*) with the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_3779_amd import inputs, qwalk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    qwalk.load()
+    yield
+
+
+def _oracle_P(N, T, ang, psi0, x0):
+    C = oracle.coin(oracle.SU2, 2, *ang)
+    return oracle.prob(oracle.walk(int(N), 1, inputs.RING, C, (int(x0), 0), psi0, int(T)))[0]
+
+
+def _mixed(seed, n_extra=0):
+    rng = np.random.default_rng(seed)
+    Ns = [1, 2, 3, 7, 100, 511, 512, 513, 2047, 4096, 4097, 4608, 4609, 6000, 9001, 20001, 31337]
+    Ns += list(rng.integers(1000, 60000, size=n_extra))
+    N = np.array(Ns, dtype=np.int64)
+    T = np.array([int(rng.integers(0, max(1, min(k, 900)))) for k in N], dtype=np.int64)
+    T[0], T[5] = 0, 1
+    ang = inputs.su2_angles(rng, N.size)
+    psi0 = np.stack([inputs.haar_state(rng, 2) for _ in range(N.size)])
+    x0 = np.array([int(rng.integers(0, k)) for k in N], dtype=np.int64)
+    return N, T, ang, psi0, x0
+
+
+def _check_walks(b, N, T, ang, psi0, x0, tolP, nbins):
+    Ps = b.probabilities()
+    mom = b.moments()
+    bins = b.binned() if nbins else None
+    for i in range(N.size):
+        ref = _oracle_P(N[i], T[i], ang[i], psi0[i], x0[i])
+        assert np.max(np.abs(Ps[i] - ref)) <= tolP, (i, N[i], T[i])
+        dx = (np.arange(N[i]) - x0[i]) % N[i]
+        dx = np.where(dx > N[i] // 2, dx - N[i], dx).astype(np.float64)
+        want = np.array([ref.sum(), (ref * dx).sum(), (ref * dx * dx).sum()])
+        scale = np.array([1.0, max(1.0, N[i]), max(1.0, N[i] ** 2)])
+        assert np.all(np.abs(mom[i] - want) <= 10 * tolP * scale), (i, mom[i], want)
+        if nbins and (N[i] - 1) // 2 >= nbins // 2:
+            bref = oracle.bin_ring(ref, x0[i], nbins)
+            assert np.max(np.abs(bins[i] - bref)) <= tolP + 1e-6, i
+
+
+@pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_batch_mixed_sizes(prec, tol, variant):
+    N, T, ang, psi0, x0 = _mixed(11 + variant)
+    b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True, tiled_variant=variant)
+    b.run()
+    _check_walks(b, N, T, ang, psi0, x0, tol, 64)
+    info = b.info()
+    assert info.n == N.size and info.whole_ring_walks >= 9
+    b.destroy()
+
+
+def test_batch_variants_and_graph_replay_bitwise():
+    N, T, ang, psi0, x0 = _mixed(5, n_extra=20)
+    ref = None
+    for variant, no_graph in ((1, True), (2, False), (3, False), (4, False), (0, False)):
+        b = qwalk.Batch(N, T, ang, psi0, x0, prec=qwalk.QW_C64, nbins=32, keep_probabilities=True,
+                        tiled_variant=variant, no_graph=no_graph)
+        for rep in range(3):
+            b.run()
+            got = (np.concatenate(b.probabilities()), b.moments(), b.binned())
+            if ref is None:
+                ref = got
+            for g, r in zip(got, ref):
+                assert np.array_equal(g, r), (variant, rep)
+        assert b.info().graph == (0 if no_graph else 1)
+        b.destroy()
+
+
+def test_batch_autotuner(tmp_path, monkeypatch):
+    monkeypatch.setenv("QWALK_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    rng = np.random.default_rng(3)
+    p = inputs.ragged_ring_batch(77, 48, nmin=1001, nmax=120001)
+    b = qwalk.Batch(p["N"], p["T"], p["angles"], p["psi0"], prec=qwalk.QW_C64, nbins=16)
+    b.run()
+    before = b.moments()
+    b.tune(samples=4, save=True)
+    info = b.info()
+    for k in range(3):
+        assert 0 <= info.bucket_cfg[k] < 4
+        assert info.bucket_tile_sites[k] in (256, 512) and info.bucket_depth[k] in (8, 16)
+    b.run()
+    assert np.array_equal(b.moments(), before)      # every variant is the same arithmetic
+    assert (tmp_path / "tune.txt").exists()
+    b.destroy()
+    # a new batch on the same device picks the saved choice up
+    b2 = qwalk.Batch(p["N"], p["T"], p["angles"], p["psi0"], prec=qwalk.QW_C64)
+    assert list(b2.info().bucket_cfg) == list(info.bucket_cfg)
+    b2.destroy()
+
+
+def test_batch_ragged_rings_c64():
+    """256 ragged rings (N odd in [1001, 99999], T in [256, N/2], SU(2), Haar start):
+    norm and the second-moment limit for every walk; the oracle on every walk with N < 1e4."""
+    p = inputs.ragged_ring_batch(4, 256, nmin=1001, nmax=99999)
+    N, T = p["N"], p["T"]
+    b = qwalk.Batch(N, T, p["angles"], p["psi0"], prec=qwalk.QW_C64, keep_probabilities=True)
+    b.run()
+    mom = b.moments()
+    assert np.max(np.abs(mom[:, 0] - 1.0)) <= 1e-4
+    lim = 1.0 - np.abs(np.sin(p["angles"][:, 0]))
+    m2 = mom[:, 2] / T.astype(np.float64) ** 2
+    assert np.max(np.abs(m2 - lim)) <= 2e-2
+    Ps = b.probabilities()
+    small = np.nonzero(N < 10000)[0]
+    assert small.size >= 3
+    for i in small:
+        ref = _oracle_P(N[i], T[i], p["angles"][i], p["psi0"][i], N[i] // 2)
+        assert np.max(np.abs(Ps[i] - ref)) <= 2e-5
+    b.destroy()
