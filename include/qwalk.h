@@ -229,6 +229,11 @@ typedef struct {
                                     (cache) or default; 1..4 = force (tile sites, steps per
                                     block) = (256, 8), (256, 16), (512, 8), (512, 16) */
     int32_t no_graph;            /* 1: launch directly instead of replaying a hipGraph */
+    int32_t renorm_every;        /* fp64 norm check (rescale by 1/sqrt(n) when |n - 1| > 1e-7):
+                                    0 = default (every 64 steps in QW_C64, never in QW_C128),
+                                    > 0 = every so many steps (rings held whole; longer rings
+                                    check after every K-step block), < 0 = never */
+    int32_t reserved;
 } qw_batch_opts;
 
 typedef struct {

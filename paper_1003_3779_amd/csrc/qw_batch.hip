@@ -62,7 +62,19 @@ struct BatchArgs {
     double *moments;        // n x 3
     float *bins;            // n x nbins (or null)
     double *P;              // full distributions (or null)
+    int32_t renorm_every;   // whole rings: steps between fp64 norm checks (0 = never); tiled rings
+                            // check after every K-step block when non-zero
+    double renorm_tol;      // rescale by 1/sqrt(n) when |n - 1| > renorm_tol
 };
+
+// fp64 norm of per-wave partial sums: lane 0 of each wave has written its sum
+// into part[wave]; after the barrier every thread adds them in wave order.
+__device__ __forceinline__ double sum_waves(const double *part) {
+    double n = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) n += part[i];
+    return n;
+}
 
 template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, Coin2<R> &cn) {
     cn.c00r = (R)w.cre[0]; cn.c00i = (R)w.cim[0];
@@ -150,7 +162,7 @@ template <typename R> __device__ __forceinline__ double abs2d(cv<R> v) {
 // ---------------------------------------------------------------- whole ring
 template <typename R, int M>
 __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A, cv<R> (*L0)[kBT], cv<R> (*L1)[kBT],
-                           double *s_bins, SiteAcc &acc) {
+                           double *s_bins, double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
     const int j = threadIdx.x;
     const int nl = (N + M - 1) / M;
@@ -172,8 +184,29 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
         if (m < cnt && x == p1) { a1[m].x = (R)w.pre[1]; a1[m].y = (R)w.pim[1]; }
     }
     // T steps, then one more exchange round for P (parity continues)
+    int npar = 0;
     for (int s = 0; s <= w.T; ++s) {
         const int p = s & 1;
+        if (A.renorm_every > 0 && s > 0 && s < w.T && s % A.renorm_every == 0) {
+            // fp64 norm of the ring (the state is a permutation of psi), fixed order
+            double part = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (m < cnt) part += abs2d<R>(a0[m]) + abs2d<R>(a1[m]);
+            part = wave_sum64(part);
+            if ((threadIdx.x & 63) == 0) s_norm[npar][threadIdx.x >> 6] = part;
+            __syncthreads();
+            const double nrm = sum_waves(s_norm[npar]);
+            npar ^= 1;
+            if (fabs(nrm - 1.0) > A.renorm_tol) {
+                const R sc = (R)(1.0 / sqrt(nrm));
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    a0[m] = cscale<R>(a0[m], sc);
+                    a1[m] = cscale<R>(a1[m], sc);
+                }
+            }
+        }
         if (active) {
             cv<R> last = a0[0];
 #pragma unroll
@@ -216,20 +249,21 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
 // one step of one site range [o, o + n) of the output box, straight from memory
 template <typename R>
 __device__ __forceinline__ void one_step_range(const cv<R> *in0, const cv<R> *in1, cv<R> *out0, cv<R> *out1,
-                                               int N, int start, int width, const Coin2<R> &cn) {
+                                               int N, int start, int width, const Coin2<R> &cn, R sc) {
     for (int i = threadIdx.x; i < width; i += kBT) {
         int x = start + i;
         x = x >= N ? x - N : x;
         const int xl = x == 0 ? N - 1 : x - 1, xr = x + 1 == N ? 0 : x + 1;
         cv<R> o0, o1;
-        cn.apply(in0[xl], in1[xr], o0, o1);
+        cn.apply(cscale<R>(in0[xl], sc), cscale<R>(in1[xr], sc), o0, o1);
         out0[x] = o0;
         out1[x] = o1;
     }
 }
 
 template <typename R, int MT, int K>
-__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, double *s_bins, SiteAcc &acc) {
+__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, double *s_bins,
+                                           double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
     const int64_t se = A.slot_elems;
     cv<R> *const base = (cv<R> *)A.slots + (int64_t)blockIdx.x * 4 * se;  // [buffer][plane][site]
@@ -263,6 +297,9 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int TW = 64 * MT - 2 * K;
     int t = 0;
+    int npar = 0;
+    R sc = (R)1;  // pending renormalisation of the current buffer, applied as it is read
+    double nacc = 0.0;
     while (t < w.T) {
         const int k = (w.T - t) >= K ? K : 1;
         half += k;
@@ -279,8 +316,8 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                 for (int m = 0; m < MT; ++m) {
                     int x = tb + m;
                     x = x >= N ? x - N : x;
-                    a0[m] = i0[x];
-                    a1[m] = i1[x];
+                    a0[m] = cscale<R>(i0[x], sc);
+                    a1[m] = cscale<R>(i1[x], sc);
                 }
                 ring_tile_steps<R, MT, K>(a0, a1, cn);
 #pragma unroll
@@ -291,13 +328,27 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                         x = x >= N ? x - N : x;
                         o0[x] = a0[m];
                         o1[x] = a1[m];
+                        if (A.renorm_every > 0) nacc += abs2d<R>(a0[m]) + abs2d<R>(a1[m]);
                     }
                 }
             }
         } else {
-            one_step_range<R>(i0, i1, o0, o1, N, start, width, cn);
+            one_step_range<R>(i0, i1, o0, o1, N, start, width, cn, sc);
+            sc = (R)1;
         }
-        __syncthreads();
+        if (A.renorm_every > 0 && k == K) {
+            // fp64 norm of the block's output, in fixed wave order; the rescale
+            // (if any) is applied by the next reads of this buffer
+            const double part = wave_sum64(nacc);
+            if (lane == 0) s_norm[npar][wave] = part;
+            __syncthreads();
+            const double nrm = sum_waves(s_norm[npar]);
+            npar ^= 1;
+            sc = fabs(nrm - 1.0) > A.renorm_tol ? (R)(1.0 / sqrt(nrm)) : (R)1;
+        } else {
+            __syncthreads();
+        }
+        nacc = 0.0;
         cur ^= 1;
         t += k;
     }
@@ -310,7 +361,7 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
         int x = ps + i;
         x = x >= N ? x - N : x;
         const int xl = x == 0 ? N - 1 : x - 1, xr = x + 1 == N ? 0 : x + 1;
-        const double pr = abs2d<R>(a0[xl]) + abs2d<R>(a1[xr]);
+        const double pr = abs2d<R>(cscale<R>(a0[xl], sc)) + abs2d<R>(cscale<R>(a1[xr], sc));
         acc.add(pr, ring_offset(x, w.x0, N), N, A.nbins, s_bins);
         if (A.P) A.P[w.p_off + x] = pr;
     }
@@ -349,6 +400,7 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
     __shared__ cv<R> L1[2][kBT];
     __shared__ double s_bins[kMaxBins];
     __shared__ double s_red[3][kWaves];
+    __shared__ double s_norm[2][kWaves];
     for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0.0;
     for (;;) {
         if (threadIdx.x == 0) s_q = (int)atomicAdd(&A.queue[0], 1u);
@@ -360,10 +412,10 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         const WalkDesc w = A.walks[wi];
         SiteAcc acc;
         switch (w.cfg) {
-        case 0: walk_tiled<R, kCfgMT[0], kCfgK[0]>(w, A, s_bins, acc); break;
-        case 1: walk_tiled<R, kCfgMT[1], kCfgK[1]>(w, A, s_bins, acc); break;
-        case 2: walk_tiled<R, kCfgMT[2], kCfgK[2]>(w, A, s_bins, acc); break;
-        default: walk_tiled<R, kCfgMT[3], kCfgK[3]>(w, A, s_bins, acc); break;
+        case 0: walk_tiled<R, kCfgMT[0], kCfgK[0]>(w, A, s_bins, s_norm, acc); break;
+        case 1: walk_tiled<R, kCfgMT[1], kCfgK[1]>(w, A, s_bins, s_norm, acc); break;
+        case 2: walk_tiled<R, kCfgMT[2], kCfgK[2]>(w, A, s_bins, s_norm, acc); break;
+        default: walk_tiled<R, kCfgMT[3], kCfgK[3]>(w, A, s_bins, s_norm, acc); break;
         }
         finish_walk<R>(A, wi, acc, s_bins, s_red);
     }
@@ -378,7 +430,7 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         SiteAcc acc;
         switch (w.m) {
 #define QW_WHOLE_CASE(MM) \
-        case MM: if (MM <= MMAX) walk_whole<R, (MM <= MMAX ? MM : 1)>(w, A, L0, L1, s_bins, acc); break;
+        case MM: if (MM <= MMAX) walk_whole<R, (MM <= MMAX ? MM : 1)>(w, A, L0, L1, s_bins, s_norm, acc); break;
         QW_WHOLE_CASE(1) QW_WHOLE_CASE(2) QW_WHOLE_CASE(3) QW_WHOLE_CASE(4)
         QW_WHOLE_CASE(5) QW_WHOLE_CASE(6) QW_WHOLE_CASE(7) QW_WHOLE_CASE(8)
         QW_WHOLE_CASE(9) QW_WHOLE_CASE(10) QW_WHOLE_CASE(11) QW_WHOLE_CASE(12)
@@ -496,6 +548,8 @@ struct qw_batch {
     std::vector<int64_t> p_off;
     int64_t total_sites = 0;
     int64_t n_tiled = 0;
+    int32_t renorm_every = 0;
+    double renorm_tol = 1e-7;
     WalkDesc *d_walks = nullptr;
     int32_t *d_order = nullptr;
     unsigned int *d_queue = nullptr;
@@ -545,6 +599,8 @@ BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, in
     A.moments = b->d_moments;
     A.bins = b->d_bins;
     A.P = b->keep ? b->d_P : nullptr;
+    A.renorm_every = b->renorm_every;
+    A.renorm_tol = b->renorm_tol;
     return A;
 }
 
@@ -613,6 +669,7 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
     b->keep = o.keep_probabilities != 0;
     b->use_graph = o.no_graph == 0;
     b->stream = (hipStream_t)stream;
+    b->renorm_every = o.renorm_every > 0 ? o.renorm_every : (o.renorm_every < 0 ? 0 : (prec == QW_C64 ? 64 : 0));
     const int mmax = prec == QW_C128 ? kMaxMC128 : kMaxMC64;
     b->walks.resize(n);
     b->p_off.resize(n);

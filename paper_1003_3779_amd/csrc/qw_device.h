@@ -112,20 +112,43 @@ __device__ __forceinline__ int wrapi(int v, int L) {
 
 // ---- cross-lane moves of one complex value within a wave64 ----
 // from_left: lane i receives lane i-1's value; from_right: lane i receives
-// lane i+1's value.  The edge lanes receive their own value (they are halo).
+// lane i+1's value.  The edge lanes keep their own value (they are halo).
+// DPP wave shifts (wave_shr:1 = 0x138, wave_shl:1 = 0x130) move 32-bit words
+// without going through LDS; every lane of the wave must be active.
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float lane_from_left(float v) {
+    return __builtin_bit_cast(float, dpp_from_left(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    return __builtin_bit_cast(float, dpp_from_right(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_from_left((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_from_left((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_from_right((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_from_right((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <typename R> __device__ __forceinline__ cv<R> from_left(cv<R> v) {
     cv<R> r;
-    r.x = __shfl_up(v.x, 1, 64);
-    r.y = __shfl_up(v.y, 1, 64);
+    r.x = lane_from_left(v.x);
+    r.y = lane_from_left(v.y);
     return r;
 }
 template <typename R> __device__ __forceinline__ cv<R> from_right(cv<R> v) {
     cv<R> r;
-    r.x = __shfl_down(v.x, 1, 64);
-    r.y = __shfl_down(v.y, 1, 64);
+    r.x = lane_from_right(v.x);
+    r.y = lane_from_right(v.y);
     return r;
 }
-
 
 // The coin of a ring (d = 2) applied to the two gathered values g0 = a(x-1, 0),
 // g1 = a(x+1, 1): out0 = C00 g0 + C01 g1, out1 = C10 g0 + C11 g1.

@@ -66,7 +66,8 @@ class KernelProfile(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int32), ("keep_probabilities", ctypes.c_int32),
-                ("tiled_variant", ctypes.c_int32), ("no_graph", ctypes.c_int32)]
+                ("tiled_variant", ctypes.c_int32), ("no_graph", ctypes.c_int32),
+                ("renorm_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -331,7 +332,7 @@ class Batch:
 
     def __init__(self, N, T, angles, psi0, x0=None, prec: int = QW_C64, nbins: int = 0,
                  keep_probabilities: bool = False, tiled_variant: int = 0, no_graph: bool = False,
-                 stream=None):
+                 renorm_every: int = 0, stream=None):
         lib = load()
         self._lib = lib
         self.N = np.ascontiguousarray(np.asarray(N, dtype=np.int64))
@@ -341,7 +342,8 @@ class Batch:
         p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128).reshape(n, 2))
         xa = None if x0 is None else np.ascontiguousarray(np.asarray(x0, dtype=np.int64))
         self.n, self.nbins, self.keep = n, nbins, keep_probabilities
-        o = BatchOpts(nbins, int(bool(keep_probabilities)), int(tiled_variant), int(bool(no_graph)))
+        o = BatchOpts(nbins, int(bool(keep_probabilities)), int(tiled_variant), int(bool(no_graph)),
+                      int(renorm_every), 0)
         h = ctypes.c_void_p()
         _bcheck(lib.walk_batch_create(n, self.N.ctypes.data, self.T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
                                       None if xa is None else xa.ctypes.data, prec, ctypes.byref(o),

@@ -158,7 +158,7 @@ def _batch_create(lib, N, T, angles, psi0, nbins=0, prec=qwalk.QW_C64):
     T = np.ascontiguousarray(T, dtype=np.int64)
     a = np.ascontiguousarray(angles, dtype=np.float64)
     p = np.ascontiguousarray(psi0, dtype=np.complex128)
-    o = qwalk.BatchOpts(nbins, 0, 0, 0)
+    o = qwalk.BatchOpts(nbins, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     rc = lib.walk_batch_create(N.size, N.ctypes.data, T.ctypes.data, a.ctypes.data, p.ctypes.data, None, prec,
                                ctypes.byref(o), None, ctypes.byref(h))
