@@ -251,19 +251,23 @@ template <typename R, int K, int M> struct StreamRegs {
 };
 
 template <typename R, int K, int M, int TABLE, int COIN, int PH>
-__device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, const cv<R> *__restrict__ in,
+__device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)[4][M], const cv<R> *__restrict__ in,
                                             cv<R> *__restrict__ out, const Geom &g, const int (&xcol)[M],
-                                            const bool (&store_col)[M], int row_in, int row_out,
+                                            const bool (&store_col)[M], int row_next, int row_out,
                                             bool do_store, const CoinR<R> &C) {
     // slot PH receives the newest row, slot (PH+2)%3 holds the row before it
     // (the row being computed at the next level), slot (PH+1)%3 the oldest.
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
+    // this iteration's input row was loaded one iteration ago; the next one is
+    // requested now so that its HBM latency overlaps the K levels below
     cv<R> cur[4][M];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            cur[c][m] = in[(int64_t)c * g.ps + (int64_t)row_in * g.Lx + xcol[m]];
+        for (int m = 0; m < M; ++m) {
+            cur[c][m] = pf[c][m];
+            pf[c][m] = in[(int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol[m]];
+        }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
 #pragma unroll
@@ -342,18 +346,24 @@ __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, 
     row_in = row_in < 0 ? row_in + g.Ly : row_in;
     int row_out = (b.y0 + r0 - 2 * K) % g.Ly;  // advanced in step with row_in
     row_out = row_out < 0 ? row_out + g.Ly : row_out;
+    cv<R> pf[4][M];  // the next input row, loaded one iteration ahead
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int m = 0; m < M; ++m) pf[c][m] = in[(int64_t)c * g.ps + (int64_t)row_in * g.Lx + xcol[m]];
+    // (rows past the segment end are loaded too -- in bounds, modulo Ly -- and never used)
     for (int i = 0; i < niter; i += 3) {
-        stream_iter<R, K, M, TABLE, COIN, 0>(st, in, out, g, xcol, store_col, row_in, row_out,
+        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        stream_iter<R, K, M, TABLE, COIN, 0>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
                                              i >= 2 * K && i < niter, C);
-        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
-        stream_iter<R, K, M, TABLE, COIN, 1>(st, in, out, g, xcol, store_col, row_in, row_out,
+        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        stream_iter<R, K, M, TABLE, COIN, 1>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
                                              i + 1 >= 2 * K && i + 1 < niter, C);
-        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
-        stream_iter<R, K, M, TABLE, COIN, 2>(st, in, out, g, xcol, store_col, row_in, row_out,
-                                             i + 2 >= 2 * K && i + 2 < niter, C);
         row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
+        stream_iter<R, K, M, TABLE, COIN, 2>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
+                                             i + 2 >= 2 * K && i + 2 < niter, C);
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
     }
 }
