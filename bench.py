@@ -40,7 +40,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grover2d", choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d"])
+    ap.add_argument("--workload", default="grover2d",
+                    choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d", "ragged_rings"])
+    ap.add_argument("--rings", type=int, default=4096, help="ragged_rings: number of rings")
+    ap.add_argument("--nmax", type=int, default=999999, help="ragged_rings: largest ring")
+    ap.add_argument("--tune", action="store_true", help="ragged_rings: run the autotuner first")
     ap.add_argument("--prec", default=None, choices=["c128", "c64"])
     ap.add_argument("--depth", type=int, default=0, help="steps per launch (0 = library default)")
     ap.add_argument("--cpu-sample-steps", type=int, default=900)
@@ -70,6 +74,50 @@ def copy_reference(nbytes: int):
     ms = e0.elapsed_time(e1) / reps
     print(json.dumps({"copy_bytes": n * 16, "ms": ms, "GBps_read_plus_write": 2 * n * 16 / (ms * 1e-3) / 1e9}),
           flush=True)
+
+
+def ragged_rings(args):
+    """Independent rings, N odd uniform in [1001, nmax], T uniform in [256, N/2],
+    SU(2) coins with theta ~ U(0, pi), phi, chi ~ U(0, 2 pi), Haar start coin
+    states (PCG64 seed 4), complex64, one persistent launch per run."""
+    import numpy as np
+    import torch
+
+    from paper_1003_3779_amd import inputs, qwalk
+    p = inputs.ragged_ring_batch(4, args.rings, nmin=1001, nmax=args.nmax)
+    b = qwalk.Batch(p["N"], p["T"], p["angles"], p["psi0"], prec=qwalk.QW_C64, nbins=512)
+    if args.tune:
+        b.tune(samples=8, save=True)
+    for _ in range(args.warmup):
+        b.run()
+        b.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = []
+    for _ in range(args.steps):
+        b.run()
+        ms.append(b.info().last_run_ms)
+    t1 = time.perf_counter()
+    info = b.info()
+    mom = b.moments()
+    lim = 1.0 - np.abs(np.sin(p["angles"][:, 0]))
+    m2 = mom[:, 2] / p["T"].astype(np.float64) ** 2
+    out = {
+        "metric": METRIC, "value": info.est_updates * args.steps / (t1 - t0), "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ragged_rings: {args.rings} rings, N odd in [1001, {args.nmax}], "
+                               f"T in [256, N/2], SU(2), c64", "parallelism": "single GPU"},
+        "walks_per_s": args.rings * args.steps / (t1 - t0),
+        "kernel_ms": ms, "grid": info.grid, "whole_ring_walks": info.whole_ring_walks,
+        "tiled_variant_per_bucket": [[info.bucket_tile_sites[k], info.bucket_depth[k]] for k in range(3)],
+        "est_updates_per_run": info.est_updates,
+        "norm_error_max": float(np.max(np.abs(mom[:, 0] - 1.0))),
+        "second_moment_vs_limit_max": float(np.max(np.abs(m2 - lim))),
+    }
+    b.destroy()
+    print(json.dumps(out), flush=True)
 
 
 def traffic_from_profile(kernel_sha: str):
@@ -117,6 +165,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_ref:
         copy_reference(args.copy_ref)
+        return
+    if args.workload == "ragged_rings":
+        ragged_rings(args)
         return
     cfg = inputs.config(args.workload)
     prec_name = args.prec or cfg["prec"]

@@ -38,16 +38,17 @@ namespace {
 constexpr int kBT = 512;          // threads per batch workgroup
 constexpr int kWaves = kBT / 64;
 constexpr int kMaxBins = 1024;
-constexpr int kNumCfg = 4;        // tiled-path variants (MT, K)
-constexpr int kCfgMT[kNumCfg] = {4, 4, 8, 8};
-constexpr int kCfgK[kNumCfg] = {8, 16, 8, 16};
+constexpr int kNumCfg = 4;        // tiled-path variants (sites per lane MT, steps per block K)
+constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16};
+constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64};
 
 struct WalkDesc {
     int32_t N, T, x0, cfg;  // cfg < 0: whole-ring path with m sites per thread; else tiled variant
-    int32_t m, pad;
+    int32_t m, rot;         // rot = 1: the walk runs in the rotation frame (see walk_batch_create)
     int64_t p_off;          // offset of this walk's P in the full-distribution output
-    double cre[4], cim[4];  // coin, row-major
-    double pre[2], pim[2];  // start coin state
+    double rc, rs;          // rotation coin [[rc, rs], [-rs, rc]] (rot = 1)
+    double cre[4], cim[4];  // SU(2) coin, row-major (rot = 0)
+    double pre[2], pim[2];  // start coin state (in the rotation frame when rot = 1)
 };
 
 struct BatchArgs {
@@ -76,6 +77,10 @@ __device__ __forceinline__ double sum_waves(const double *part) {
     return n;
 }
 
+template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, CoinRot<R> &cn) {
+    cn.c = (R)w.rc;
+    cn.s = (R)w.rs;
+}
 template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, Coin2<R> &cn) {
     cn.c00r = (R)w.cre[0]; cn.c00i = (R)w.cim[0];
     cn.c01r = (R)w.cre[1]; cn.c01i = (R)w.cim[1];
@@ -160,7 +165,7 @@ template <typename R> __device__ __forceinline__ double abs2d(cv<R> v) {
 }
 
 // ---------------------------------------------------------------- whole ring
-template <typename R, int M>
+template <typename R, int M, typename CN>
 __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A, cv<R> (*L0)[kBT], cv<R> (*L1)[kBT],
                            double *s_bins, double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
@@ -170,7 +175,7 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
     const int cnt = active ? min(M, N - j * M) : 0;
     const int jl = j == 0 ? nl - 1 : j - 1;
     const int jr = j + 1 >= nl ? 0 : j + 1;
-    Coin2<R> cn;
+    CN cn;
     load_coin<R>(w, cn);
     // a_0: component 0 at x0 - 1, component 1 at x0 + 1
     const int p0 = wrapN((int64_t)w.x0 - 1, N), p1 = wrapN((int64_t)w.x0 + 1, N);
@@ -246,28 +251,13 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
 }
 
 // ---------------------------------------------------------------- tiled ring
-// one step of one site range [o, o + n) of the output box, straight from memory
-template <typename R>
-__device__ __forceinline__ void one_step_range(const cv<R> *in0, const cv<R> *in1, cv<R> *out0, cv<R> *out1,
-                                               int N, int start, int width, const Coin2<R> &cn, R sc) {
-    for (int i = threadIdx.x; i < width; i += kBT) {
-        int x = start + i;
-        x = x >= N ? x - N : x;
-        const int xl = x == 0 ? N - 1 : x - 1, xr = x + 1 == N ? 0 : x + 1;
-        cv<R> o0, o1;
-        cn.apply(cscale<R>(in0[xl], sc), cscale<R>(in1[xr], sc), o0, o1);
-        out0[x] = o0;
-        out1[x] = o1;
-    }
-}
-
-template <typename R, int MT, int K>
-__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, double *s_bins,
+template <typename R, int MT, typename CN>
+__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, const int K, double *s_bins,
                                            double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
     const int64_t se = A.slot_elems;
     cv<R> *const base = (cv<R> *)A.slots + (int64_t)blockIdx.x * 4 * se;  // [buffer][plane][site]
-    Coin2<R> cn;
+    CN cn;
     load_coin<R>(w, cn);
     // zero both buffers over the region the walk can reach (cone plus halo)
     const int64_t reach = (int64_t)w.T + K + 2;
@@ -295,22 +285,22 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     int cur = 0;
     int64_t half = 1;  // box half-width
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int TW = 64 * MT - 2 * K;
     int t = 0;
     int npar = 0;
     R sc = (R)1;  // pending renormalisation of the current buffer, applied as it is read
     double nacc = 0.0;
     while (t < w.T) {
-        const int k = (w.T - t) >= K ? K : 1;
+        const int k = (w.T - t) >= K ? K : w.T - t;  // the last block may be shorter
+        const int TW = 64 * MT - 2 * k;
         half += k;
         const int width = (int)std::min<int64_t>(N, 2 * half + 1);
         const int start = width == N ? 0 : wrapN((int64_t)w.x0 - half, N);
         const cv<R> *i0 = base + (int64_t)cur * 2 * se, *i1 = i0 + se;
         cv<R> *o0 = base + (int64_t)(cur ^ 1) * 2 * se, *o1 = o0 + se;
-        if (k == K) {
+        {
             const int ntiles = (width + TW - 1) / TW;
             for (int tile = wave; tile < ntiles; tile += kWaves) {
-                const int tb = wrapN((int64_t)start + (int64_t)tile * TW - K + lane * MT, N);
+                const int tb = wrapN((int64_t)start + (int64_t)tile * TW - k + lane * MT, N);
                 cv<R> a0[MT], a1[MT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
@@ -319,11 +309,11 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                     a0[m] = cscale<R>(i0[x], sc);
                     a1[m] = cscale<R>(i1[x], sc);
                 }
-                ring_tile_steps<R, MT, K>(a0, a1, cn);
+                ring_tile_steps_n<R, MT, CN>(a0, a1, cn, k);
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
                     const int q = lane * MT + m;
-                    if (q >= K && q < 64 * MT - K && tile * TW + q - K < width) {
+                    if (q >= k && q < 64 * MT - k && tile * TW + q - k < width) {
                         int x = tb + m;
                         x = x >= N ? x - N : x;
                         o0[x] = a0[m];
@@ -332,11 +322,8 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                     }
                 }
             }
-        } else {
-            one_step_range<R>(i0, i1, o0, o1, N, start, width, cn, sc);
-            sc = (R)1;
         }
-        if (A.renorm_every > 0 && k == K) {
+        if (A.renorm_every > 0) {
             // fp64 norm of the block's output, in fixed wave order; the rescale
             // (if any) is applied by the next reads of this buffer
             const double part = wave_sum64(nacc);
@@ -411,11 +398,14 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         const int wi = A.order[q];
         const WalkDesc w = A.walks[wi];
         SiteAcc acc;
-        switch (w.cfg) {
-        case 0: walk_tiled<R, kCfgMT[0], kCfgK[0]>(w, A, s_bins, s_norm, acc); break;
-        case 1: walk_tiled<R, kCfgMT[1], kCfgK[1]>(w, A, s_bins, s_norm, acc); break;
-        case 2: walk_tiled<R, kCfgMT[2], kCfgK[2]>(w, A, s_bins, s_norm, acc); break;
-        default: walk_tiled<R, kCfgMT[3], kCfgK[3]>(w, A, s_bins, s_norm, acc); break;
+        if (!w.rot) {
+            // a walk whose light cone wraps the ring: full SU(2) coin, one variant
+            walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
+        } else if (kCfgMT[w.cfg] == 8) {
+            walk_tiled<R, 8, CoinRot<R>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+        } else {
+            // 16 sites per lane in complex64; complex128 keeps 8 (register budget)
+            walk_tiled<R, (sizeof(R) == 8 ? 8 : 16), CoinRot<R>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         }
         finish_walk<R>(A, wi, acc, s_bins, s_red);
     }
@@ -429,8 +419,13 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         const WalkDesc w = A.walks[wi];
         SiteAcc acc;
         switch (w.m) {
-#define QW_WHOLE_CASE(MM) \
-        case MM: if (MM <= MMAX) walk_whole<R, (MM <= MMAX ? MM : 1)>(w, A, L0, L1, s_bins, s_norm, acc); break;
+#define QW_WHOLE_CASE(MM)                                                                                  \
+        case MM:                                                                                           \
+            if (MM <= MMAX) {                                                                              \
+                if (w.rot) walk_whole<R, (MM <= MMAX ? MM : 1), CoinRot<R>>(w, A, L0, L1, s_bins, s_norm, acc); \
+                else walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>>(w, A, L0, L1, s_bins, s_norm, acc);         \
+            }                                                                                              \
+            break;
         QW_WHOLE_CASE(1) QW_WHOLE_CASE(2) QW_WHOLE_CASE(3) QW_WHOLE_CASE(4)
         QW_WHOLE_CASE(5) QW_WHOLE_CASE(6) QW_WHOLE_CASE(7) QW_WHOLE_CASE(8)
         QW_WHOLE_CASE(9) QW_WHOLE_CASE(10) QW_WHOLE_CASE(11) QW_WHOLE_CASE(12)
@@ -701,14 +696,28 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         int64_t xs = x0 ? x0[i] : N[i] / 2;
         xs %= N[i];
         w.x0 = (int32_t)(xs < 0 ? xs + N[i] : xs);
-        // SU(2) coin [[e^{i phi} cos t, e^{i chi} sin t], [-e^{-i chi} sin t, e^{-i phi} cos t]]
+        // SU(2) coin C = [[e^{i phi} cos t, e^{i chi} sin t], [-e^{-i chi} sin t, e^{-i phi} cos t]].
+        // The outputs are P only, so the walk runs in an equivalent frame:
+        // the gauge (phi, chi) -> (0, chi - phi) (conjugation by a site phase
+        // e^{-i phi x}, which S turns into diag(e^{-i phi}, e^{i phi}) on the coin)
+        // and conjugation by D = diag(1, e^{i(chi - phi)}), which commutes with
+        // the shift, take C to the real rotation [[cos t, sin t], [-sin t, cos t]]
+        // and psi0 to D psi0 (up to a global phase); |psi_T(x, c)| is unchanged.
+        // The site phase is single-valued only while the light cone does not
+        // wrap the ring (2T < N); a wrapping walk keeps the coin as given.
         const double ct = cos(th), st = sin(th);
         w.cre[0] = cos(ph) * ct;  w.cim[0] = sin(ph) * ct;
         w.cre[1] = cos(ch) * st;  w.cim[1] = sin(ch) * st;
         w.cre[2] = -cos(ch) * st; w.cim[2] = sin(ch) * st;
         w.cre[3] = cos(ph) * ct;  w.cim[3] = -sin(ph) * ct;
-        w.pre[0] = psi0[4 * i];     w.pim[0] = psi0[4 * i + 1];
-        w.pre[1] = psi0[4 * i + 2]; w.pim[1] = psi0[4 * i + 3];
+        w.rc = ct;
+        w.rs = st;
+        w.rot = 2 * T[i] < N[i] ? 1 : 0;
+        const double dphi = w.rot ? ch - ph : 0.0, cd = cos(dphi), sd = sin(dphi);
+        w.pre[0] = psi0[4 * i];
+        w.pim[0] = psi0[4 * i + 1];
+        w.pre[1] = cd * psi0[4 * i + 2] - sd * psi0[4 * i + 3];
+        w.pim[1] = sd * psi0[4 * i + 2] + cd * psi0[4 * i + 3];
         const int64_t m = (N[i] + kBT - 1) / kBT;
         if (m <= mmax) {
             w.cfg = -1;
@@ -881,7 +890,7 @@ int walk_batch_info(qw_batch_t b, qw_batch_info *out) {
     out->last_run_ms = ms;
     for (int k = 0; k < 3; ++k) {
         out->bucket_cfg[k] = b->bucket_cfg[k];
-        out->bucket_tile_sites[k] = 64 * kCfgMT[b->bucket_cfg[k]];
+        out->bucket_tile_sites[k] = 64 * (b->prec == QW_C128 ? 8 : kCfgMT[b->bucket_cfg[k]]);
         out->bucket_depth[k] = kCfgK[b->bucket_cfg[k]];
     }
     return QW_OK;

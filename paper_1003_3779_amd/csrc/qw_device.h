@@ -164,16 +164,47 @@ template <typename R> struct Coin2 {
     }
 };
 
+// A real rotation coin [[c, s], [-s, c]]: out0 = c g0 + s g1, out1 = -s g0 + c g1
+// (two real-times-complex products per output instead of two complex ones).
+template <typename R> struct CoinRot {
+    R c, s;
+    __device__ __forceinline__ void apply(cv<R> g0, cv<R> g1, cv<R> &o0, cv<R> &o1) const {
+        o0.x = fmaR(c, g0.x, s * g1.x);
+        o0.y = fmaR(c, g0.y, s * g1.y);
+        o1.x = fmaR(c, g1.x, -(s * g0.x));
+        o1.y = fmaR(c, g1.y, -(s * g0.y));
+    }
+};
+
 // K steps of a ring tile held by one wave: lane l holds sites l*M .. l*M+M-1
 // of both planes; the value a lane needs from its neighbour moves one lane per
-// step.  After K steps the sites K .. 64M-K-1 are exact.
-template <typename R, int M, int K>
-__device__ __forceinline__ void ring_tile_steps(cv<R> (&a0)[M], cv<R> (&a1)[M], const Coin2<R> &cn) {
+// step.  After K steps the sites K .. 64M-K-1 are exact.  CN: Coin2 or CoinRot.
+template <typename R, int M, int K, typename CN>
+__device__ __forceinline__ void ring_tile_steps(cv<R> (&a0)[M], cv<R> (&a1)[M], const CN &cn) {
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         const cv<R> left = from_left<R>(a0[M - 1]);
         const cv<R> right = from_right<R>(a1[0]);
         // in place, ascending m: a0[m-1] is carried, a1[m+1] is still old
+        cv<R> prev = left;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const cv<R> g0 = prev;
+            const cv<R> g1 = m == M - 1 ? right : a1[m == M - 1 ? m : m + 1];
+            prev = a0[m];
+            cn.apply(g0, g1, a0[m], a1[m]);
+        }
+    }
+}
+
+// As ring_tile_steps with a run-time step count k (the step loop is not
+// unrolled, so deep blocks cost no code size); sites k .. 64M-k-1 are exact.
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void ring_tile_steps_n(cv<R> (&a0)[M], cv<R> (&a1)[M], const CN &cn, int k) {
+#pragma unroll 2
+    for (int s = 0; s < k; ++s) {
+        const cv<R> left = from_left<R>(a0[M - 1]);
+        const cv<R> right = from_right<R>(a1[0]);
         cv<R> prev = left;
 #pragma unroll
         for (int m = 0; m < M; ++m) {

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_ring_tiles(const cv<R> *__restrict__ in
     }
     Coin2<R> cn;
     cn.load(C);
-    ring_tile_steps<R, M, K>(a0, a1, cn);
+    ring_tile_steps<R, M, K, Coin2<R>>(a0, a1, cn);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int q = lane * M + m;

@@ -95,7 +95,7 @@ def test_batch_autotuner(tmp_path, monkeypatch):
     info = b.info()
     for k in range(3):
         assert 0 <= info.bucket_cfg[k] < 4
-        assert info.bucket_tile_sites[k] in (256, 512) and info.bucket_depth[k] in (8, 16)
+        assert info.bucket_tile_sites[k] in (512, 1024) and info.bucket_depth[k] in (16, 32, 64)
     b.run()
     assert np.array_equal(b.moments(), before)      # every variant is the same arithmetic
     assert (tmp_path / "tune.txt").exists()

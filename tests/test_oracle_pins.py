@@ -319,6 +319,26 @@ def test_su2_gauge_invariance():
     assert np.max(np.abs(P1 - P3)) > 1e-4
 
 
+def test_su2_reduces_to_real_rotation():
+    """For P alone, the SU(2) walk C(theta, phi, chi) from psi0 equals the walk with
+    the real rotation [[cos t, sin t], [-sin t, cos t]] from (psi0_0, e^{i(chi-phi)} psi0_1):
+    the gauge (phi, chi) -> (phi - phi, chi - phi) plus conjugation by diag(1, e^{i(chi-phi)}),
+    which commutes with the shift.  (Used by the batched walks, whose outputs are P only.)"""
+    rng = np.random.default_rng(31)
+    for th, ph, ch in inputs.su2_angles(rng, 6):
+        psi0 = inputs.haar_state(rng, 2)
+        N, T, x0 = 301, 150, (150, 0)
+        P = oracle.prob(oracle.walk(N, 1, inputs.RING, oracle.coin(oracle.SU2, 2, th, ph, ch), x0, psi0, T))
+        R = np.array([[math.cos(th), math.sin(th)], [-math.sin(th), math.cos(th)]], dtype=complex)
+        psi0r = np.array([psi0[0], np.exp(1j * (ch - ph)) * psi0[1]])
+        Pr = oracle.prob(oracle.walk(N, 1, inputs.RING, R, x0, psi0r, T))
+        assert np.max(np.abs(P - Pr)) <= 1e-14
+        # control: without the phase on the second component the distributions differ
+        Pw = oracle.prob(oracle.walk(N, 1, inputs.RING, R, x0, psi0, T))
+        if abs(math.sin(ch - ph)) > 0.1 and abs(psi0[0] * psi0[1]) > 0.05:
+            assert np.max(np.abs(P - Pw)) > 1e-6
+
+
 @pytest.mark.parametrize("table", ["RING", "PAIR", "DIAG"])
 def test_exact_reversal(table):
     disp = getattr(inputs, table)
