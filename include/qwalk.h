@@ -274,6 +274,90 @@ int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save);
 int walk_batch_destroy(qw_batch_t b);
 const char *walk_batch_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the ring walk.
+ *
+ * A network maps the parameters of one ring walk -- SU(2) angles, start coin
+ * state, T/N, as 32 features (surr_features) -- to its distribution in 512
+ * symmetric bins (the binning of walk_batch_binned):
+ *   h1 = relu(x W1^T + b1) (512 x 32), h2 = relu(h1 W2^T + b2) (1024 x 512),
+ *   h3 = relu(h2 W3^T + b3) (1024 x 1024), z4 = h3 W4^T + b4 (1024 x 1024) read
+ *   as 2 channels x 512 bins, l = conv1d(z4; 9 taps, zero padding) + cb,
+ *   q = softmax(l).
+ * The GEMMs run on MFMA with bf16 operands and fp32 accumulation; the head,
+ * softmax, KL(y || q) loss and its gradient in fp32; Adam keeps fp32 master
+ * weights.  Parameters are one fp32 vector in the order W1, b1, W2, b2, W3,
+ * b3, W4, b4, cw (2 x 9), cb (surr_num_params() values).  The plain walk is
+ * the surrogate's fallback and its judge (surr_predict).
+ * ------------------------------------------------------------------------ */
+typedef struct qw_surr *qw_surr_t;
+
+typedef struct {
+    int32_t batch;        /* samples per step: a multiple of 128 in [128, 4096] */
+    int32_t epochs;
+    float lr;             /* peak Adam learning rate (cosine decay to lr * lr_floor) */
+    float lr_floor;
+    float weight_decay;   /* added to the gradient: g + wd * p */
+    int32_t reserved;
+    uint64_t seed;        /* shuffling */
+} qw_train_opts;
+
+typedef struct {
+    double recheck_frac;  /* fraction of every chunk re-run with the plain walk (default 0.01) */
+    double tvd_tol;       /* a chunk falls back when a re-checked walk is farther (default 1e-3) */
+    int64_t chunk;        /* walks per chunk (default 1024) */
+    uint64_t seed;        /* choice of the re-checked walks */
+    int64_t reserved;
+} qw_predict_opts;
+
+typedef struct {
+    int64_t out_of_range;     /* walks outside the training range (always plain) */
+    int64_t rechecked;        /* walks re-run to check the network */
+    int64_t failed_chunks;    /* chunks whose re-check exceeded tvd_tol */
+    int64_t fallback;         /* walks answered by the plain walk (out of range + failed chunks) */
+    double max_tvd_sampled;   /* largest TVD seen in the re-check */
+    double ms_network, ms_recheck, ms_fallback;  /* device time of each part */
+} qw_predict_stats;
+
+int64_t surr_num_params(void);
+/* New network with seeded He-uniform weights (zero biases) on `stream` (NULL:
+ * a private stream).  Training range defaults to N = 4097, T in [256, 2048]. */
+int surr_create(uint64_t seed, void *stream, qw_surr_t *out);
+/* out: host, surr_num_params() floats (bf16_rounded != 0: weight matrices as
+ * the GEMMs see them). */
+int surr_get_params(qw_surr_t s, float *out, int32_t bf16_rounded);
+int surr_set_params(qw_surr_t s, const float *in);
+/* Features of n walks (host arrays as for walk_batch_create) into out (host,
+ * n x 32 floats): sin/cos of theta, phi, chi; |a|, Re b', Im b' with
+ * b' = b e^{-i arg a}; T/N; cos and sin of arg b - arg a + chi - phi; zeros. */
+int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles,
+                  const double *psi0, float *out);
+/* Network output q (n x 512, host) for features X (n x 32, host). */
+int surr_forward(qw_surr_t s, int64_t n, const float *X, float *out);
+/* Mean loss and the gradient of every parameter (host, surr_num_params()) for
+ * n <= 4096 samples (X: n x 32, Y: n x 512 targets, host). */
+int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, double *loss, float *grads);
+/* Train on n samples held on the device (X: n x 32, Y: n x 512 floats);
+ * epoch_loss (host, epochs floats, may be NULL) receives the mean loss of
+ * every epoch.  Synchronises. */
+int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_train_opts *opts,
+               float *epoch_loss);
+/* Inputs accepted without fallback: ring size N, T in [tmin, tmax]. */
+int surr_set_range(qw_surr_t s, int64_t N, int32_t tmin, int32_t tmax);
+/* Binned P of n walks (host arrays as for walk_batch_create; x0 = N/2) into
+ * out (host, n x 512): the network answers; walks outside the training range
+ * and every chunk whose seeded re-check sample exceeds tvd_tol are answered by
+ * the plain walk (complex64 batch); used_fallback (host, n bytes, may be NULL)
+ * marks them.  Re-checked walks keep their plain result.  Synchronises. */
+int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles,
+                 const double *psi0, const qw_predict_opts *opts, float *out, uint8_t *used_fallback,
+                 qw_predict_stats *stats);
+/* Binary file: "QWSURR1\n", int64 {n_params, N, tmin, tmax}, fp32 parameters. */
+int surr_save(qw_surr_t s, const char *path);
+int surr_load(const char *path, void *stream, qw_surr_t *out);
+int surr_destroy(qw_surr_t s);
+const char *surr_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

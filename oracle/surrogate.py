@@ -1,0 +1,152 @@
+"""fp64 reference of the surrogate network (test infrastructure only).
+
+The learned surrogate maps the parameters of one ring walk (SU(2) coin
+angles, start coin state, T/N) to its position distribution in 512 symmetric
+bins.  This module is the plain, slow definition of that network in float64
+numpy, used to check the GPU forward pass, loss and gradients; it shares no
+code with the HIP path.  The parameters are passed in as a dict of arrays (the
+GPU's bf16-rounded weights when comparing with it).
+
+Network (input F = 32 features, zero-padded):
+    h1 = relu(x W1^T + b1)          W1: 512 x 32
+    h2 = relu(h1 W2^T + b2)         W2: 1024 x 512
+    h3 = relu(h2 W3^T + b3)         W3: 1024 x 1024
+    z4 = h3 W4^T + b4               W4: 1024 x 1024, read as 2 channels x 512 positions
+    l[i] = cb + sum_c sum_j cw[c, j] z4[c, i + j - 4]   (1D conv, 9 taps, zero padding)
+    q = softmax(l)                  over the 512 bins
+Loss: mean over the batch of KL(y || q) = sum_i y_i (log y_i - log q_i), with
+0 log 0 = 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NBINS = 512
+CONV_TAPS = 9
+CONV_PAD = 4
+SHAPES = {
+    "W1": (512, 32), "b1": (512,),
+    "W2": (1024, 512), "b2": (1024,),
+    "W3": (1024, 1024), "b3": (1024,),
+    "W4": (1024, 1024), "b4": (1024,),
+    "cw": (2, CONV_TAPS), "cb": (1,),
+}
+ORDER = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "cw", "cb")
+
+
+def n_params() -> int:
+    return int(sum(np.prod(s) for s in SHAPES.values()))
+
+
+def unflatten(flat: np.ndarray) -> dict:
+    out, o = {}, 0
+    for k in ORDER:
+        n = int(np.prod(SHAPES[k]))
+        out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(SHAPES[k])
+        o += n
+    return out
+
+
+def flatten(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).ravel() for k in ORDER])
+
+
+def _conv(z4, cw, cb):
+    """l[b, i] = cb + sum_c sum_j cw[c, j] z4[b, c, i + j - 4] with zero padding."""
+    B = z4.shape[0]
+    zp = np.zeros((B, 2, NBINS + 2 * CONV_PAD))
+    zp[:, :, CONV_PAD:CONV_PAD + NBINS] = z4
+    out = np.full((B, NBINS), cb[0])
+    for c in range(2):
+        for j in range(CONV_TAPS):
+            out += cw[c, j] * zp[:, c, j:j + NBINS]
+    return out
+
+
+def forward(p: dict, x: np.ndarray) -> dict:
+    x = np.asarray(x, dtype=np.float64)
+    a = {"x": x}
+    a["z1"] = x @ p["W1"].T + p["b1"]
+    a["h1"] = np.maximum(a["z1"], 0.0)
+    a["z2"] = a["h1"] @ p["W2"].T + p["b2"]
+    a["h2"] = np.maximum(a["z2"], 0.0)
+    a["z3"] = a["h2"] @ p["W3"].T + p["b3"]
+    a["h3"] = np.maximum(a["z3"], 0.0)
+    a["z4"] = a["h3"] @ p["W4"].T + p["b4"]
+    a["l"] = _conv(a["z4"].reshape(-1, 2, NBINS), p["cw"], p["cb"])
+    m = a["l"].max(axis=1, keepdims=True)
+    e = np.exp(a["l"] - m)
+    a["q"] = e / e.sum(axis=1, keepdims=True)
+    a["logq"] = (a["l"] - m) - np.log(e.sum(axis=1, keepdims=True))
+    return a
+
+
+def loss(p: dict, x: np.ndarray, y: np.ndarray) -> float:
+    a = forward(p, x)
+    y = np.asarray(y, dtype=np.float64)
+    ylogy = np.where(y > 0, y * np.log(np.where(y > 0, y, 1.0)), 0.0)
+    return float(np.mean(np.sum(ylogy - y * a["logq"], axis=1)))
+
+
+def backward(p: dict, x: np.ndarray, y: np.ndarray) -> dict:
+    """Gradients of loss() with respect to every parameter (chain rule written out)."""
+    a = forward(p, x)
+    y = np.asarray(y, dtype=np.float64)
+    B = x.shape[0]
+    # d/dl of sum_i -y_i log softmax(l)_i = q * sum(y) - y
+    dl = (a["q"] * y.sum(axis=1, keepdims=True) - y) / B
+    g = {}
+    g["cb"] = np.array([dl.sum()])
+    z4 = a["z4"].reshape(B, 2, NBINS)
+    zp = np.zeros((B, 2, NBINS + 2 * CONV_PAD))
+    zp[:, :, CONV_PAD:CONV_PAD + NBINS] = z4
+    g["cw"] = np.zeros((2, CONV_TAPS))
+    dzp = np.zeros_like(zp)
+    for c in range(2):
+        for j in range(CONV_TAPS):
+            g["cw"][c, j] = np.sum(dl * zp[:, c, j:j + NBINS])
+            dzp[:, c, j:j + NBINS] += p["cw"][c, j] * dl
+    dz4 = dzp[:, :, CONV_PAD:CONV_PAD + NBINS].reshape(B, 2 * NBINS)
+    g["W4"] = dz4.T @ a["h3"]
+    g["b4"] = dz4.sum(axis=0)
+    dh3 = dz4 @ p["W4"]
+    dz3 = dh3 * (a["z3"] > 0)
+    g["W3"] = dz3.T @ a["h2"]
+    g["b3"] = dz3.sum(axis=0)
+    dh2 = dz3 @ p["W3"]
+    dz2 = dh2 * (a["z2"] > 0)
+    g["W2"] = dz2.T @ a["h1"]
+    g["b2"] = dz2.sum(axis=0)
+    dh1 = dz2 @ p["W2"]
+    dz1 = dh1 * (a["z1"] > 0)
+    g["W1"] = dz1.T @ a["x"]
+    g["b1"] = dz1.sum(axis=0)
+    return g
+
+
+def tvd(p: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Total-variation distance 1/2 sum_b |p_b - q_b| per row."""
+    return 0.5 * np.sum(np.abs(np.asarray(p, np.float64) - np.asarray(q, np.float64)), axis=-1)
+
+
+def features(N, T, angles, psi0) -> np.ndarray:
+    """The 32 input features of each walk (fp64): sin/cos of (theta, phi, chi);
+    |a|, Re b', Im b' with b' = b e^{-i arg a}; T/N; cos and sin of
+    delta = arg b - arg a + chi - phi; zeros."""
+    N = np.asarray(N, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 3)
+    p = np.asarray(psi0, dtype=np.complex128).reshape(-1, 2)
+    th, ph, ch = ang[:, 0], ang[:, 1], ang[:, 2]
+    a, b = p[:, 0], p[:, 1]
+    arga, argb = np.angle(a), np.angle(b)
+    bp = b * np.exp(-1j * arga)
+    dl = argb - arga + ch - ph
+    X = np.zeros((p.shape[0], 32))
+    X[:, 0], X[:, 1] = np.sin(th), np.cos(th)
+    X[:, 2], X[:, 3] = np.sin(ph), np.cos(ph)
+    X[:, 4], X[:, 5] = np.sin(ch), np.cos(ch)
+    X[:, 6], X[:, 7], X[:, 8] = np.abs(a), bp.real, bp.imag
+    X[:, 9] = T / N
+    X[:, 10], X[:, 11] = np.cos(dl), np.sin(dl)
+    return X

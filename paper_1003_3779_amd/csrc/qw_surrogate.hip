@@ -1,0 +1,978 @@
+// qw_surrogate.hip -- a learned surrogate of the ring walk: a small network
+// (MLP + 1D convolution head) that maps the parameters of a walk to its
+// position distribution in 512 symmetric bins, trained on walks produced by
+// the batched simulator, with the plain walk as its fallback and its judge.
+//
+// Network (x: 32 features, 12 used, the rest zero):
+//   h1 = relu(x W1^T + b1)      512 x 32        (GEMMs: bf16 operands on
+//   h2 = relu(h1 W2^T + b2)     1024 x 512       MFMA, fp32 accumulation)
+//   h3 = relu(h2 W3^T + b3)     1024 x 1024
+//   z4 = h3 W4^T + b4           1024 x 1024, read as 2 channels x 512 bins
+//   l  = conv1d(z4; 2 -> 1 channel, 9 taps, zero padding) + cb
+//   q  = softmax(l)
+// Loss: mean over the batch of KL(y || q).  Training: Adam on fp32 master
+// weights; the kernels read bf16 copies (and transposed copies for dX).
+#include "qwalk.h"
+#include "qw_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+namespace qw {
+namespace {
+
+typedef unsigned short bf16_t;
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kF = 32;      // input features (padded)
+constexpr int kH1 = 512, kH2 = 1024, kH3 = 1024, kZ4 = 1024;
+constexpr int kBins = 512;
+constexpr int kTaps = 9, kPad = 4;
+
+__host__ __device__ inline bf16_t f2bf(float f) {
+    unsigned u = __builtin_bit_cast(unsigned, f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
+
+// ---------------------------------------------------------------- GEMM
+// C[m][n] = alpha * sum_k A[m][k] B[n][k] (+ bias[n]); optional mask (keep where
+// mask[m][n] > 0) and relu; store fp32 and/or bf16.  A: M x K, B: N x K, both
+// bf16 row-major with K contiguous; K % 32 == 0.  Tile 128 x 128 x 32 per
+// 256-thread block, each wave a 64 x 64 quarter as 2 x 2 MFMA 32x32x8 tiles.
+struct GemmArgs {
+    const bf16_t *A;
+    int lda;
+    const bf16_t *B;
+    int ldb;
+    int M, N, K;
+    float alpha;
+    const float *bias;
+    const bf16_t *mask;
+    int ldm;
+    int relu;
+    float *C;
+    int ldc;
+    bf16_t *Cb;
+    int ldcb;
+};
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsRow = kBK + 4;  // +4 bf16 row padding (bank spread)
+
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+    __shared__ bf16_t sA[kBM * kLdsRow];
+    __shared__ bf16_t sB[kBN * kLdsRow];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    float16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    // staging: each thread moves 2 x 16 bytes of A and of B per K step
+    const int lrow = tid >> 2, lk = (tid & 3) * 8;
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        uint4 va[2], vb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = lrow + 64 * h;
+            const int ma = m0 + r, nb = n0 + r;
+            va[h] = ma < g.M ? *(const uint4 *)(g.A + (int64_t)ma * g.lda + k0 + lk) : make_uint4(0, 0, 0, 0);
+            vb[h] = nb < g.N ? *(const uint4 *)(g.B + (int64_t)nb * g.ldb + k0 + lk) : make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = lrow + 64 * h;
+            unsigned *pa = (unsigned *)(sA + r * kLdsRow + lk);
+            unsigned *pb = (unsigned *)(sB + r * kLdsRow + lk);
+            pa[0] = va[h].x; pa[1] = va[h].y; pa[2] = va[h].z; pa[3] = va[h].w;
+            pb[0] = vb[h].x; pb[1] = vb[h].y; pb[2] = vb[h].z; pb[3] = vb[h].w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 8) {
+            // lane l supplies row (l % 32) of the 32 x 8 operand, k = kk + 4 (l / 32) .. + 3
+            const int kof = kk + 4 * (lane >> 5);
+            short4_t a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16_t *p = sA + (wm * 64 + i * 32 + (lane & 31)) * kLdsRow + kof;
+                a[i] = *(const short4_t *)p;
+                const bf16_t *q = sB + (wn * 64 + i * 32 + (lane & 31)) * kLdsRow + kof;
+                b[i] = *(const short4_t *)q;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // result layout of a 32x32 tile: lane l holds column l % 32, rows
+    // 8 (r / 4) + 4 (l / 32) + (r % 4) for r = 0 .. 15
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+            if (n >= g.N) continue;
+            const float bn = g.bias ? g.bias[n] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (m >= g.M) continue;
+                float v = g.alpha * acc[i][j][r] + bn;
+                if (g.mask && !(bf2f(g.mask[(int64_t)m * g.ldm + n]) > 0.0f)) v = 0.0f;
+                if (g.relu) v = v > 0.0f ? v : 0.0f;
+                if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
+                if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = f2bf(v);
+            }
+        }
+}
+
+// out[c][r] = in[r][c] (bf16, R x C -> C x R), 32 x 32 tiles through LDS
+__global__ __launch_bounds__(256) void k_transpose(const bf16_t *__restrict__ in, int R, int C, int ldi,
+                                                   bf16_t *__restrict__ out, int ldo) {
+    __shared__ bf16_t t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, c = c0 + tx;
+        t[y][tx] = (r < R && c < C) ? in[(int64_t)r * ldi + c] : (bf16_t)0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int c = c0 + y, r = r0 + tx;
+        if (c < C && r < R) out[(int64_t)c * ldo + r] = t[tx][y];
+    }
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ in, bf16_t *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = f2bf(in[i]);
+}
+
+// db[n] = sum_b dz[b][n] (fixed order over b)
+__global__ void k_colsum(const float *__restrict__ dz, int B, int N, float *__restrict__ db) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += dz[(int64_t)b * N + n];
+    db[n] = s;
+}
+
+// ---------------------------------------------------------------- conv head
+// One block (256 threads) per sample: l = conv(z4) + cb, q = softmax(l); with
+// targets: dl = (q sum(y) - y) / B and the per-sample loss.
+__global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, const float *__restrict__ cw,
+                                                  const float *__restrict__ cb, float *__restrict__ q,
+                                                  const float *__restrict__ y, float *__restrict__ dl,
+                                                  float *__restrict__ loss_row, int B) {
+    __shared__ float sz[2][kBins + 2 * kPad];
+    __shared__ float red[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const float *zr = z4 + (int64_t)b * kZ4;
+    for (int i = t; i < kBins + 2 * kPad; i += 256) {
+        const int p = i - kPad;
+        sz[0][i] = (p >= 0 && p < kBins) ? zr[p] : 0.0f;
+        sz[1][i] = (p >= 0 && p < kBins) ? zr[kBins + p] : 0.0f;
+    }
+    __syncthreads();
+    float l[2];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = t + 256 * h;
+        float v = cb[0];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) v += cw[c * kTaps + j] * sz[c][i + j];
+        l[h] = v;
+        mx = fmaxf(mx, v);
+    }
+    red[t] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] = fmaxf(red[t], red[t + s]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    const float e0 = expf(l[0] - mx), e1 = expf(l[1] - mx);
+    red[t] = e0 + e1;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const float den = red[0];
+    __syncthreads();
+    const float lse = logf(den);
+    const float q0 = e0 / den, q1 = e1 / den;
+    if (q) {
+        q[(int64_t)b * kBins + t] = q0;
+        q[(int64_t)b * kBins + t + 256] = q1;
+    }
+    if (y) {
+        const float y0 = y[(int64_t)b * kBins + t], y1 = y[(int64_t)b * kBins + t + 256];
+        // loss_b = sum y log y - sum y (l - mx - lse)
+        float lv = 0.0f;
+        if (y0 > 0.0f) lv += y0 * logf(y0);
+        if (y1 > 0.0f) lv += y1 * logf(y1);
+        lv -= y0 * (l[0] - mx - lse) + y1 * (l[1] - mx - lse);
+        red[t] = y0 + y1;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (t < s) red[t] += red[t + s];
+            __syncthreads();
+        }
+        const float ysum = red[0];
+        __syncthreads();
+        dl[(int64_t)b * kBins + t] = (q0 * ysum - y0) / (float)B;
+        dl[(int64_t)b * kBins + t + 256] = (q1 * ysum - y1) / (float)B;
+        red[t] = lv;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (t < s) red[t] += red[t + s];
+            __syncthreads();
+        }
+        if (t == 0) loss_row[b] = red[0];
+    }
+}
+
+// Backward of the head for one sample: dz4[c][p] = sum_j cw[c][j] dl[p - j + pad];
+// per-sample partial gradients of the 18 taps and the bias (reduced later).
+__global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, const float *__restrict__ cw,
+                                                  const float *__restrict__ dl, float *__restrict__ dz4,
+                                                  float *__restrict__ part /* B x 19 */) {
+    __shared__ float sdl[kBins + 2 * kPad];
+    __shared__ float sz[2][kBins + 2 * kPad];
+    __shared__ float red[19][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    for (int i = t; i < kBins + 2 * kPad; i += 256) {
+        const int p = i - kPad;
+        const bool in = p >= 0 && p < kBins;
+        sdl[i] = in ? dl[(int64_t)b * kBins + p] : 0.0f;
+        sz[0][i] = in ? z4[(int64_t)b * kZ4 + p] : 0.0f;
+        sz[1][i] = in ? z4[(int64_t)b * kZ4 + kBins + p] : 0.0f;
+    }
+    __syncthreads();
+    float g[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) g[k] = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int p = t + 256 * h;  // position in [0, 512)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float v = 0.0f;
+            // l[i] uses z[i + j - pad]: z[p] feeds l[p - j + pad]
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) v += cw[c * kTaps + j] * sdl[p - j + 2 * kPad];
+            dz4[(int64_t)b * kZ4 + c * kBins + p] = v;
+        }
+        const float d = sdl[p + kPad];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) g[c * kTaps + j] += d * sz[c][p + j];
+        g[18] += d;
+    }
+#pragma unroll
+    for (int k = 0; k < 19; ++k) red[k][t] = g[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int k = 0; k < 19; ++k) red[k][t] += red[k][t + s];
+        __syncthreads();
+    }
+    if (t < 19) part[(int64_t)b * 19 + t] = red[t][0];
+}
+
+// sum over samples of the per-sample head gradients (fixed order)
+__global__ void k_head_reduce(const float *__restrict__ part, int B, float *__restrict__ gcw, float *__restrict__ gcb) {
+    const int k = threadIdx.x;
+    if (k >= 19) return;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += part[(int64_t)b * 19 + k];
+    if (k < 18) gcw[k] = s;
+    else gcb[0] = s;
+}
+
+// Adam on fp32 master weights; writes the bf16 copy used by the GEMMs
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, bf16_t *__restrict__ pb, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, float wd) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i] + wd * p[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (pb) pb[i] = f2bf(pi);
+    }
+}
+
+// rows idx[i] of X (n x 32 fp32) and Y (n x 512 fp32) -> batch buffers (X as bf16)
+__global__ void k_gather(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *__restrict__ idx,
+                         int B, bf16_t *__restrict__ xb, float *__restrict__ yb) {
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const int64_t r = idx[b];
+    for (int i = threadIdx.x; i < kF; i += blockDim.x) xb[(int64_t)b * kF + i] = f2bf(X[r * kF + i]);
+    if (Y)
+        for (int i = threadIdx.x; i < kBins; i += blockDim.x) yb[(int64_t)b * kBins + i] = Y[r * kBins + i];
+}
+
+// features of a walk: sin/cos of (theta, phi, chi); the start state with its
+// global phase removed, (|a|, Re b', Im b'), b' = b e^{-i arg a}; T/N; cos and
+// sin of delta = arg b - arg a + chi - phi (the relative phase that, with theta
+// and |a|, fixes P); zeros up to 32.
+__global__ void k_features(int64_t n, const int64_t *__restrict__ N, const int64_t *__restrict__ T,
+                           const double *__restrict__ ang, const double *__restrict__ psi0, float *__restrict__ X) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double th = ang[3 * i], ph = ang[3 * i + 1], ch = ang[3 * i + 2];
+        const double ar = psi0[4 * i], ai = psi0[4 * i + 1], br = psi0[4 * i + 2], bi = psi0[4 * i + 3];
+        const double aa = sqrt(ar * ar + ai * ai);
+        const double arga = aa > 0.0 ? atan2(ai, ar) : 0.0;
+        const double argb = (br != 0.0 || bi != 0.0) ? atan2(bi, br) : 0.0;
+        const double ca = cos(arga), sa = sin(arga);
+        const double bpr = br * ca + bi * sa, bpi = bi * ca - br * sa;  // b e^{-i arg a}
+        const double dl = argb - arga + ch - ph;
+        float *x = X + i * kF;
+        x[0] = (float)sin(th); x[1] = (float)cos(th);
+        x[2] = (float)sin(ph); x[3] = (float)cos(ph);
+        x[4] = (float)sin(ch); x[5] = (float)cos(ch);
+        x[6] = (float)aa; x[7] = (float)bpr; x[8] = (float)bpi;
+        x[9] = (float)((double)T[i] / (double)N[i]);
+        x[10] = (float)cos(dl); x[11] = (float)sin(dl);
+        for (int k = 12; k < kF; ++k) x[k] = 0.0f;
+    }
+}
+
+// tvd[i] = 1/2 sum_b |p - q| (fp64 accumulation), one block per row
+__global__ __launch_bounds__(256) void k_tvd(const float *__restrict__ p, const float *__restrict__ q, int nb,
+                                             double *__restrict__ out) {
+    __shared__ double red[256];
+    const int r = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (int i = t; i < nb; i += 256) s += fabs((double)p[(int64_t)r * nb + i] - (double)q[(int64_t)r * nb + i]);
+    red[t] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) red[t] += red[t + k];
+        __syncthreads();
+    }
+    if (t == 0) out[r] = 0.5 * red[0];
+}
+
+}  // namespace
+}  // namespace qw
+
+using namespace qw;
+
+// ================================================================ host side
+namespace {
+
+thread_local std::string g_serr;
+
+int sfail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_serr = buf;
+    return code;
+}
+
+#define QS_HIP(call, what)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return sfail(QW_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
+    } while (0)
+
+// parameter layout (fp32 master vector), the order of the reference network
+struct Layout {
+    int64_t W1, b1, W2, b2, W3, b3, W4, b4, cw, cb, total;
+    Layout() {
+        int64_t o = 0;
+        W1 = o; o += (int64_t)kH1 * kF;
+        b1 = o; o += kH1;
+        W2 = o; o += (int64_t)kH2 * kH1;
+        b2 = o; o += kH2;
+        W3 = o; o += (int64_t)kH3 * kH2;
+        b3 = o; o += kH3;
+        W4 = o; o += (int64_t)kZ4 * kH3;
+        b4 = o; o += kZ4;
+        cw = o; o += 2 * kTaps;
+        cb = o; o += 1;
+        total = o;
+    }
+};
+const Layout L;
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+double unif(uint64_t &s) { return (splitmix(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+}  // namespace
+
+struct qw_surr {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int bmax = 4096;
+    float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 params, Adam moments, grads
+    bf16_t *pb = nullptr;                                          // bf16 mirror of p
+    bf16_t *W2T = nullptr, *W3T = nullptr, *W4T = nullptr;
+    // activations (bmax rows)
+    bf16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;
+    float *z4 = nullptr, *q = nullptr, *yb = nullptr, *dl = nullptr, *lrow = nullptr, *part = nullptr;
+    float *dz = nullptr;                       // fp32 dz (bmax x 1024)
+    bf16_t *dzb = nullptr, *dzT = nullptr, *hT = nullptr;
+    int32_t *idx = nullptr;
+    int64_t adam_t = 0;
+    uint64_t seed = 0;
+    int64_t train_n = 4097;   // the ring size the network was trained on
+    int32_t tmin = 256, tmax = 2048;
+};
+
+namespace {
+
+void free_surr(qw_surr *s) {
+    if (!s) return;
+    void *bufs[] = {s->p, s->m, s->v, s->g, s->pb, s->W2T, s->W3T, s->W4T, s->xb, s->h1, s->h2, s->h3,
+                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx};
+    for (void *b : bufs) (void)hipFree(b);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
+                const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
+    if (K % kBK) return hipErrorInvalidValue;
+    GemmArgs a{A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb};
+    dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t transpose(hipStream_t st, const bf16_t *in, int R, int C, int ldi, bf16_t *out, int ldo) {
+    dim3 grid((C + 31) / 32, (R + 31) / 32);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, in, R, C, ldi, out, ldo);
+    return hipGetLastError();
+}
+
+// refresh the bf16 mirror (from p) and the transposed weights
+hipError_t refresh_weights(qw_surr *s) {
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(2048), dim3(256), 0, s->stream, (const float *)s->p, s->pb, L.total);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2);
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3);
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4);
+    return e;
+}
+
+// forward of B rows already in s->xb; y (device, B x 512) optional -> dl, lrow
+hipError_t forward(qw_surr *s, int B, int Bscale, const float *y) {
+    hipStream_t st = s->stream;
+    hipError_t e = gemm(st, s->xb, kF, s->pb + L.W1, kF, B, kH1, kF, 1.0f, s->p + L.b1, nullptr, 0, 1, nullptr, 0, s->h1, kH1);
+    if (e == hipSuccess)
+        e = gemm(st, s->h1, kH1, s->pb + L.W2, kH1, B, kH2, kH1, 1.0f, s->p + L.b2, nullptr, 0, 1, nullptr, 0, s->h2, kH2);
+    if (e == hipSuccess)
+        e = gemm(st, s->h2, kH2, s->pb + L.W3, kH2, B, kH3, kH2, 1.0f, s->p + L.b3, nullptr, 0, 1, nullptr, 0, s->h3, kH3);
+    if (e == hipSuccess)
+        e = gemm(st, s->h3, kH3, s->pb + L.W4, kH3, B, kZ4, kH3, 1.0f, s->p + L.b4, nullptr, 0, 0, s->z4, kZ4, nullptr, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
+                       (const float *)(s->p + L.cb), s->q, y, s->dl, s->lrow, Bscale);
+    return hipGetLastError();
+}
+
+// backward of the batch of the last forward (with targets): gradients into s->g
+hipError_t backward(qw_surr *s, int B) {
+    hipStream_t st = s->stream;
+    hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
+                       (const float *)s->dl, s->dz, s->part);
+    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(64), 0, st, (const float *)s->part, B, s->g + L.cw, s->g + L.cb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    struct Lay {
+        const bf16_t *hin;  // layer input activation (B x kin)
+        int kin, kout;
+        int64_t W, b;
+        const bf16_t *WT;   // kin x kout (transposed weight) for dX; null for the first layer
+    } lays[4] = {
+        {s->xb, kF, kH1, L.W1, L.b1, nullptr},
+        {s->h1, kH1, kH2, L.W2, L.b2, s->W2T},
+        {s->h2, kH2, kH3, L.W3, L.b3, s->W3T},
+        {s->h3, kH3, kZ4, L.W4, L.b4, s->W4T},
+    };
+    for (int li = 3; li >= 0; --li) {
+        const Lay &ly = lays[li];
+        // s->dz holds dZ of this layer (fp32, B x kout)
+        hipLaunchKernelGGL(k_colsum, dim3((ly.kout + 255) / 256), dim3(256), 0, st, (const float *)s->dz, B, ly.kout,
+                           s->g + ly.b);
+        hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, s->dzb, (int64_t)B * ly.kout);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = transpose(st, s->dzb, B, ly.kout, ly.kout, s->dzT, B);
+        if (e == hipSuccess) e = transpose(st, ly.hin, B, ly.kin, ly.kin, s->hT, B);
+        // dW[n][k] = sum_b dZ[b][n] Hin[b][k]
+        if (e == hipSuccess)
+            e = gemm(st, s->dzT, B, s->hT, B, ly.kout, ly.kin, B, 1.0f, nullptr, nullptr, 0, 0, s->g + ly.W, ly.kin,
+                     nullptr, 0);
+        if (e != hipSuccess) return e;
+        if (li > 0) {
+            // dZ_prev = (dZ W) masked by the previous activation > 0
+            const Lay &pv = lays[li - 1];
+            e = gemm(st, s->dzb, ly.kout, ly.WT, ly.kout, B, ly.kin, ly.kout, 1.0f, nullptr, ly.hin, ly.kin, 0, s->dz,
+                     ly.kin, nullptr, 0);
+            (void)pv;
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t adam_step(qw_surr *s, float lr, float wd) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    s->adam_t += 1;
+    const float c1 = 1.0f - powf(b1, (float)s->adam_t), c2 = 1.0f - powf(b2, (float)s->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, s->stream, s->p, s->m, s->v, (const float *)s->g, s->pb,
+                       L.total, lr, b1, b2, eps, c1, c2, wd);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2);
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3);
+    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4);
+    return e;
+}
+
+int alloc_surr(qw_surr *s) {
+    const int B = s->bmax;
+    struct A {
+        void **p;
+        size_t bytes;
+    } list[] = {
+        {(void **)&s->p, sizeof(float) * L.total}, {(void **)&s->m, sizeof(float) * L.total},
+        {(void **)&s->v, sizeof(float) * L.total}, {(void **)&s->g, sizeof(float) * L.total},
+        {(void **)&s->pb, sizeof(bf16_t) * L.total},
+        {(void **)&s->W2T, sizeof(bf16_t) * kH2 * kH1}, {(void **)&s->W3T, sizeof(bf16_t) * kH3 * kH2},
+        {(void **)&s->W4T, sizeof(bf16_t) * kZ4 * kH3},
+        {(void **)&s->xb, sizeof(bf16_t) * B * kF}, {(void **)&s->h1, sizeof(bf16_t) * B * kH1},
+        {(void **)&s->h2, sizeof(bf16_t) * B * kH2}, {(void **)&s->h3, sizeof(bf16_t) * B * kH3},
+        {(void **)&s->z4, sizeof(float) * B * kZ4}, {(void **)&s->q, sizeof(float) * B * kBins},
+        {(void **)&s->yb, sizeof(float) * B * kBins}, {(void **)&s->dl, sizeof(float) * B * kBins},
+        {(void **)&s->lrow, sizeof(float) * B}, {(void **)&s->part, sizeof(float) * B * 19},
+        {(void **)&s->dz, sizeof(float) * B * 1024}, {(void **)&s->dzb, sizeof(bf16_t) * B * 1024},
+        {(void **)&s->dzT, sizeof(bf16_t) * B * 1024}, {(void **)&s->hT, sizeof(bf16_t) * B * 1024},
+        {(void **)&s->idx, sizeof(int32_t) * B},
+    };
+    for (auto &a : list) {
+        hipError_t e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *a.p = nullptr;
+            return sfail(QW_ENOMEM, "hipMalloc of %zu bytes for the surrogate failed: %s", a.bytes, hipGetErrorString(e));
+        }
+    }
+    return QW_OK;
+}
+
+// rows [0, n) of host X (n x 32 fp32) -> s->xb (zero rows up to the multiple of 128)
+int upload_rows(qw_surr *s, const float *Xh, int n, int npad) {
+    std::vector<bf16_t> xb((size_t)npad * kF, 0);
+    for (int64_t i = 0; i < (int64_t)n * kF; ++i) xb[i] = f2bf(Xh[i]);
+    QS_HIP(hipMemcpyAsync(s->xb, xb.data(), xb.size() * sizeof(bf16_t), hipMemcpyHostToDevice, s->stream), "upload");
+    QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    return QW_OK;
+}
+
+bool in_training_range(const qw_surr *s, int64_t N, int64_t T, const double *ang) {
+    const double pi = 3.14159265358979323846;
+    return N == s->train_n && T >= s->tmin && T <= s->tmax && ang[0] >= 0.0 && ang[0] <= pi && ang[1] >= 0.0 &&
+           ang[1] <= 2 * pi && ang[2] >= 0.0 && ang[2] <= 2 * pi;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *surr_last_error(void) { return g_serr.c_str(); }
+
+int64_t surr_num_params(void) { return L.total; }
+
+int surr_create(uint64_t seed, void *stream, qw_surr_t *out) {
+    if (!out) return sfail(QW_EINVAL, "out handle pointer is NULL");
+    *out = nullptr;
+    qw_surr *s = new (std::nothrow) qw_surr();
+    if (!s) return sfail(QW_ENOMEM, "host allocation failed");
+    s->seed = seed;
+    s->stream = (hipStream_t)stream;
+    if (!s->stream) {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return sfail(QW_EHIP, "hipStreamCreate failed");
+        }
+        s->own_stream = true;
+    }
+    int rc = alloc_surr(s);
+    if (rc) {
+        free_surr(s);
+        return rc;
+    }
+    // He-uniform initialisation from a seeded counter-free generator; zero biases
+    std::vector<float> h(L.total, 0.0f);
+    uint64_t st = seed ^ 0x5eed5eed5eedull;
+    auto fill = [&](int64_t off, int64_t rows, int64_t cols, double gain) {
+        const double lim = gain * sqrt(6.0 / (double)cols);
+        for (int64_t i = 0; i < rows * cols; ++i) h[off + i] = (float)((2.0 * unif(st) - 1.0) * lim);
+    };
+    fill(L.W1, kH1, kF, 1.0);
+    fill(L.W2, kH2, kH1, 1.0);
+    fill(L.W3, kH3, kH2, 1.0);
+    fill(L.W4, kZ4, kH3, 0.5);
+    for (int i = 0; i < 2 * kTaps; ++i) h[L.cw + i] = (i == kPad || i == kTaps + kPad) ? 0.5f : 0.0f;
+    hipError_t e = hipMemcpyAsync(s->p, h.data(), sizeof(float) * L.total, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->m, 0, sizeof(float) * L.total, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->v, 0, sizeof(float) * L.total, s->stream);
+    if (e == hipSuccess) e = refresh_weights(s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        free_surr(s);
+        return sfail(QW_EHIP, "surrogate initialisation: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return QW_OK;
+}
+
+int surr_get_params(qw_surr_t s, float *out, int32_t bf16_rounded) {
+    if (!s || !out) return sfail(QW_EINVAL, "NULL argument");
+    QS_HIP(hipMemcpyAsync(out, s->p, sizeof(float) * L.total, hipMemcpyDeviceToHost, s->stream), "copy of the parameters");
+    QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    if (bf16_rounded) {
+        const int64_t ws[4][2] = {{L.W1, (int64_t)kH1 * kF}, {L.W2, (int64_t)kH2 * kH1}, {L.W3, (int64_t)kH3 * kH2},
+                                  {L.W4, (int64_t)kZ4 * kH3}};
+        for (auto &w : ws)
+            for (int64_t i = 0; i < w[1]; ++i) out[w[0] + i] = bf2f(f2bf(out[w[0] + i]));
+    }
+    return QW_OK;
+}
+
+int surr_set_params(qw_surr_t s, const float *in) {
+    if (!s || !in) return sfail(QW_EINVAL, "NULL argument");
+    for (int64_t i = 0; i < L.total; ++i)
+        if (!isfinite(in[i])) return sfail(QW_EINVAL, "parameter %lld is not finite", (long long)i);
+    QS_HIP(hipMemcpyAsync(s->p, in, sizeof(float) * L.total, hipMemcpyHostToDevice, s->stream), "upload of the parameters");
+    QS_HIP(refresh_weights(s), "weight refresh");
+    QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    return QW_OK;
+}
+
+int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles,
+                  const double *psi0, float *out) {
+    if (!s || !N || !T || !angles || !psi0 || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
+    int64_t *dN = nullptr, *dT = nullptr;
+    double *dA = nullptr, *dP = nullptr;
+    float *dX = nullptr;
+    hipError_t e = hipMalloc((void **)&dN, 8 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dT, 8 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dA, 24 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dP, 32 * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dX, 4 * kF * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dN, N, 8 * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dT, T, 8 * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dA, angles, 24 * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dP, psi0, 32 * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_features, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s->stream,
+                           n, (const int64_t *)dN, (const int64_t *)dT, (const double *)dA, (const double *)dP, dX);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dX, 4 * kF * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(dN); (void)hipFree(dT); (void)hipFree(dA); (void)hipFree(dP); (void)hipFree(dX);
+    if (e != hipSuccess) return sfail(QW_EHIP, "surr_features: %s", hipGetErrorString(e));
+    return QW_OK;
+}
+
+int surr_forward(qw_surr_t s, int64_t n, const float *X, float *out) {
+    if (!s || !X || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
+    for (int64_t r0 = 0; r0 < n; r0 += s->bmax) {
+        const int b = (int)std::min<int64_t>(s->bmax, n - r0);
+        const int bp = (b + 127) / 128 * 128;
+        int rc = upload_rows(s, X + r0 * kF, b, bp);
+        if (rc) return rc;
+        QS_HIP(forward(s, bp, bp, nullptr), "surrogate forward");
+        QS_HIP(hipMemcpyAsync(out + r0 * kBins, s->q, sizeof(float) * b * kBins, hipMemcpyDeviceToHost, s->stream),
+               "copy of the bins");
+        QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    }
+    return QW_OK;
+}
+
+int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, double *loss, float *grads) {
+    if (!s || !X || !Y || !loss || !grads || n < 1) return sfail(QW_EINVAL, "bad arguments");
+    if (n > s->bmax) return sfail(QW_ERANGE, "at most %d rows per gradient call", s->bmax);
+    const int b = (int)n, bp = (b + 127) / 128 * 128;
+    int rc = upload_rows(s, X, b, bp);
+    if (rc) return rc;
+    std::vector<float> y((size_t)bp * kBins, 0.0f);
+    memcpy(y.data(), Y, sizeof(float) * b * kBins);
+    QS_HIP(hipMemcpyAsync(s->yb, y.data(), y.size() * sizeof(float), hipMemcpyHostToDevice, s->stream), "upload");
+    QS_HIP(forward(s, bp, b, s->yb), "surrogate forward");
+    QS_HIP(backward(s, bp), "surrogate backward");
+    std::vector<float> lr(bp);
+    QS_HIP(hipMemcpyAsync(lr.data(), s->lrow, sizeof(float) * bp, hipMemcpyDeviceToHost, s->stream), "copy");
+    QS_HIP(hipMemcpyAsync(grads, s->g, sizeof(float) * L.total, hipMemcpyDeviceToHost, s->stream), "copy");
+    QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    double acc = 0.0;
+    for (int i = 0; i < b; ++i) acc += lr[i];
+    *loss = acc / b;
+    return QW_OK;
+}
+
+int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_train_opts *o, float *epoch_loss) {
+    if (!s || !X || !Y || !o) return sfail(QW_EINVAL, "NULL argument");
+    const int B = o->batch;
+    if (B < 128 || B > s->bmax || B % 128) return sfail(QW_EINVAL, "batch must be a multiple of 128 in [128, %d]", s->bmax);
+    if (n < B) return sfail(QW_EINVAL, "need at least one batch of samples (n = %lld)", (long long)n);
+    if (o->epochs < 1 || !(o->lr > 0.0f)) return sfail(QW_EINVAL, "epochs >= 1 and lr > 0 required");
+    if (n > (1LL << 31) - 1) return sfail(QW_ERANGE, "too many samples");
+    const int64_t steps = n / B;
+    int32_t *perm = nullptr;
+    float *eloss = nullptr;
+    QS_HIP(hipMalloc((void **)&perm, sizeof(int32_t) * n), "hipMalloc");
+    if (hipMalloc((void **)&eloss, sizeof(float) * steps) != hipSuccess) {
+        (void)hipFree(perm);
+        return sfail(QW_ENOMEM, "hipMalloc failed");
+    }
+    std::vector<int32_t> hp(n);
+    std::vector<float> hl(steps);
+    uint64_t st = o->seed ^ 0x7a11ull;
+    hipError_t e = hipSuccess;
+    for (int ep = 0; ep < o->epochs && e == hipSuccess; ++ep) {
+        for (int64_t i = 0; i < n; ++i) hp[i] = (int32_t)i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(hp[i], hp[splitmix(st) % (uint64_t)(i + 1)]);
+        e = hipMemcpyAsync(perm, hp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s->stream);
+        // cosine learning-rate decay over the run
+        for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
+            const double prog = ((double)ep * steps + k) / ((double)o->epochs * steps);
+            const float lr = (float)(o->lr * (o->lr_floor + (1.0 - o->lr_floor) * 0.5 * (1.0 + cos(3.14159265358979 * prog))));
+            hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, X, Y, (const int32_t *)(perm + k * B), B, s->xb,
+                               s->yb);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = forward(s, B, B, s->yb);
+            if (e == hipSuccess) e = backward(s, B);
+            if (e == hipSuccess) e = adam_step(s, lr, o->weight_decay);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1), 0, s->stream, (const float *)s->lrow, B, 1, eloss + k);
+                e = hipGetLastError();
+            }
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), eloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess && epoch_loss) {
+            double acc = 0.0;
+            for (auto x : hl) acc += x;
+            epoch_loss[ep] = (float)(acc / ((double)steps * B));
+        }
+    }
+    (void)hipFree(perm);
+    (void)hipFree(eloss);
+    if (e != hipSuccess) return sfail(QW_EHIP, "training: %s", hipGetErrorString(e));
+    return QW_OK;
+}
+
+int surr_save(qw_surr_t s, const char *path) {
+    if (!s || !path) return sfail(QW_EINVAL, "NULL argument");
+    std::vector<float> h(L.total);
+    int rc = surr_get_params(s, h.data(), 0);
+    if (rc) return rc;
+    FILE *f = fopen(path, "wb");
+    if (!f) return sfail(QW_EINVAL, "cannot open %s for writing", path);
+    const char magic[8] = {'Q', 'W', 'S', 'U', 'R', 'R', '1', '\n'};
+    const int64_t meta[4] = {L.total, s->train_n, s->tmin, s->tmax};
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(meta, sizeof meta, 1, f) == 1 &&
+              fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return sfail(QW_EINVAL, "write to %s failed", path);
+    return QW_OK;
+}
+
+int surr_load(const char *path, void *stream, qw_surr_t *out) {
+    if (!path || !out) return sfail(QW_EINVAL, "NULL argument");
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return sfail(QW_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int64_t meta[4];
+    std::vector<float> h(L.total);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "QWSURR1\n", 8) == 0 && fread(meta, sizeof meta, 1, f) == 1 &&
+              meta[0] == L.total && fread(h.data(), sizeof(float), h.size(), f) == h.size();
+    fclose(f);
+    if (!ok) return sfail(QW_EINVAL, "%s is not a surrogate file of this network", path);
+    qw_surr_t s = nullptr;
+    int rc = surr_create(0, stream, &s);
+    if (rc) return rc;
+    s->train_n = meta[1];
+    s->tmin = (int32_t)meta[2];
+    s->tmax = (int32_t)meta[3];
+    rc = surr_set_params(s, h.data());
+    if (rc) {
+        free_surr(s);
+        return rc;
+    }
+    *out = s;
+    return QW_OK;
+}
+
+int surr_set_range(qw_surr_t s, int64_t N, int32_t tmin, int32_t tmax) {
+    if (!s || N < 1 || tmin < 0 || tmax < tmin) return sfail(QW_EINVAL, "bad training range");
+    s->train_n = N;
+    s->tmin = tmin;
+    s->tmax = tmax;
+    return QW_OK;
+}
+
+int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles, const double *psi0,
+                 const qw_predict_opts *po, float *out, uint8_t *used_fallback, qw_predict_stats *stats) {
+    if (!s || !N || !T || !angles || !psi0 || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
+    qw_predict_opts o = {0.01, 1e-3, 1024, 1, 0};
+    if (po) o = *po;
+    if (o.chunk < 1 || !(o.recheck_frac >= 0.0) || !(o.tvd_tol > 0.0)) return sfail(QW_EINVAL, "bad predict options");
+    qw_predict_stats ps;
+    memset(&ps, 0, sizeof ps);
+    hipEvent_t e0, e1;
+    QS_HIP(hipEventCreate(&e0), "hipEventCreate");
+    QS_HIP(hipEventCreate(&e1), "hipEventCreate");
+    // 1. network on every walk
+    std::vector<float> X((size_t)n * kF);
+    int rc = surr_features(s, n, N, T, angles, psi0, X.data());
+    if (rc) return rc;
+    QS_HIP(hipEventRecord(e0, s->stream), "event");
+    rc = surr_forward(s, n, X.data(), out);
+    if (rc) return rc;
+    QS_HIP(hipEventRecord(e1, s->stream), "event");
+    QS_HIP(hipEventSynchronize(e1), "event");
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ps.ms_network = ms;
+    // 2. range check and the seeded re-check sample of every chunk
+    std::vector<uint8_t> fb(n, 0);
+    std::vector<int64_t> sample;
+    const int64_t nch = (n + o.chunk - 1) / o.chunk;
+    uint64_t st = o.seed ^ 0xc0ffeeull;
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t a = c * o.chunk, b = std::min<int64_t>(n, a + o.chunk), len = b - a;
+        std::vector<int64_t> inr;
+        for (int64_t i = a; i < b; ++i) {
+            if (!in_training_range(s, N[i], T[i], angles + 3 * i)) {
+                fb[i] = 1;
+                ps.out_of_range++;
+            } else {
+                inr.push_back(i);
+            }
+        }
+        int64_t k = (int64_t)ceil(o.recheck_frac * (double)len);
+        k = std::min<int64_t>(k, (int64_t)inr.size());
+        for (int64_t j = 0; j < k; ++j) {  // partial Fisher-Yates
+            const int64_t r = j + (int64_t)(splitmix(st) % (uint64_t)(inr.size() - j));
+            std::swap(inr[j], inr[r]);
+            sample.push_back(inr[j]);
+        }
+    }
+    auto plain_bins = [&](const std::vector<int64_t> &ids, std::vector<float> &bins, double &msp) -> int {
+        std::vector<int64_t> n1(ids.size()), t1(ids.size());
+        std::vector<double> a1(3 * ids.size()), p1(4 * ids.size());
+        for (size_t j = 0; j < ids.size(); ++j) {
+            n1[j] = N[ids[j]];
+            t1[j] = T[ids[j]];
+            for (int q = 0; q < 3; ++q) a1[3 * j + q] = angles[3 * ids[j] + q];
+            for (int q = 0; q < 4; ++q) p1[4 * j + q] = psi0[4 * ids[j] + q];
+        }
+        qw_batch_opts bo;
+        memset(&bo, 0, sizeof bo);
+        bo.nbins = kBins;
+        qw_batch_t bt = nullptr;
+        int r = walk_batch_create((int64_t)ids.size(), n1.data(), t1.data(), a1.data(), p1.data(), nullptr, QW_C64, &bo,
+                                  s->stream, &bt);
+        if (r) return sfail(r, "plain walk batch: %s", walk_batch_last_error());
+        r = walk_batch_run(bt);
+        bins.resize(ids.size() * kBins);
+        if (!r) r = walk_batch_binned(bt, bins.data(), 0);
+        qw_batch_info bi;
+        if (!r) r = walk_batch_info(bt, &bi);
+        if (!r) msp += bi.last_run_ms;
+        (void)walk_batch_destroy(bt);
+        if (r) return sfail(r, "plain walk batch: %s", walk_batch_last_error());
+        return QW_OK;
+    };
+    // 3. re-check: a chunk fails when any sampled walk is farther than tvd_tol from the plain walk
+    std::vector<uint8_t> chunk_bad(nch, 0);
+    if (!sample.empty()) {
+        std::vector<float> pb;
+        rc = plain_bins(sample, pb, ps.ms_recheck);
+        if (rc) return rc;
+        for (size_t j = 0; j < sample.size(); ++j) {
+            double tv = 0.0;
+            for (int q = 0; q < kBins; ++q) tv += fabs((double)out[sample[j] * kBins + q] - (double)pb[j * kBins + q]);
+            tv *= 0.5;
+            ps.max_tvd_sampled = std::max(ps.max_tvd_sampled, tv);
+            if (tv > o.tvd_tol) chunk_bad[sample[j] / o.chunk] = 1;
+            // the re-checked walks keep the plain result
+            memcpy(out + sample[j] * kBins, pb.data() + j * kBins, sizeof(float) * kBins);
+        }
+        ps.rechecked = (int64_t)sample.size();
+    }
+    // 4. fallback: failing chunks and out-of-range walks run the plain walk
+    std::vector<int64_t> fall;
+    for (int64_t i = 0; i < n; ++i) {
+        if (chunk_bad[i / o.chunk]) fb[i] = 1;
+        if (fb[i]) fall.push_back(i);
+    }
+    for (int64_t c = 0; c < nch; ++c) ps.failed_chunks += chunk_bad[c];
+    if (!fall.empty()) {
+        std::vector<float> pb;
+        rc = plain_bins(fall, pb, ps.ms_fallback);
+        if (rc) return rc;
+        for (size_t j = 0; j < fall.size(); ++j) memcpy(out + fall[j] * kBins, pb.data() + j * kBins, sizeof(float) * kBins);
+    }
+    ps.fallback = (int64_t)fall.size();
+    if (used_fallback)
+        for (int64_t i = 0; i < n; ++i) used_fallback[i] = fb[i];
+    if (stats) *stats = ps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return QW_OK;
+}
+
+int surr_destroy(qw_surr_t s) {
+    if (!s) return QW_OK;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    free_surr(s);
+    if (e != hipSuccess) return sfail(QW_EHIP, "stream synchronise: %s", hipGetErrorString(e));
+    return QW_OK;
+}
+
+}  // extern "C"

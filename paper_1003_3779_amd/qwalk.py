@@ -33,6 +33,9 @@ ABI_SYMBOLS = (
     "walk_batch_create", "walk_batch_run", "walk_batch_moments", "walk_batch_binned",
     "walk_batch_probabilities", "walk_batch_info", "walk_batch_tune", "walk_batch_destroy",
     "walk_batch_last_error",
+    "surr_num_params", "surr_create", "surr_get_params", "surr_set_params", "surr_features", "surr_forward",
+    "surr_loss_grad", "surr_train", "surr_set_range", "surr_predict", "surr_save", "surr_load",
+    "surr_destroy", "surr_last_error",
 )
 KERNEL_NAMES = ("step", "ring_whole", "ring_tiles", "stream2d")
 
@@ -78,6 +81,23 @@ class BatchInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_floor", ctypes.c_float), ("weight_decay", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class PredictOpts(ctypes.Structure):
+    _fields_ = [("recheck_frac", ctypes.c_double), ("tvd_tol", ctypes.c_double), ("chunk", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int64)]
+
+
+class PredictStats(ctypes.Structure):
+    _fields_ = [("out_of_range", ctypes.c_int64), ("rechecked", ctypes.c_int64), ("failed_chunks", ctypes.c_int64),
+                ("fallback", ctypes.c_int64), ("max_tvd_sampled", ctypes.c_double), ("ms_network", ctypes.c_double),
+                ("ms_recheck", ctypes.c_double), ("ms_fallback", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("renorm_checks", ctypes.c_int64), ("renorms", ctypes.c_int64),
                 ("last_norm", ctypes.c_double), ("launches", ctypes.c_int64), ("updates", ctypes.c_int64)]
@@ -121,12 +141,26 @@ def load():
         "walk_batch_info": [P, P],
         "walk_batch_tune": [P, I32, I32],
         "walk_batch_destroy": [P],
+        "surr_create": [ctypes.c_uint64, P, P],
+        "surr_get_params": [P, P, I32],
+        "surr_set_params": [P, P],
+        "surr_features": [P, I64, P, P, P, P, P],
+        "surr_forward": [P, I64, P, P],
+        "surr_loss_grad": [P, I64, P, P, P, P],
+        "surr_train": [P, I64, P, P, P, P],
+        "surr_set_range": [P, I64, I32, I32],
+        "surr_predict": [P, I64, P, P, P, P, P, P, P, P],
+        "surr_save": [P, ctypes.c_char_p],
+        "surr_load": [ctypes.c_char_p, P, P],
+        "surr_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
-    for name in ("walk_last_error", "walk_batch_last_error"):
+    lib.surr_num_params.argtypes = []
+    lib.surr_num_params.restype = ctypes.c_int64
+    for name in ("walk_last_error", "walk_batch_last_error", "surr_last_error"):
         f = getattr(lib, name)
         f.argtypes = []
         f.restype = ctypes.c_char_p
@@ -384,6 +418,127 @@ class Batch:
             rc = self._lib.walk_batch_destroy(self.h)
             self.h = ctypes.c_void_p()
             _bcheck(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _scheck(rc: int):
+    if rc != QW_OK:
+        msg = load().surr_last_error().decode(errors="replace")
+        raise QWError(rc, msg)
+
+
+def _walk_arrays(N, T, angles, psi0):
+    N = np.ascontiguousarray(np.asarray(N, dtype=np.int64))
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.int64))
+    n = N.size
+    ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).reshape(n, 3))
+    p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128).reshape(n, 2))
+    return n, N, T, ang, p0
+
+
+class Surrogate:
+    """The learned surrogate (surr_*): features -> network -> 512 bins, with
+    the plain walk as fallback and judge."""
+
+    NBINS = 512
+    NFEAT = 32
+
+    def __init__(self, seed: int = 0, stream=None, _handle=None):
+        lib = load()
+        self._lib = lib
+        if _handle is not None:
+            self.h = _handle
+            return
+        h = ctypes.c_void_p()
+        _scheck(lib.surr_create(int(seed), _stream_of(stream), ctypes.byref(h)))
+        self.h = h
+
+    @classmethod
+    def load_file(cls, path: str, stream=None) -> "Surrogate":
+        lib = load()
+        h = ctypes.c_void_p()
+        _scheck(lib.surr_load(path.encode(), _stream_of(stream), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    @staticmethod
+    def num_params() -> int:
+        return int(load().surr_num_params())
+
+    def params(self, bf16_rounded: bool = False) -> np.ndarray:
+        out = np.empty(self.num_params(), dtype=np.float32)
+        _scheck(self._lib.surr_get_params(self.h, out.ctypes.data, int(bool(bf16_rounded))))
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        if a.size != self.num_params():
+            raise ValueError("wrong parameter count")
+        _scheck(self._lib.surr_set_params(self.h, a.ctypes.data))
+
+    def features(self, N, T, angles, psi0) -> np.ndarray:
+        n, N, T, ang, p0 = _walk_arrays(N, T, angles, psi0)
+        out = np.empty((n, self.NFEAT), dtype=np.float32)
+        _scheck(self._lib.surr_features(self.h, n, N.ctypes.data, T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
+                                        out.ctypes.data))
+        return out
+
+    def forward(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+        out = np.empty((X.shape[0], self.NBINS), dtype=np.float32)
+        _scheck(self._lib.surr_forward(self.h, X.shape[0], X.ctypes.data, out.ctypes.data))
+        return out
+
+    def loss_grad(self, X, Y):
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+        Y = np.ascontiguousarray(np.asarray(Y, dtype=np.float32))
+        loss = ctypes.c_double()
+        g = np.empty(self.num_params(), dtype=np.float32)
+        _scheck(self._lib.surr_loss_grad(self.h, X.shape[0], X.ctypes.data, Y.ctypes.data, ctypes.byref(loss),
+                                         g.ctypes.data))
+        return loss.value, g
+
+    def train(self, X_dev, Y_dev, n: int, batch: int = 1024, epochs: int = 10, lr: float = 1e-3,
+              lr_floor: float = 0.05, weight_decay: float = 0.0, seed: int = 0) -> np.ndarray:
+        """X_dev (n x 32) and Y_dev (n x 512): float32 device tensors."""
+        o = TrainOpts(batch, epochs, lr, lr_floor, weight_decay, 0, seed)
+        hist = np.zeros(epochs, dtype=np.float32)
+        _scheck(self._lib.surr_train(self.h, int(n), _ptr_of(X_dev), _ptr_of(Y_dev), ctypes.byref(o),
+                                     hist.ctypes.data))
+        return hist
+
+    def set_range(self, N: int, tmin: int, tmax: int):
+        _scheck(self._lib.surr_set_range(self.h, int(N), int(tmin), int(tmax)))
+
+    def predict(self, N, T, angles, psi0, recheck_frac: float = 0.01, tvd_tol: float = 1e-3, chunk: int = 1024,
+                seed: int = 1):
+        n, N, T, ang, p0 = _walk_arrays(N, T, angles, psi0)
+        out = np.empty((n, self.NBINS), dtype=np.float32)
+        fb = np.zeros(n, dtype=np.uint8)
+        st = PredictStats()
+        o = PredictOpts(recheck_frac, tvd_tol, chunk, seed, 0)
+        _scheck(self._lib.surr_predict(self.h, n, N.ctypes.data, T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
+                                       ctypes.byref(o), out.ctypes.data, fb.ctypes.data, ctypes.byref(st)))
+        return out, fb.astype(bool), st
+
+    def save(self, path: str):
+        _scheck(self._lib.surr_save(self.h, path.encode()))
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            rc = self._lib.surr_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            _scheck(rc)
 
     def __enter__(self):
         return self

@@ -27,7 +27,7 @@ def lib():
 def header_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(walk_\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:walk|surr)_\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_header_lists_the_binding_symbols():

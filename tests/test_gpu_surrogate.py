@@ -1,0 +1,123 @@
+"""The learned surrogate on the GPU: forward pass and gradients against the
+fp64 network oracle (on the GPU's bf16-rounded weights), training, and the
+fallback semantics of surr_predict against the plain batched walk."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+from paper_1003_3779_amd import inputs, qwalk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    qwalk.load()
+    yield
+
+
+def _walk_params(seed, n, N=4097, tmin=256, tmax=2048):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = rng.integers(tmin, tmax, size=n, endpoint=True)
+    ang = inputs.su2_angles(rng, n)
+    psi0 = np.stack([inputs.haar_state(rng, 2) for _ in range(n)])
+    return np.full(n, N, dtype=np.int64), T.astype(np.int64), ang, psi0
+
+
+def _plain_bins(N, T, ang, psi0):
+    b = qwalk.Batch(N, T, ang, psi0, prec=qwalk.QW_C64, nbins=512)
+    b.run()
+    out = b.binned()
+    b.destroy()
+    return out
+
+
+def test_features_match_oracle():
+    N, T, ang, psi0 = _walk_params(1, 300)
+    s = qwalk.Surrogate(seed=1)
+    X = s.features(N, T, ang, psi0)
+    s.destroy()
+    assert np.max(np.abs(X - S.features(N, T, ang, psi0))) <= 2e-6
+
+
+def test_forward_matches_oracle():
+    N, T, ang, psi0 = _walk_params(2, 256)
+    s = qwalk.Surrogate(seed=7)
+    X = s.features(N, T, ang, psi0)
+    q = s.forward(X)
+    p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
+    s.destroy()
+    xr = X.astype(np.float32).view(np.uint32)          # the GPU feeds bf16 inputs
+    xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
+    qr = S.forward(p, xr)["q"]
+    assert np.all(np.abs(q.sum(axis=1) - 1.0) <= 1e-4)
+    # bf16 activations between the layers: a few 1e-3 relative on the logits
+    assert np.max(S.tvd(q, qr)) <= 2e-2
+    assert np.median(S.tvd(q, qr)) <= 5e-3
+
+
+def test_gradients_match_oracle():
+    N, T, ang, psi0 = _walk_params(3, 256)
+    y = _plain_bins(N, T, ang, psi0).astype(np.float64)
+    y /= y.sum(axis=1, keepdims=True)
+    s = qwalk.Surrogate(seed=11)
+    X = s.features(N, T, ang, psi0)
+    loss, g = s.loss_grad(X, y.astype(np.float32))
+    p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
+    s.destroy()
+    xr = X.astype(np.float32).view(np.uint32)
+    xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
+    assert abs(loss - S.loss(p, xr, y)) <= 2e-2 * abs(S.loss(p, xr, y))
+    gr = S.backward(p, xr, y)
+    gg = S.unflatten(g.astype(np.float64))
+    for k in S.ORDER:
+        rel = np.linalg.norm(gg[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
+        assert rel <= 5e-2, (k, rel)
+
+
+def test_training_reduces_loss_and_save_load(tmp_path):
+    torch = pytest.importorskip("torch")
+    n = 4096
+    N, T, ang, psi0 = _walk_params(4, n)
+    y = _plain_bins(N, T, ang, psi0)
+    s = qwalk.Surrogate(seed=3)
+    X = s.features(N, T, ang, psi0)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.from_numpy(y).cuda()
+    hist = s.train(Xd, Yd, n, batch=512, epochs=6, lr=1e-3, seed=5)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.7 * hist[0]
+    q1 = s.forward(X[:64])
+    path = str(tmp_path / "s.qws")
+    s.save(path)
+    s.destroy()
+    s2 = qwalk.Surrogate.load_file(path)
+    assert np.array_equal(s2.forward(X[:64]), q1)
+    s2.destroy()
+
+
+def test_predict_fallback_semantics():
+    """Out-of-range walks and chunks whose re-check fails return exactly the
+    plain walk's bins; the untouched chunks return the network's."""
+    n = 2048
+    N, T, ang, psi0 = _walk_params(5, n)
+    N[:10] = 3001                                     # outside the training range
+    T[10:20] = 4000
+    plain = _plain_bins(N, T, ang, psi0)
+    s = qwalk.Surrogate(seed=9)                       # untrained: every re-check fails
+    out, fb, st = s.predict(N, T, ang, psi0, chunk=512)
+    assert st.out_of_range == 20 and fb.all() and st.failed_chunks == 4
+    assert np.array_equal(out, plain)
+    # an impossible tolerance keeps the network's answer except where re-checked/out of range
+    out2, fb2, st2 = s.predict(N, T, ang, psi0, chunk=512, tvd_tol=2.0)
+    assert st2.failed_chunks == 0 and st2.fallback == 20 and fb2.sum() == 20
+    net = s.forward(s.features(N, T, ang, psi0))
+    keep = ~fb2
+    rechecked = np.all(out2 == plain, axis=1) & keep
+    assert rechecked.sum() >= st2.rechecked - 1     # re-checked walks carry the plain result
+    assert np.array_equal(out2[keep & ~rechecked], net[keep & ~rechecked])
+    s.destroy()

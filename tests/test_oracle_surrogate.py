@@ -1,0 +1,83 @@
+"""Pins of the fp64 surrogate-network oracle: finite differences of its loss
+against its backward pass, and properties of its forward pass."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+
+def _small_params(rng, scale=0.05):
+    p = {}
+    for k in S.ORDER:
+        p[k] = rng.normal(size=S.SHAPES[k]) * scale
+    p["cw"] = rng.normal(size=S.SHAPES["cw"]) * 0.5
+    return p
+
+
+def _batch(rng, B=3):
+    x = np.zeros((B, 32))
+    x[:, :12] = rng.normal(size=(B, 12))
+    y = rng.random(size=(B, S.NBINS)) ** 4
+    y[:, :40] = 0.0                                   # exact zeros exercise 0 log 0
+    y /= y.sum(axis=1, keepdims=True)
+    return x, y
+
+
+def test_forward_is_a_distribution():
+    rng = np.random.default_rng(0)
+    p = _small_params(rng)
+    x, _ = _batch(rng)
+    q = S.forward(p, x)["q"]
+    assert np.all(q > 0) and np.allclose(q.sum(axis=1), 1.0, atol=1e-13)
+
+
+def test_loss_is_kl_and_zero_at_match():
+    rng = np.random.default_rng(1)
+    p = _small_params(rng)
+    x, _ = _batch(rng)
+    q = S.forward(p, x)["q"]
+    assert abs(S.loss(p, x, q)) <= 1e-13            # KL(q || q) = 0
+    _, y = _batch(rng)
+    assert S.loss(p, x, y) > 0.0
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(2)
+    p = _small_params(rng)
+    x, y = _batch(rng)
+    g = S.backward(p, x, y)
+    h = 1e-6
+    for k in S.ORDER:
+        flat = p[k].ravel()
+        for _ in range(3):
+            i = int(rng.integers(0, flat.size))
+            old = flat[i]
+            flat[i] = old + h
+            lp = S.loss(p, x, y)
+            flat[i] = old - h
+            lm = S.loss(p, x, y)
+            flat[i] = old
+            num = (lp - lm) / (2 * h)
+            ana = g[k].ravel()[i]
+            assert abs(num - ana) <= 1e-7 + 1e-5 * abs(num), (k, i, num, ana)
+
+
+def test_flatten_roundtrip():
+    rng = np.random.default_rng(3)
+    p = _small_params(rng)
+    q = S.unflatten(S.flatten(p))
+    for k in S.ORDER:
+        assert np.array_equal(p[k], q[k])
+    assert S.n_params() == S.flatten(p).size
+
+
+def test_features_invariants():
+    """Features depend on the start state only through its global-phase class."""
+    rng = np.random.default_rng(4)
+    psi = rng.normal(size=(5, 2)) + 1j * rng.normal(size=(5, 2))
+    psi /= np.linalg.norm(psi, axis=1, keepdims=True)
+    ang = rng.uniform(0, 3, size=(5, 3))
+    X1 = S.features(np.full(5, 4097), np.full(5, 300), ang, psi)
+    X2 = S.features(np.full(5, 4097), np.full(5, 300), ang, psi * np.exp(1j * 0.7))
+    assert np.allclose(X1, X2, atol=1e-12)
+    assert np.allclose(X1[:, 6] ** 2 + X1[:, 7] ** 2 + X1[:, 8] ** 2, 1.0)
