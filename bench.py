@@ -41,7 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grover2d",
-                    choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d", "ragged_rings"])
+                    choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d", "ragged_rings", "surrogate"])
+    ap.add_argument("--train-walks", type=int, default=1 << 18, help="surrogate: training walks")
+    ap.add_argument("--eval-walks", type=int, default=65536, help="surrogate: held-out walks")
+    ap.add_argument("--epochs", type=int, default=30, help="surrogate: training epochs")
+    ap.add_argument("--save", default="", help="surrogate: write the trained network here")
     ap.add_argument("--rings", type=int, default=4096, help="ragged_rings: number of rings")
     ap.add_argument("--nmax", type=int, default=999999, help="ragged_rings: largest ring")
     ap.add_argument("--tune", action="store_true", help="ragged_rings: run the autotuner first")
@@ -120,6 +124,87 @@ def ragged_rings(args):
     print(json.dumps(out), flush=True)
 
 
+def _surrogate_walks(seed: int, n: int):
+    """N = 4097 rings, T uniform in [256, 2048], SU(2) angles and Haar start states from PCG64(seed)."""
+    import numpy as np
+
+    from paper_1003_3779_amd import inputs
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = rng.integers(256, 2048, size=n, endpoint=True).astype(np.int64)
+    ang = inputs.su2_angles(rng, n)
+    psi0 = np.stack([inputs.haar_state(rng, 2) for _ in range(n)])
+    return np.full(n, 4097, dtype=np.int64), T, ang, psi0
+
+
+def surrogate(args):
+    """Learned surrogate vs the plain batched walk on the same GPU: train on
+    walks the batched simulator generates (seed 5), evaluate on held-out
+    parameter sets (seed 55).  Reports walks/s of both paths, the surrogate's
+    TVD to the plain walk on every held-out walk and its fallback rate."""
+    import numpy as np
+    import torch
+
+    from paper_1003_3779_amd import qwalk
+
+    def plain(N, T, ang, psi0):
+        b = qwalk.Batch(N, T, ang, psi0, prec=qwalk.QW_C64, nbins=512)
+        b.run()
+        bins = b.binned()
+        ms = b.info().last_run_ms
+        b.destroy()
+        return bins, ms
+
+    t0 = time.perf_counter()
+    Ntr, Ttr, Atr, Ptr = _surrogate_walks(5, args.train_walks)
+    Ytr, gen_ms = plain(Ntr, Ttr, Atr, Ptr)
+    s = qwalk.Surrogate(seed=5)
+    Xtr = s.features(Ntr, Ttr, Atr, Ptr)
+    Xd, Yd = torch.from_numpy(Xtr).cuda(), torch.from_numpy(Ytr).cuda()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = s.train(Xd, Yd, args.train_walks, batch=1024, epochs=args.epochs, lr=1e-3, lr_floor=0.02, seed=5)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del Xd, Yd
+    if args.save:
+        s.save(args.save)
+    Nev, Tev, Aev, Pev = _surrogate_walks(55, args.eval_walks)
+    # the plain walk: best variant (whole rings in registers), one persistent launch
+    plain(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])     # warm-up
+    tp0 = time.perf_counter()
+    Yev, plain_ms = plain(Nev, Tev, Aev, Pev)
+    tp1 = time.perf_counter()
+    net = s.forward(s.features(Nev, Tev, Aev, Pev))
+    tvd = 0.5 * np.abs(net.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
+    s.predict(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])   # warm-up
+    ts0 = time.perf_counter()
+    out, fb, st = s.predict(Nev, Tev, Aev, Pev)
+    ts1 = time.perf_counter()
+    tvd_out = 0.5 * np.abs(out.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
+    s.destroy()
+    plain_wps = args.eval_walks / (tp1 - tp0)
+    surr_wps = args.eval_walks / (ts1 - ts0)
+    res = {
+        "metric": "surrogate vs plain walks/s at TVD<=1e-3", "value": surr_wps, "unit": "walks/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 (network), f32 (plain walk)",
+        "data": "synthetic",
+        "config": {"workload": f"surrogate: rings N=4097, T in [256, 2048], SU(2), Haar start; "
+                               f"{args.train_walks} training walks (seed 5), {args.eval_walks} held-out (seed 55)"},
+        "plain_walks_per_s": plain_wps, "plain_kernel_ms": plain_ms,
+        "surrogate_walks_per_s": surr_wps, "speedup": surr_wps / plain_wps,
+        "fallback_rate": float(fb.mean()), "failed_chunks": int(st.failed_chunks),
+        "recheck_max_tvd": st.max_tvd_sampled,
+        "network_ms": st.ms_network, "recheck_ms": st.ms_recheck, "fallback_ms": st.ms_fallback,
+        "tvd_network": {"median": float(np.median(tvd)), "p90": float(np.quantile(tvd, 0.9)),
+                        "p99": float(np.quantile(tvd, 0.99)), "max": float(tvd.max()),
+                        "frac_le_1e-3": float(np.mean(tvd <= 1e-3)), "frac_le_1e-2": float(np.mean(tvd <= 1e-2))},
+        "tvd_output_max": float(tvd_out.max()),
+        "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+        "train_s": t2 - t1, "datagen_ms": gen_ms, "setup_s": t1 - t0,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def traffic_from_profile(kernel_sha: str):
     """Measured HBM bytes per launch of the dominant kernel (rocprofv3 PMC),
     if the committed summary was taken on this exact kernel source."""
@@ -168,6 +253,9 @@ def main():
         return
     if args.workload == "ragged_rings":
         ragged_rings(args)
+        return
+    if args.workload == "surrogate":
+        surrogate(args)
         return
     cfg = inputs.config(args.workload)
     prec_name = args.prec or cfg["prec"]
