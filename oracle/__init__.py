@@ -46,26 +46,31 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def _open(path: str):
+    """Open an oracle library and declare its signatures."""
+    lib = ctypes.CDLL(path)
+    i64, i32, dp, ip = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+    lib.orc_coin.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.orc_coin.restype = i32
+    lib.orc_evolve.argtypes = [i64, i64, i32, ip, dp, dp, i64, i32, i64, i64, i64]
+    lib.orc_evolve.restype = i32
+    lib.orc_evolve_inverse.argtypes = [i64, i64, i32, ip, dp, dp, i64]
+    lib.orc_evolve_inverse.restype = i32
+    lib.orc_prob.argtypes = [i64, i32, dp, dp]
+    lib.orc_prob.restype = None
+    lib.orc_norm.argtypes = [i64, dp]
+    lib.orc_norm.restype = ctypes.c_double
+    lib.orc_bin.argtypes = [i64, i64, dp, i32, dp]
+    lib.orc_bin.restype = i32
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
-        i64, i32, dp, ip = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
-        lib.orc_coin.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
-        lib.orc_coin.restype = i32
-        lib.orc_evolve.argtypes = [i64, i64, i32, ip, dp, dp, i64, i32, i64, i64, i64]
-        lib.orc_evolve.restype = i32
-        lib.orc_evolve_inverse.argtypes = [i64, i64, i32, ip, dp, dp, i64]
-        lib.orc_evolve_inverse.restype = i32
-        lib.orc_prob.argtypes = [i64, i32, dp, dp]
-        lib.orc_prob.restype = None
-        lib.orc_norm.argtypes = [i64, dp]
-        lib.orc_norm.restype = ctypes.c_double
-        lib.orc_bin.argtypes = [i64, i64, dp, i32, dp]
-        lib.orc_bin.restype = i32
-        _lib = lib
+        _lib = _open(_LIB_PATH)
     return _lib
 
 

@@ -1,0 +1,92 @@
+"""Planted mistakes in a copy of the oracle must be caught by the pins.
+
+Each mutant is qw_oracle.c with one plausible error (a sign, an index, a
+transposed operand, a dropped term, an off-by-one window), compiled into a
+temporary library; the oracle module is pointed at it and a battery of the
+pin tests runs.  At least one pin must fail for every mutant.  CPU only.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_3779_amd import inputs
+from tests import test_oracle_pins as P
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "qw_oracle.c")
+
+MUTANTS = {
+    "shift_sign": ("int64_t sx = wrap(x - disp[2 * c], Lx);", "int64_t sx = wrap(x + disp[2 * c], Lx);"),
+    "shift_y_index": ("int64_t sy = wrap(y - disp[2 * c + 1], Ly);", "int64_t sy = wrap(y - disp[2 * c], Ly);"),
+    "coin_transposed": ("acc = c_add(acc, c_mul(C[c * d + cp], src[cp]));",
+                        "acc = c_add(acc, c_mul(C[cp * d + c], src[cp]));"),
+    "dropped_term": ("for (cp = 0; cp < d; cp++)\n                    acc = c_add(acc, c_mul(C[c * d + cp], src[cp]));",
+                     "for (cp = 0; cp < d - 1; cp++)\n                    acc = c_add(acc, c_mul(C[c * d + cp], src[cp]));"),
+    "cmul_sign": ("r.im = a.re * b.im + a.im * b.re;", "r.im = a.re * b.im - a.im * b.re;"),
+    "su2_sign": ("C[2] = c_make(-ec.re * st, ec.im * st);", "C[2] = c_make(ec.re * st, ec.im * st);"),
+    "su2_conj": ("C[3] = c_make(ep.re * ct, -ep.im * ct);", "C[3] = c_make(ep.re * ct, ep.im * ct);"),
+    "grover_weight": ("C[a * d + b] = c_make(2.0 / d - (a == b ? 1.0 : 0.0), 0.0);",
+                      "C[a * d + b] = c_make(1.0 / d - (a == b ? 1.0 : 0.0), 0.0);"),
+    "hh_index": ("h[a >> 1][b >> 1] * h[a & 1][b & 1]", "h[a >> 1][b & 1] * h[a & 1][b >> 1]"),
+    "prob_drops_imag": ("s += re * re + im * im;", "s += re * re;"),
+    "window_radius": ("int64_t r = windowed ? t0 + s + 1 : -1;", "int64_t r = windowed ? t0 + s : -1;"),
+    "inverse_no_conj": ("c_mul(c_conj(C[cp * d + c]), a[(sy * Lx + sx) * d + cp])",
+                        "c_mul(C[cp * d + c], a[(sy * Lx + sx) * d + cp])"),
+    "inverse_shift_sign": ("int64_t sx = wrap(x + disp[2 * cp], Lx);", "int64_t sx = wrap(x - disp[2 * cp], Lx);"),
+    "bin_left_offset": ("int64_t offl = -(h - b) * w + k;", "int64_t offl = -(h - b) * w + k + 1;"),
+}
+
+ONE = lambda rng: inputs.haar_unitary(rng, 2)          # noqa: E731
+FOUR = lambda rng: inputs.haar_unitary(rng, 4)         # noqa: E731
+
+BATTERY = [
+    lambda: P.test_dense_matrix_power_ring(5, "haar", ONE),
+    lambda: P.test_dense_matrix_power_ring(8, "su2", P.COIN_CASES_1D[1][1]),
+    lambda: P.test_dense_matrix_power_torus((4, 5), "PAIR", "haar", FOUR),
+    lambda: P.test_dense_matrix_power_torus((4, 5), "DIAG", "grover", P.COIN_CASES_2D[0][1]),
+    lambda: P.test_dense_matrix_power_torus((4, 5), "EQ8", "hh", P.COIN_CASES_2D[1][1]),
+    lambda: P.test_dense_matrix_power_windowed_start(),
+    lambda: P.test_path_sum_ring(5),
+    lambda: P.test_hh_is_kron(),
+    lambda: P.test_su2_is_unitary_and_special(),
+    lambda: P.test_norm_conserved_torus(),
+    lambda: P.test_site_parity_and_light_cone("PAIR"),
+    lambda: P.test_exact_reversal("PAIR"),
+    lambda: P.test_inverse_matches_matrix_inverse(),
+    lambda: P.test_binning_symmetric_and_complete(),
+]
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
+    c = tmp_path / f"{name}.c"
+    c.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.check_call(["gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                           str(c), "-o", str(so), "-lm"])
+    return str(so)
+
+
+def _failures():
+    n = 0
+    for check in BATTERY:
+        try:
+            check()
+        except (AssertionError, ValueError, RuntimeError):
+            n += 1
+    return n
+
+
+def test_unmutated_oracle_passes_the_battery():
+    assert _failures() == 0
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path, monkeypatch):
+    old, new = MUTANTS[name]
+    lib = oracle._open(_build(tmp_path, name, old, new))
+    monkeypatch.setattr(oracle, "_lib", lib)
+    assert _failures() >= 1, f"no pin caught the planted mistake {name}"
