@@ -90,8 +90,10 @@ def ragged_rings(args):
     from paper_1003_3779_amd import inputs, qwalk
     p = inputs.ragged_ring_batch(4, args.rings, nmin=1001, nmax=args.nmax)
     b = qwalk.Batch(p["N"], p["T"], p["angles"], p["psi0"], prec=qwalk.QW_C64, nbins=512)
+    print(f"# ragged rings: {args.rings} walks, est. {b.info().est_updates:.3e} updates", file=sys.stderr, flush=True)
     if args.tune:
         b.tune(samples=8, save=True)
+        print(f"# ragged rings: tuned {[b.info().bucket_cfg[k] for k in range(3)]}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         b.run()
         b.info()
@@ -162,13 +164,21 @@ def surrogate(args):
     Xd, Yd = torch.from_numpy(Xtr).cuda(), torch.from_numpy(Ytr).cuda()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hist = s.train(Xd, Yd, args.train_walks, batch=1024, epochs=args.epochs, lr=1e-3, lr_floor=0.02, seed=5)
+    print(f"# surrogate: {args.train_walks} training walks generated in {gen_ms:.0f} ms", file=sys.stderr, flush=True)
+    hist = []
+    per = 5
+    for e0 in range(0, args.epochs, per):
+        ne = min(per, args.epochs - e0)
+        hist += list(s.train(Xd, Yd, args.train_walks, batch=1024, epochs=ne, lr=1e-3, lr_floor=0.02, seed=5,
+                             epoch_offset=e0, schedule_epochs=args.epochs))
+        print(f"# surrogate: epoch {e0 + ne}/{args.epochs} loss {hist[-1]:.4e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del Xd, Yd
     if args.save:
         s.save(args.save)
     Nev, Tev, Aev, Pev = _surrogate_walks(55, args.eval_walks)
+    print("# surrogate: evaluating", file=sys.stderr, flush=True)
     # the plain walk: best variant (whole rings in registers), one persistent launch
     plain(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])     # warm-up
     tp0 = time.perf_counter()

@@ -298,8 +298,11 @@ typedef struct {
     float lr;             /* peak Adam learning rate (cosine decay to lr * lr_floor) */
     float lr_floor;
     float weight_decay;   /* added to the gradient: g + wd * p */
-    int32_t reserved;
+    int32_t epoch_offset; /* epochs already run of a longer schedule (the learning rate
+                             follows epoch_offset + e of schedule_epochs) */
     uint64_t seed;        /* shuffling */
+    int32_t schedule_epochs;  /* length of the cosine schedule; 0 = epochs */
+    int32_t reserved;
 } qw_train_opts;
 
 typedef struct {

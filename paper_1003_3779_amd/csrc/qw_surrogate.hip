@@ -769,15 +769,16 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_
     }
     std::vector<int32_t> hp(n);
     std::vector<float> hl(steps);
-    uint64_t st = o->seed ^ 0x7a11ull;
+    uint64_t st = (o->seed ^ 0x7a11ull) + 0x9e37ull * (uint64_t)o->epoch_offset;
     hipError_t e = hipSuccess;
     for (int ep = 0; ep < o->epochs && e == hipSuccess; ++ep) {
         for (int64_t i = 0; i < n; ++i) hp[i] = (int32_t)i;
         for (int64_t i = n - 1; i > 0; --i) std::swap(hp[i], hp[splitmix(st) % (uint64_t)(i + 1)]);
         e = hipMemcpyAsync(perm, hp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s->stream);
-        // cosine learning-rate decay over the run
+        // cosine learning-rate decay over the schedule
+        const int sched = o->schedule_epochs > 0 ? o->schedule_epochs : o->epochs;
         for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
-            const double prog = ((double)ep * steps + k) / ((double)o->epochs * steps);
+            const double prog = std::min(1.0, ((double)(o->epoch_offset + ep) * steps + k) / ((double)sched * steps));
             const float lr = (float)(o->lr * (o->lr_floor + (1.0 - o->lr_floor) * 0.5 * (1.0 + cos(3.14159265358979 * prog))));
             hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, X, Y, (const int32_t *)(perm + k * B), B, s->xb,
                                s->yb);

@@ -83,8 +83,8 @@ class BatchInfo(ctypes.Structure):
 
 class TrainOpts(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
-                ("lr_floor", ctypes.c_float), ("weight_decay", ctypes.c_float), ("reserved", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("lr_floor", ctypes.c_float), ("weight_decay", ctypes.c_float), ("epoch_offset", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("schedule_epochs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PredictOpts(ctypes.Structure):
@@ -509,9 +509,10 @@ class Surrogate:
         return loss.value, g
 
     def train(self, X_dev, Y_dev, n: int, batch: int = 1024, epochs: int = 10, lr: float = 1e-3,
-              lr_floor: float = 0.05, weight_decay: float = 0.0, seed: int = 0) -> np.ndarray:
+              lr_floor: float = 0.05, weight_decay: float = 0.0, seed: int = 0, epoch_offset: int = 0,
+              schedule_epochs: int = 0) -> np.ndarray:
         """X_dev (n x 32) and Y_dev (n x 512): float32 device tensors."""
-        o = TrainOpts(batch, epochs, lr, lr_floor, weight_decay, 0, seed)
+        o = TrainOpts(batch, epochs, lr, lr_floor, weight_decay, epoch_offset, seed, schedule_epochs, 0)
         hist = np.zeros(epochs, dtype=np.float32)
         _scheck(self._lib.surr_train(self.h, int(n), _ptr_of(X_dev), _ptr_of(Y_dev), ctypes.byref(o),
                                      hist.ctypes.data))
