@@ -162,6 +162,7 @@ def surrogate(args):
     s = qwalk.Surrogate(seed=5)
     Xtr = s.features(Ntr, Ttr, Atr, Ptr)
     Xd, Yd = torch.from_numpy(Xtr).cuda(), torch.from_numpy(Ytr).cuda()
+    Td = torch.from_numpy(Ttr.astype(np.int32)).cuda()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"# surrogate: {args.train_walks} training walks generated in {gen_ms:.0f} ms", file=sys.stderr, flush=True)
@@ -169,12 +170,12 @@ def surrogate(args):
     per = 5
     for e0 in range(0, args.epochs, per):
         ne = min(per, args.epochs - e0)
-        hist += list(s.train(Xd, Yd, args.train_walks, batch=1024, epochs=ne, lr=1e-3, lr_floor=0.02, seed=5,
+        hist += list(s.train(Xd, Yd, Td, args.train_walks, batch=1024, epochs=ne, lr=1e-3, lr_floor=0.02, seed=5,
                              epoch_offset=e0, schedule_epochs=args.epochs))
         print(f"# surrogate: epoch {e0 + ne}/{args.epochs} loss {hist[-1]:.4e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    del Xd, Yd
+    del Xd, Yd, Td
     if args.save:
         s.save(args.save)
     Nev, Tev, Aev, Pev = _surrogate_walks(55, args.eval_walks)
@@ -184,7 +185,7 @@ def surrogate(args):
     tp0 = time.perf_counter()
     Yev, plain_ms = plain(Nev, Tev, Aev, Pev)
     tp1 = time.perf_counter()
-    net = s.forward(s.features(Nev, Tev, Aev, Pev))
+    net = s.forward(s.features(Nev, Tev, Aev, Pev), Tev)
     tvd = 0.5 * np.abs(net.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
     s.predict(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])   # warm-up
     ts0 = time.perf_counter()

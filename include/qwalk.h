@@ -282,8 +282,11 @@ const char *walk_batch_last_error(void);
  * symmetric bins (the binning of walk_batch_binned):
  *   h1 = relu(x W1^T + b1) (512 x 32), h2 = relu(h1 W2^T + b2) (1024 x 512),
  *   h3 = relu(h2 W3^T + b3) (1024 x 1024), z4 = h3 W4^T + b4 (1024 x 1024) read
- *   as 2 channels x 512 bins, l = conv1d(z4; 9 taps, zero padding) + cb,
- *   q = softmax(l).
+ *   as 2 channels x 512 cells, l = conv1d(z4; 9 taps, zero padding) + cb,
+ *   q = softmax(l), a density over 512 cells of the scaled coordinate
+ *   k / (T + 1) of the walk's sites x0 - T + 2k, k = 0..T; p = the 512 bins
+ *   this density puts on the ring (each cell's mass spread uniformly over its
+ *   share of the T + 1 sites, each site's mass to its bin).
  * The GEMMs run on MFMA with bf16 operands and fp32 accumulation; the head,
  * softmax, KL(y || q) loss and its gradient in fp32; Adam keeps fp32 master
  * weights.  Parameters are one fp32 vector in the order W1, b1, W2, b2, W3,
@@ -335,16 +338,18 @@ int surr_set_params(qw_surr_t s, const float *in);
  * b' = b e^{-i arg a}; T/N; cos and sin of arg b - arg a + chi - phi; zeros. */
 int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles,
                   const double *psi0, float *out);
-/* Network output q (n x 512, host) for features X (n x 32, host). */
-int surr_forward(qw_surr_t s, int64_t n, const float *X, float *out);
+/* Network output p (n x 512 bins, host) for features X (n x 32, host) of walks
+ * of T steps (n int32, host). */
+int surr_forward(qw_surr_t s, int64_t n, const float *X, const int32_t *T, float *out);
 /* Mean loss and the gradient of every parameter (host, surr_num_params()) for
- * n <= 4096 samples (X: n x 32, Y: n x 512 targets, host). */
-int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, double *loss, float *grads);
-/* Train on n samples held on the device (X: n x 32, Y: n x 512 floats);
- * epoch_loss (host, epochs floats, may be NULL) receives the mean loss of
- * every epoch.  Synchronises. */
-int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_train_opts *opts,
-               float *epoch_loss);
+ * n <= 4096 samples (X: n x 32, Y: n x 512 targets, T: n steps; host). */
+int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, const int32_t *T, double *loss,
+                   float *grads);
+/* Train on n samples held on the device (X: n x 32, Y: n x 512 floats, T: n
+ * int32 steps); epoch_loss (host, epochs floats, may be NULL) receives the
+ * mean loss of every epoch.  Synchronises. */
+int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int32_t *T,
+               const qw_train_opts *opts, float *epoch_loss);
 /* Inputs accepted without fallback: ring size N, T in [tmin, tmax]. */
 int surr_set_range(qw_surr_t s, int64_t N, int32_t tmin, int32_t tmax);
 /* Binned P of n walks (host arrays as for walk_batch_create; x0 = N/2) into

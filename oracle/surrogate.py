@@ -7,14 +7,20 @@ numpy, used to check the GPU forward pass, loss and gradients; it shares no
 code with the HIP path.  The parameters are passed in as a dict of arrays (the
 GPU's bf16-rounded weights when comparing with it).
 
-Network (input F = 32 features, zero-padded):
+Network (input F = 32 features, zero-padded; T = steps of the walk):
     h1 = relu(x W1^T + b1)          W1: 512 x 32
     h2 = relu(h1 W2^T + b2)         W2: 1024 x 512
     h3 = relu(h2 W3^T + b3)         W3: 1024 x 1024
     z4 = h3 W4^T + b4               W4: 1024 x 1024, read as 2 channels x 512 positions
     l[i] = cb + sum_c sum_j cw[c, j] z4[c, i + j - 4]   (1D conv, 9 taps, zero padding)
-    q = softmax(l)                  over the 512 bins
-Loss: mean over the batch of KL(y || q) = sum_i y_i (log y_i - log q_i), with
+    q = softmax(l)                  a density over 512 cells of the scaled coordinate
+    p = R(T) q                      the 512 position bins
+The walk after T steps lives on the sites x0 - T + 2k, k = 0..T.  Cell j of q
+covers k in [j (T+1)/512, (j+1)(T+1)/512) (site k is the unit interval
+[k, k+1)), its mass spread uniformly over that interval; R(T) hands each site's
+share to the bin that holds it (the binning of the ring distributions: bins of
+w = 8 sites, the start site half to each of the two middle bins).
+Loss: mean over the batch of KL(y || p) = sum_b y_b (log y_b - log p_b), with
 0 log 0 = 0.
 """
 from __future__ import annotations
@@ -22,6 +28,8 @@ from __future__ import annotations
 import numpy as np
 
 NBINS = 512
+NCELLS = 512
+BIN_SITES = 8           # sites per bin of the N = 4097 rings (floor((N - 1) / 2 / 256))
 CONV_TAPS = 9
 CONV_PAD = 4
 SHAPES = {
@@ -63,7 +71,34 @@ def _conv(z4, cw, cb):
     return out
 
 
-def forward(p: dict, x: np.ndarray) -> dict:
+def site_bin(dx: int, w: int = BIN_SITES, nbins: int = NBINS):
+    """[(bin, share)] of the site at offset dx from the start (symmetric binning)."""
+    h = nbins // 2
+    if dx == 0:
+        return [(h - 1, 0.5), (h, 0.5)]
+    if dx < 0:
+        k = (-dx - 1) // w
+        return [(h - 1 - k, 1.0)] if k < h else []
+    k = (dx - 1) // w
+    return [(h + k, 1.0)] if k < h else []
+
+
+def resample_matrix(T: int, w: int = BIN_SITES) -> np.ndarray:
+    """R(T): NBINS x NCELLS, column j = how cell j's mass lands in the bins."""
+    R = np.zeros((NBINS, NCELLS))
+    clen = (T + 1) / NCELLS
+    for j in range(NCELLS):
+        a, b = j * clen, (j + 1) * clen
+        for k in range(int(np.floor(a)), int(np.ceil(b))):
+            ov = min(b, k + 1) - max(a, k)
+            if ov <= 0:
+                continue
+            for bi, sh in site_bin(-T + 2 * k, w):
+                R[bi, j] += sh * ov / clen
+    return R
+
+
+def forward(p: dict, x: np.ndarray, T) -> dict:
     x = np.asarray(x, dtype=np.float64)
     a = {"x": x}
     a["z1"] = x @ p["W1"].T + p["b1"]
@@ -77,24 +112,32 @@ def forward(p: dict, x: np.ndarray) -> dict:
     m = a["l"].max(axis=1, keepdims=True)
     e = np.exp(a["l"] - m)
     a["q"] = e / e.sum(axis=1, keepdims=True)
-    a["logq"] = (a["l"] - m) - np.log(e.sum(axis=1, keepdims=True))
+    T = np.broadcast_to(np.asarray(T, dtype=np.int64), (x.shape[0],))
+    a["R"] = [resample_matrix(int(t)) for t in T]
+    a["p"] = np.stack([R @ q for R, q in zip(a["R"], a["q"])])
     return a
 
 
-def loss(p: dict, x: np.ndarray, y: np.ndarray) -> float:
-    a = forward(p, x)
+def _kl_rows(y, pb):
     y = np.asarray(y, dtype=np.float64)
-    ylogy = np.where(y > 0, y * np.log(np.where(y > 0, y, 1.0)), 0.0)
-    return float(np.mean(np.sum(ylogy - y * a["logq"], axis=1)))
+    safe = np.where(y > 0, y, 1.0)
+    return np.sum(np.where(y > 0, y * (np.log(safe) - np.log(np.where(y > 0, pb, 1.0))), 0.0), axis=1)
 
 
-def backward(p: dict, x: np.ndarray, y: np.ndarray) -> dict:
+def loss(p: dict, x: np.ndarray, y: np.ndarray, T) -> float:
+    a = forward(p, x, T)
+    return float(np.mean(_kl_rows(y, a["p"])))
+
+
+def backward(p: dict, x: np.ndarray, y: np.ndarray, T) -> dict:
     """Gradients of loss() with respect to every parameter (chain rule written out)."""
-    a = forward(p, x)
+    a = forward(p, x, T)
     y = np.asarray(y, dtype=np.float64)
     B = x.shape[0]
-    # d/dl of sum_i -y_i log softmax(l)_i = q * sum(y) - y
-    dl = (a["q"] * y.sum(axis=1, keepdims=True) - y) / B
+    # dL/dp_b = -y_b / p_b; dL/dq = R^T dL/dp; softmax: dl = q (dq - <q, dq>)
+    gp = np.where(y > 0, -y / np.where(y > 0, a["p"], 1.0), 0.0) / B
+    dq = np.stack([R.T @ g for R, g in zip(a["R"], gp)])
+    dl = a["q"] * (dq - np.sum(a["q"] * dq, axis=1, keepdims=True))
     g = {}
     g["cb"] = np.array([dl.sum()])
     z4 = a["z4"].reshape(B, 2, NBINS)

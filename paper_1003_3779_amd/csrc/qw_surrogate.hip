@@ -3,14 +3,15 @@
 // position distribution in 512 symmetric bins, trained on walks produced by
 // the batched simulator, with the plain walk as its fallback and its judge.
 //
-// Network (x: 32 features, 12 used, the rest zero):
+// Network (x: 32 features, 12 used, the rest zero; T the walk's steps):
 //   h1 = relu(x W1^T + b1)      512 x 32        (GEMMs: bf16 operands on
 //   h2 = relu(h1 W2^T + b2)     1024 x 512       MFMA, fp32 accumulation)
 //   h3 = relu(h2 W3^T + b3)     1024 x 1024
-//   z4 = h3 W4^T + b4           1024 x 1024, read as 2 channels x 512 bins
+//   z4 = h3 W4^T + b4           1024 x 1024, read as 2 channels x 512 cells
 //   l  = conv1d(z4; 2 -> 1 channel, 9 taps, zero padding) + cb
-//   q  = softmax(l)
-// Loss: mean over the batch of KL(y || q).  Training: Adam on fp32 master
+//   q  = softmax(l)             a density over 512 cells of the walk's support
+//   p  = R(T) q                 the 512 position bins (see the head below)
+// Loss: mean over the batch of KL(y || p).  Training: Adam on fp32 master
 // weights; the kernels read bf16 copies (and transposed copies for dX).
 #include "qwalk.h"
 #include "qw_internal.h"
@@ -175,14 +176,47 @@ __global__ void k_colsum(const float *__restrict__ dz, int B, int N, float *__re
 }
 
 // ---------------------------------------------------------------- conv head
-// One block (256 threads) per sample: l = conv(z4) + cb, q = softmax(l); with
-// targets: dl = (q sum(y) - y) / B and the per-sample loss.
+// The walk after T steps lives on the sites x0 - T + 2k, k = 0..T.  The network
+// describes that support in a scaled coordinate: cell j of q = softmax(l)
+// covers k in [j (T+1)/512, (j+1)(T+1)/512) (site k being the unit interval
+// [k, k+1)), with its mass spread uniformly; each site then hands its mass to
+// the position bin that holds it (bins of w sites, the start site half to each
+// of the two middle bins).  So the support's growth with T is geometry, not
+// something the network has to learn.
+constexpr int kCells = 512;
+constexpr int kMaxSites = 4096;  // T is clamped to kMaxSites - 1 (walks that long are outside any training range)
+
+// bins of the site at offset dx: first bin and share; second bin (or -1)
+__device__ __forceinline__ void site_bins(int dx, int w, int &b0, float &s0, int &b1) {
+    const int h = kBins / 2;
+    b1 = -1;
+    if (dx == 0) {
+        b0 = h - 1;
+        s0 = 0.5f;
+        b1 = h;
+    } else if (dx < 0) {
+        const int k = (-dx - 1) / w;
+        b0 = k < h ? h - 1 - k : -1;
+        s0 = 1.0f;
+    } else {
+        const int k = (dx - 1) / w;
+        b0 = k < h ? h + k : -1;
+        s0 = 1.0f;
+    }
+}
+
+// One block (256 threads) per sample: l = conv(z4) + cb, q = softmax(l),
+// p = the binned distribution; with targets y: the per-sample KL(y || p) and
+// dl = dL/dl (already divided by Bscale).
 __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, const float *__restrict__ cw,
-                                                  const float *__restrict__ cb, float *__restrict__ q,
-                                                  const float *__restrict__ y, float *__restrict__ dl,
-                                                  float *__restrict__ loss_row, int B) {
+                                                  const float *__restrict__ cb, const int32_t *__restrict__ Tst,
+                                                  int w, float *__restrict__ pout, const float *__restrict__ y,
+                                                  float *__restrict__ dl, float *__restrict__ loss_row, int Bscale) {
     __shared__ float sz[2][kBins + 2 * kPad];
     __shared__ float red[256];
+    __shared__ float sq[kCells];
+    __shared__ float sm[kMaxSites];   // site masses, then site gradients
+    __shared__ float sg[kBins];       // bin gradients
     const int b = blockIdx.x, t = threadIdx.x;
     const float *zr = z4 + (int64_t)b * kZ4;
     for (int i = t; i < kBins + 2 * kPad; i += 256) {
@@ -221,37 +255,97 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     }
     const float den = red[0];
     __syncthreads();
-    const float lse = logf(den);
     const float q0 = e0 / den, q1 = e1 / den;
-    if (q) {
-        q[(int64_t)b * kBins + t] = q0;
-        q[(int64_t)b * kBins + t + 256] = q1;
-    }
-    if (y) {
-        const float y0 = y[(int64_t)b * kBins + t], y1 = y[(int64_t)b * kBins + t + 256];
-        // loss_b = sum y log y - sum y (l - mx - lse)
-        float lv = 0.0f;
-        if (y0 > 0.0f) lv += y0 * logf(y0);
-        if (y1 > 0.0f) lv += y1 * logf(y1);
-        lv -= y0 * (l[0] - mx - lse) + y1 * (l[1] - mx - lse);
-        red[t] = y0 + y1;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) red[t] += red[t + s];
-            __syncthreads();
+    sq[t] = q0;
+    sq[t + 256] = q1;
+    int T = Tst[b];
+    T = T < 0 ? 0 : (T > kMaxSites - 1 ? kMaxSites - 1 : T);
+    const int ns = T + 1;
+    const double clen = (double)ns / kCells;
+    __syncthreads();
+    // site masses: m_k = sum over the cells overlapping [k, k+1) of q_j * overlap / clen
+    for (int k = t; k < ns; k += 256) {
+        const int j0 = (int)floor(k / clen);
+        double acc = 0.0;
+        for (int j = j0; j < kCells && j * clen < k + 1; ++j) {
+            const double lo = fmax(j * clen, (double)k), hi = fmin((j + 1) * clen, (double)(k + 1));
+            if (hi > lo) acc += (double)sq[j] * (hi - lo) / clen;
         }
-        const float ysum = red[0];
-        __syncthreads();
-        dl[(int64_t)b * kBins + t] = (q0 * ysum - y0) / (float)B;
-        dl[(int64_t)b * kBins + t + 256] = (q1 * ysum - y1) / (float)B;
-        red[t] = lv;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) red[t] += red[t + s];
-            __syncthreads();
-        }
-        if (t == 0) loss_row[b] = red[0];
+        sm[k] = (float)acc;
     }
+    __syncthreads();
+    // bins: each bin gathers its sites (offsets of the parity of T) in a fixed order
+    const int hb = kBins / 2;
+    float pb[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int bin = t + 256 * hh;
+        int lo, hi;
+        if (bin < hb) {
+            lo = -(hb - bin) * w;
+            hi = -(hb - bin - 1) * w - 1;
+        } else {
+            lo = (bin - hb) * w + 1;
+            hi = (bin - hb + 1) * w;
+        }
+        float acc = 0.0f;
+        if (bin == hb - 1 || bin == hb) {  // half of the start site
+            if ((T & 1) == 0) acc += 0.5f * sm[T / 2];
+        }
+        for (int dx = lo; dx <= hi; ++dx) {
+            const int kk = T + dx;
+            if ((kk & 1) || kk < 0 || kk > 2 * T) continue;
+            acc += sm[kk >> 1];
+        }
+        pb[hh] = acc;
+        if (pout) pout[(int64_t)b * kBins + bin] = acc;
+    }
+    if (!y) return;  // uniform across the block
+    const float y0 = y[(int64_t)b * kBins + t], y1 = y[(int64_t)b * kBins + t + 256];
+    float lv = 0.0f;
+    if (y0 > 0.0f) lv += y0 * (logf(y0) - logf(fmaxf(pb[0], 1e-30f)));
+    if (y1 > 0.0f) lv += y1 * (logf(y1) - logf(fmaxf(pb[1], 1e-30f)));
+    sg[t] = y0 > 0.0f ? -y0 / fmaxf(pb[0], 1e-30f) / (float)Bscale : 0.0f;
+    sg[t + 256] = y1 > 0.0f ? -y1 / fmaxf(pb[1], 1e-30f) / (float)Bscale : 0.0f;
+    red[t] = lv;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) loss_row[b] = red[0];
+    // site gradients (a site lies in one bin, the start site half in each middle bin)
+    for (int k = t; k < ns; k += 256) {
+        int b0, b1;
+        float s0;
+        site_bins(-T + 2 * k, w, b0, s0, b1);
+        float gk = b0 >= 0 ? s0 * sg[b0] : 0.0f;
+        if (b1 >= 0) gk += 0.5f * sg[b1];
+        sm[k] = gk;
+    }
+    __syncthreads();
+    // dq_j = sum over the sites overlapping cell j of g_k * overlap / clen
+    float dq[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int j = t + 256 * hh;
+        const double a0 = j * clen, a1 = (j + 1) * clen;
+        double acc = 0.0;
+        for (int k = (int)floor(a0); k < ns && k < a1; ++k) {
+            const double lo = fmax(a0, (double)k), hi = fmin(a1, (double)(k + 1));
+            if (hi > lo) acc += (double)sm[k] * (hi - lo) / clen;
+        }
+        dq[hh] = (float)acc;
+    }
+    red[t] = q0 * dq[0] + q1 * dq[1];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const float qdq = red[0];
+    dl[(int64_t)b * kBins + t] = q0 * (dq[0] - qdq);
+    dl[(int64_t)b * kBins + t + 256] = q1 * (dq[1] - qdq);
 }
 
 // Backward of the head for one sample: dz4[c][p] = sum_j cw[c][j] dl[p - j + pad];
@@ -330,12 +424,14 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
     }
 }
 
-// rows idx[i] of X (n x 32 fp32) and Y (n x 512 fp32) -> batch buffers (X as bf16)
-__global__ void k_gather(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *__restrict__ idx,
-                         int B, bf16_t *__restrict__ xb, float *__restrict__ yb) {
+// rows idx[i] of X (n x 32 fp32), Y (n x 512 fp32) and Ts (n) -> batch buffers (X as bf16)
+__global__ void k_gather(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *__restrict__ Ts,
+                         const int32_t *__restrict__ idx, int B, bf16_t *__restrict__ xb, float *__restrict__ yb,
+                         int32_t *__restrict__ tb) {
     const int b = blockIdx.x;
     if (b >= B) return;
     const int64_t r = idx[b];
+    if (threadIdx.x == 0) tb[b] = Ts[r];
     for (int i = threadIdx.x; i < kF; i += blockDim.x) xb[(int64_t)b * kF + i] = f2bf(X[r * kF + i]);
     if (Y)
         for (int i = threadIdx.x; i < kBins; i += blockDim.x) yb[(int64_t)b * kBins + i] = Y[r * kBins + i];
@@ -452,6 +548,7 @@ struct qw_surr {
     float *dz = nullptr;                       // fp32 dz (bmax x 1024)
     bf16_t *dzb = nullptr, *dzT = nullptr, *hT = nullptr;
     int32_t *idx = nullptr;
+    int32_t *tb = nullptr;                     // steps of the batch rows
     int64_t adam_t = 0;
     uint64_t seed = 0;
     int64_t train_n = 4097;   // the ring size the network was trained on
@@ -463,7 +560,7 @@ namespace {
 void free_surr(qw_surr *s) {
     if (!s) return;
     void *bufs[] = {s->p, s->m, s->v, s->g, s->pb, s->W2T, s->W3T, s->W4T, s->xb, s->h1, s->h2, s->h3,
-                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx};
+                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx, s->tb};
     for (void *b : bufs) (void)hipFree(b);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -505,8 +602,10 @@ hipError_t forward(qw_surr *s, int B, int Bscale, const float *y) {
     if (e == hipSuccess)
         e = gemm(st, s->h3, kH3, s->pb + L.W4, kH3, B, kZ4, kH3, 1.0f, s->p + L.b4, nullptr, 0, 0, s->z4, kZ4, nullptr, 0);
     if (e != hipSuccess) return e;
+    const int w = (int)(((s->train_n - 1) / 2) / (kBins / 2));
     hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
-                       (const float *)(s->p + L.cb), s->q, y, s->dl, s->lrow, Bscale);
+                       (const float *)(s->p + L.cb), (const int32_t *)s->tb, w < 1 ? 1 : w, s->q, y, s->dl, s->lrow,
+                       Bscale);
     return hipGetLastError();
 }
 
@@ -586,7 +685,7 @@ int alloc_surr(qw_surr *s) {
         {(void **)&s->lrow, sizeof(float) * B}, {(void **)&s->part, sizeof(float) * B * 19},
         {(void **)&s->dz, sizeof(float) * B * 1024}, {(void **)&s->dzb, sizeof(bf16_t) * B * 1024},
         {(void **)&s->dzT, sizeof(bf16_t) * B * 1024}, {(void **)&s->hT, sizeof(bf16_t) * B * 1024},
-        {(void **)&s->idx, sizeof(int32_t) * B},
+        {(void **)&s->idx, sizeof(int32_t) * B}, {(void **)&s->tb, sizeof(int32_t) * B},
     };
     for (auto &a : list) {
         hipError_t e = hipMalloc(a.p, a.bytes);
@@ -599,11 +698,14 @@ int alloc_surr(qw_surr *s) {
     return QW_OK;
 }
 
-// rows [0, n) of host X (n x 32 fp32) -> s->xb (zero rows up to the multiple of 128)
-int upload_rows(qw_surr *s, const float *Xh, int n, int npad) {
+// rows [0, n) of host X (n x 32 fp32) and T -> s->xb, s->tb (zero rows up to the multiple of 128)
+int upload_rows(qw_surr *s, const float *Xh, const int32_t *Th, int n, int npad) {
     std::vector<bf16_t> xb((size_t)npad * kF, 0);
     for (int64_t i = 0; i < (int64_t)n * kF; ++i) xb[i] = f2bf(Xh[i]);
+    std::vector<int32_t> tb((size_t)npad, 0);
+    for (int i = 0; i < n; ++i) tb[i] = Th[i];
     QS_HIP(hipMemcpyAsync(s->xb, xb.data(), xb.size() * sizeof(bf16_t), hipMemcpyHostToDevice, s->stream), "upload");
+    QS_HIP(hipMemcpyAsync(s->tb, tb.data(), tb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream), "upload");
     QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
     return QW_OK;
 }
@@ -716,12 +818,12 @@ int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, co
     return QW_OK;
 }
 
-int surr_forward(qw_surr_t s, int64_t n, const float *X, float *out) {
-    if (!s || !X || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
+int surr_forward(qw_surr_t s, int64_t n, const float *X, const int32_t *T, float *out) {
+    if (!s || !X || !T || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
     for (int64_t r0 = 0; r0 < n; r0 += s->bmax) {
         const int b = (int)std::min<int64_t>(s->bmax, n - r0);
         const int bp = (b + 127) / 128 * 128;
-        int rc = upload_rows(s, X + r0 * kF, b, bp);
+        int rc = upload_rows(s, X + r0 * kF, T + r0, b, bp);
         if (rc) return rc;
         QS_HIP(forward(s, bp, bp, nullptr), "surrogate forward");
         QS_HIP(hipMemcpyAsync(out + r0 * kBins, s->q, sizeof(float) * b * kBins, hipMemcpyDeviceToHost, s->stream),
@@ -731,11 +833,12 @@ int surr_forward(qw_surr_t s, int64_t n, const float *X, float *out) {
     return QW_OK;
 }
 
-int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, double *loss, float *grads) {
-    if (!s || !X || !Y || !loss || !grads || n < 1) return sfail(QW_EINVAL, "bad arguments");
+int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, const int32_t *T, double *loss,
+                   float *grads) {
+    if (!s || !X || !Y || !T || !loss || !grads || n < 1) return sfail(QW_EINVAL, "bad arguments");
     if (n > s->bmax) return sfail(QW_ERANGE, "at most %d rows per gradient call", s->bmax);
     const int b = (int)n, bp = (b + 127) / 128 * 128;
-    int rc = upload_rows(s, X, b, bp);
+    int rc = upload_rows(s, X, T, b, bp);
     if (rc) return rc;
     std::vector<float> y((size_t)bp * kBins, 0.0f);
     memcpy(y.data(), Y, sizeof(float) * b * kBins);
@@ -752,8 +855,9 @@ int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, doubl
     return QW_OK;
 }
 
-int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_train_opts *o, float *epoch_loss) {
-    if (!s || !X || !Y || !o) return sfail(QW_EINVAL, "NULL argument");
+int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int32_t *T, const qw_train_opts *o,
+               float *epoch_loss) {
+    if (!s || !X || !Y || !T || !o) return sfail(QW_EINVAL, "NULL argument");
     const int B = o->batch;
     if (B < 128 || B > s->bmax || B % 128) return sfail(QW_EINVAL, "batch must be a multiple of 128 in [128, %d]", s->bmax);
     if (n < B) return sfail(QW_EINVAL, "need at least one batch of samples (n = %lld)", (long long)n);
@@ -780,8 +884,8 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const qw_
         for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
             const double prog = std::min(1.0, ((double)(o->epoch_offset + ep) * steps + k) / ((double)sched * steps));
             const float lr = (float)(o->lr * (o->lr_floor + (1.0 - o->lr_floor) * 0.5 * (1.0 + cos(3.14159265358979 * prog))));
-            hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, X, Y, (const int32_t *)(perm + k * B), B, s->xb,
-                               s->yb);
+            hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, X, Y, T, (const int32_t *)(perm + k * B), B,
+                               s->xb, s->yb, s->tb);
             e = hipGetLastError();
             if (e == hipSuccess) e = forward(s, B, B, s->yb);
             if (e == hipSuccess) e = backward(s, B);
@@ -871,8 +975,10 @@ int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, con
     std::vector<float> X((size_t)n * kF);
     int rc = surr_features(s, n, N, T, angles, psi0, X.data());
     if (rc) return rc;
+    std::vector<int32_t> T32(n);
+    for (int64_t i = 0; i < n; ++i) T32[i] = (int32_t)std::min<int64_t>(T[i], kMaxSites - 1);
     QS_HIP(hipEventRecord(e0, s->stream), "event");
-    rc = surr_forward(s, n, X.data(), out);
+    rc = surr_forward(s, n, X.data(), T32.data(), out);
     if (rc) return rc;
     QS_HIP(hipEventRecord(e1, s->stream), "event");
     QS_HIP(hipEventSynchronize(e1), "event");

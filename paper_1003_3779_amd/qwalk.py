@@ -145,9 +145,9 @@ def load():
         "surr_get_params": [P, P, I32],
         "surr_set_params": [P, P],
         "surr_features": [P, I64, P, P, P, P, P],
-        "surr_forward": [P, I64, P, P],
-        "surr_loss_grad": [P, I64, P, P, P, P],
-        "surr_train": [P, I64, P, P, P, P],
+        "surr_forward": [P, I64, P, P, P],
+        "surr_loss_grad": [P, I64, P, P, P, P, P],
+        "surr_train": [P, I64, P, P, P, P, P],
         "surr_set_range": [P, I64, I32, I32],
         "surr_predict": [P, I64, P, P, P, P, P, P, P, P],
         "surr_save": [P, ctypes.c_char_p],
@@ -493,29 +493,31 @@ class Surrogate:
                                         out.ctypes.data))
         return out
 
-    def forward(self, X) -> np.ndarray:
+    def forward(self, X, T) -> np.ndarray:
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+        T = np.ascontiguousarray(np.asarray(T, dtype=np.int32))
         out = np.empty((X.shape[0], self.NBINS), dtype=np.float32)
-        _scheck(self._lib.surr_forward(self.h, X.shape[0], X.ctypes.data, out.ctypes.data))
+        _scheck(self._lib.surr_forward(self.h, X.shape[0], X.ctypes.data, T.ctypes.data, out.ctypes.data))
         return out
 
-    def loss_grad(self, X, Y):
+    def loss_grad(self, X, Y, T):
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
         Y = np.ascontiguousarray(np.asarray(Y, dtype=np.float32))
+        T = np.ascontiguousarray(np.asarray(T, dtype=np.int32))
         loss = ctypes.c_double()
         g = np.empty(self.num_params(), dtype=np.float32)
-        _scheck(self._lib.surr_loss_grad(self.h, X.shape[0], X.ctypes.data, Y.ctypes.data, ctypes.byref(loss),
-                                         g.ctypes.data))
+        _scheck(self._lib.surr_loss_grad(self.h, X.shape[0], X.ctypes.data, Y.ctypes.data, T.ctypes.data,
+                                         ctypes.byref(loss), g.ctypes.data))
         return loss.value, g
 
-    def train(self, X_dev, Y_dev, n: int, batch: int = 1024, epochs: int = 10, lr: float = 1e-3,
+    def train(self, X_dev, Y_dev, T_dev, n: int, batch: int = 1024, epochs: int = 10, lr: float = 1e-3,
               lr_floor: float = 0.05, weight_decay: float = 0.0, seed: int = 0, epoch_offset: int = 0,
               schedule_epochs: int = 0) -> np.ndarray:
-        """X_dev (n x 32) and Y_dev (n x 512): float32 device tensors."""
+        """X_dev (n x 32 float32), Y_dev (n x 512 float32), T_dev (n int32): device tensors."""
         o = TrainOpts(batch, epochs, lr, lr_floor, weight_decay, epoch_offset, seed, schedule_epochs, 0)
         hist = np.zeros(epochs, dtype=np.float32)
-        _scheck(self._lib.surr_train(self.h, int(n), _ptr_of(X_dev), _ptr_of(Y_dev), ctypes.byref(o),
-                                     hist.ctypes.data))
+        _scheck(self._lib.surr_train(self.h, int(n), _ptr_of(X_dev), _ptr_of(Y_dev), _ptr_of(T_dev),
+                                     ctypes.byref(o), hist.ctypes.data))
         return hist
 
     def set_range(self, N: int, tmin: int, tmax: int):

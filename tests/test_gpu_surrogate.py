@@ -48,12 +48,12 @@ def test_forward_matches_oracle():
     N, T, ang, psi0 = _walk_params(2, 256)
     s = qwalk.Surrogate(seed=7)
     X = s.features(N, T, ang, psi0)
-    q = s.forward(X)
+    q = s.forward(X, T)
     p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
     s.destroy()
     xr = X.astype(np.float32).view(np.uint32)          # the GPU feeds bf16 inputs
     xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
-    qr = S.forward(p, xr)["q"]
+    qr = S.forward(p, xr, T)["p"]
     assert np.all(np.abs(q.sum(axis=1) - 1.0) <= 1e-4)
     # bf16 activations between the layers: a few 1e-3 relative on the logits
     assert np.max(S.tvd(q, qr)) <= 2e-2
@@ -66,13 +66,14 @@ def test_gradients_match_oracle():
     y /= y.sum(axis=1, keepdims=True)
     s = qwalk.Surrogate(seed=11)
     X = s.features(N, T, ang, psi0)
-    loss, g = s.loss_grad(X, y.astype(np.float32))
+    loss, g = s.loss_grad(X, y.astype(np.float32), T)
     p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
     s.destroy()
     xr = X.astype(np.float32).view(np.uint32)
     xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
-    assert abs(loss - S.loss(p, xr, y)) <= 2e-2 * abs(S.loss(p, xr, y))
-    gr = S.backward(p, xr, y)
+    lref = S.loss(p, xr, y, T)
+    assert abs(loss - lref) <= 2e-2 * abs(lref)
+    gr = S.backward(p, xr, y, T)
     gg = S.unflatten(g.astype(np.float64))
     for k in S.ORDER:
         rel = np.linalg.norm(gg[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
@@ -88,15 +89,16 @@ def test_training_reduces_loss_and_save_load(tmp_path):
     X = s.features(N, T, ang, psi0)
     Xd = torch.from_numpy(X).cuda()
     Yd = torch.from_numpy(y).cuda()
-    hist = s.train(Xd, Yd, n, batch=512, epochs=6, lr=1e-3, seed=5)
+    Td = torch.from_numpy(T.astype(np.int32)).cuda()
+    hist = s.train(Xd, Yd, Td, n, batch=512, epochs=6, lr=1e-3, seed=5)
     assert np.all(np.isfinite(hist))
     assert hist[-1] < 0.7 * hist[0]
-    q1 = s.forward(X[:64])
+    q1 = s.forward(X[:64], T[:64])
     path = str(tmp_path / "s.qws")
     s.save(path)
     s.destroy()
     s2 = qwalk.Surrogate.load_file(path)
-    assert np.array_equal(s2.forward(X[:64]), q1)
+    assert np.array_equal(s2.forward(X[:64], T[:64]), q1)
     s2.destroy()
 
 
@@ -115,7 +117,7 @@ def test_predict_fallback_semantics():
     # an impossible tolerance keeps the network's answer except where re-checked/out of range
     out2, fb2, st2 = s.predict(N, T, ang, psi0, chunk=512, tvd_tol=2.0)
     assert st2.failed_chunks == 0 and st2.fallback == 20 and fb2.sum() == 20
-    net = s.forward(s.features(N, T, ang, psi0))
+    net = s.forward(s.features(N, T, ang, psi0), T)
     keep = ~fb2
     rechecked = np.all(out2 == plain, axis=1) & keep
     assert rechecked.sum() >= st2.rechecked - 1     # re-checked walks carry the plain result

@@ -14,38 +14,59 @@ def _small_params(rng, scale=0.05):
     return p
 
 
-def _batch(rng, B=3):
+def _batch(rng, B=3, T=(300, 2048, 1001)):
     x = np.zeros((B, 32))
     x[:, :12] = rng.normal(size=(B, 12))
-    y = rng.random(size=(B, S.NBINS)) ** 4
-    y[:, :40] = 0.0                                   # exact zeros exercise 0 log 0
+    T = np.array(T[:B])
+    y = np.zeros((B, S.NBINS))
+    for i, t in enumerate(T):                          # support of a walk of t steps
+        half = int(np.ceil(t / S.BIN_SITES))
+        y[i, 256 - half:256 + half] = rng.random(2 * half) ** 4 + 1e-3
+        y[i, 256 - half] = 0.0                         # exact zeros exercise 0 log 0
     y /= y.sum(axis=1, keepdims=True)
-    return x, y
+    return x, y, T
 
 
-def test_forward_is_a_distribution():
+def test_forward_is_a_distribution_on_the_cone():
     rng = np.random.default_rng(0)
     p = _small_params(rng)
-    x, _ = _batch(rng)
-    q = S.forward(p, x)["q"]
-    assert np.all(q > 0) and np.allclose(q.sum(axis=1), 1.0, atol=1e-13)
+    x, _, T = _batch(rng)
+    a = S.forward(p, x, T)
+    assert np.all(a["q"] > 0) and np.allclose(a["q"].sum(axis=1), 1.0, atol=1e-13)
+    assert np.allclose(a["p"].sum(axis=1), 1.0, atol=1e-12)
+    for i, t in enumerate(T):                          # no mass beyond the light cone
+        half = int(np.ceil(t / S.BIN_SITES))
+        assert np.all(a["p"][i, :256 - half] == 0) and np.all(a["p"][i, 256 + half:] == 0)
+
+
+def test_resample_matrix_geometry():
+    """Columns sum to 1; a uniform cell density gives each bin its share of sites."""
+    for T in (256, 257, 1000, 2048):
+        R = S.resample_matrix(T)
+        assert np.allclose(R.sum(axis=0), 1.0, atol=1e-12)
+        p = R @ np.full(S.NCELLS, 1.0 / S.NCELLS)      # uniform over the T + 1 sites
+        counts = np.zeros(S.NBINS)
+        for k in range(T + 1):
+            for b, sh in S.site_bin(-T + 2 * k):
+                counts[b] += sh
+        assert np.allclose(p, counts / (T + 1), atol=1e-12)
 
 
 def test_loss_is_kl_and_zero_at_match():
     rng = np.random.default_rng(1)
     p = _small_params(rng)
-    x, _ = _batch(rng)
-    q = S.forward(p, x)["q"]
-    assert abs(S.loss(p, x, q)) <= 1e-13            # KL(q || q) = 0
-    _, y = _batch(rng)
-    assert S.loss(p, x, y) > 0.0
+    x, _, T = _batch(rng)
+    pb = S.forward(p, x, T)["p"]
+    assert abs(S.loss(p, x, pb, T)) <= 1e-13        # KL(p || p) = 0
+    _, y, _ = _batch(rng)
+    assert S.loss(p, x, y, T) > 0.0
 
 
 def test_backward_matches_finite_differences():
     rng = np.random.default_rng(2)
     p = _small_params(rng)
-    x, y = _batch(rng)
-    g = S.backward(p, x, y)
+    x, y, T = _batch(rng)
+    g = S.backward(p, x, y, T)
     h = 1e-6
     for k in S.ORDER:
         flat = p[k].ravel()
@@ -53,9 +74,9 @@ def test_backward_matches_finite_differences():
             i = int(rng.integers(0, flat.size))
             old = flat[i]
             flat[i] = old + h
-            lp = S.loss(p, x, y)
+            lp = S.loss(p, x, y, T)
             flat[i] = old - h
-            lm = S.loss(p, x, y)
+            lm = S.loss(p, x, y, T)
             flat[i] = old
             num = (lp - lm) / (2 * h)
             ana = g[k].ravel()[i]
