@@ -76,6 +76,11 @@ def test_gradients_match_oracle():
     gr = S.backward(p, xr, y, T)
     gg = S.unflatten(g.astype(np.float64))
     for k in S.ORDER:
+        if k == "cb":
+            # softmax is invariant under a common shift of the logits: the exact
+            # gradient of the output bias is zero, so compare absolutely
+            assert abs(gr[k][0]) <= 1e-12 and abs(gg[k][0]) <= 1e-4, (gr[k], gg[k])
+            continue
         rel = np.linalg.norm(gg[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
         assert rel <= 5e-2, (k, rel)
 
