@@ -16,10 +16,15 @@ Functions and the passages they follow (see ``qw_oracle.c`` for the details):
   prob(psi)                 P(x) = sum_c |psi(x,c)|^2, Eqs. (4)-(6)
   norm(P)                   sum_x P(x)
   bin_ring(P, x0, nbins)    symmetric binning of a ring distribution
+  philox(ctr, key)          Philox4x32-10 (the random source of the broken links)
+  rbl_threshold(p)          floor(p * 2^32): a link is broken when Philox's word 0 is below it
+  evolve_rbl(psi, ...)      T steps with random broken links, Sec. 3 Eqs. (9)-(10), and
+                            the finite segment / box with reflecting walls (Fig. 3)
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -62,6 +67,11 @@ def _open(path: str):
     lib.orc_norm.restype = ctypes.c_double
     lib.orc_bin.argtypes = [i64, i64, dp, i32, dp]
     lib.orc_bin.restype = i32
+    lib.orc_philox.argtypes = [dp, dp, dp]
+    lib.orc_philox.restype = None
+    u64 = ctypes.c_uint64
+    lib.orc_evolve_rbl.argtypes = [i64, i64, i32, ip, dp, dp, i64, i64, u64, u64, u64, i32]
+    lib.orc_evolve_rbl.restype = i32
     return lib
 
 
@@ -171,3 +181,37 @@ def walk(Lx: int, Ly: int, disp, C: np.ndarray, x0, psi0, T: int, windowed: bool
     d = C.shape[0]
     psi = initial_state(Lx, Ly, d, x0, psi0)
     return evolve(psi, disp, C, T, windowed=windowed, x0=x0, t0=0)
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of a 4-word counter and a 2-word key (uint32 words)."""
+    lib = _load()
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64).astype(np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64).astype(np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib.orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def rbl_threshold(p: float) -> int:
+    """floor(p * 2^32), the integer threshold of a link breaking with probability p."""
+    if not (0.0 <= p <= 1.0):
+        raise ValueError("p must lie in [0, 1]")
+    return int(math.floor(p * 4294967296.0))
+
+
+def evolve_rbl(psi: np.ndarray, disp, C: np.ndarray, T: int, p: float, seed: int = 0,
+               realization: int = 0, step0: int = 0, walls: bool = False) -> np.ndarray:
+    """T steps with random broken links (probability p per link and step) on a
+    copy of psi; step s draws its links with step index step0 + s.  walls: the
+    links across the lattice edge are always broken (segment / box)."""
+    lib = _load()
+    Ly, Lx, d = psi.shape
+    out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+    da = _disp_array(disp, d)
+    Cc = np.ascontiguousarray(C, dtype=np.complex128)
+    rc = lib.orc_evolve_rbl(Lx, Ly, d, _ptr(da), _ptr(Cc), _ptr(out), int(T), int(step0),
+                            rbl_threshold(p), int(seed), int(realization), int(bool(walls)))
+    if rc != 0:
+        raise ValueError("orc_evolve_rbl: bad arguments (every component needs an opposite)")
+    return out

@@ -31,6 +31,9 @@
  *   orc_prob           -- P(x) = sum_c |psi(x,c)|^2, c ascending
  *   orc_norm           -- sum_x P(x), pairwise summation
  *   orc_bin            -- symmetric binning of a 1D P(x) into nbins bins
+ *   orc_philox         -- the Philox4x32-10 counter-based generator
+ *   orc_evolve_rbl     -- T steps with random broken links (Sec. 3, Eqs. (9)-(10)),
+ *                         optionally with reflecting walls (the finite segment)
  */
 #include <math.h>
 #include <stdint.h>
@@ -291,5 +294,153 @@ int orc_bin(int64_t N, int64_t x0, const double *P, int nbins, double *out) {
         out[b] += sl;
         out[h + b] += sr;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Random broken links (Sec. 3, Eq. (9) and the evolution equation (10)).
+ *
+ * Each link of the lattice is, at every step, either intact (RBL = (-1)^j in
+ * Eq. (9): the component crosses it) or broken (RBL = 0: Eq. (10) then leaves
+ * the walker on its site with the coin index complemented, i.e. reflected).
+ * In gather form, with e_cbar = -e_c:
+ *   psi'(x, c) = (C psi)(x - e_c, c)   if the link joining x - e_c and x is intact,
+ *   psi'(x, c) = (C psi)(x, cbar)      if it is broken.
+ * The paper fixes neither the probability p nor the random source.  Reading:
+ * every link is broken independently at every step with probability p, drawn
+ * with the counter-based Philox4x32-10 generator (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11):
+ *   counter = (link id low 32 bits, link id high 32 bits, step, realization),
+ *   key     = (seed low 32 bits, seed high 32 bits),
+ *   broken  <=> first output word < thr, thr = floor(p * 2^32) in [0, 2^32].
+ * Links: the components come in opposite pairs (e_cbar = -e_c).  In each pair
+ * the "positive" member p has e_p.x > 0, or e_p.x = 0 and e_p.y > 0; pairs
+ * are numbered by their positive member in ascending component order.  The
+ * link crossed by a move along p out of site a has id
+ * (a.y * Lx + a.x) * npairs + pair; a move along the negative member out of
+ * site b crosses the link of site b + e_c (so both sides see one link).
+ * ------------------------------------------------------------------------ */
+static uint32_t mulhilo32(uint32_t a, uint32_t b, uint32_t *hi) {
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    *hi = (uint32_t)(p >> 32);
+    return (uint32_t)p;
+}
+
+/* Philox4x32 with 10 rounds: each round multiplies counter words 0 and 2 by
+ * the two round constants and mixes the high halves with the other words and
+ * the key; the key is bumped by the two Weyl constants between rounds. */
+void orc_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    int r;
+    for (r = 0; r < 10; r++) {
+        uint32_t hi0, hi1, lo0, lo1;
+        if (r > 0) { k0 += W0; k1 += W1; }
+        lo0 = mulhilo32(M0, c0, &hi0);
+        lo1 = mulhilo32(M1, c2, &hi1);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static int link_broken(uint64_t link, uint64_t step, uint64_t realization, uint64_t seed, uint64_t thr) {
+    uint32_t ctr[4], key[2], o[4];
+    if (thr == 0) return 0;
+    ctr[0] = (uint32_t)link; ctr[1] = (uint32_t)(link >> 32);
+    ctr[2] = (uint32_t)step; ctr[3] = (uint32_t)realization;
+    key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
+    orc_philox(ctr, key, o);
+    return (uint64_t)o[0] < thr;
+}
+
+/* opposite-pair structure of a displacement table; returns the number of
+ * pairs, or -1 when some component has no opposite or a zero displacement */
+static int rbl_pairs(int d, const int *disp, int *opp, int *positive, int *pair) {
+    int c, k, np = 0;
+    for (c = 0; c < d; c++) {
+        if (disp[2 * c] == 0 && disp[2 * c + 1] == 0) return -1;
+        opp[c] = -1;
+        for (k = 0; k < d; k++)
+            if (k != c && disp[2 * k] == -disp[2 * c] && disp[2 * k + 1] == -disp[2 * c + 1]) opp[c] = k;
+        if (opp[c] < 0) return -1;
+        positive[c] = disp[2 * c] > 0 || (disp[2 * c] == 0 && disp[2 * c + 1] > 0);
+    }
+    for (c = 0; c < d; c++) pair[c] = -1;
+    for (c = 0; c < d; c++)
+        if (positive[c]) { pair[c] = np; pair[opp[c]] = np; np++; }
+    return np;
+}
+
+/*
+ * T steps with random broken links (full sweep, in place); step s of this
+ * call draws its links with step index step0 + s.  walls != 0: the links
+ * across the lattice edge (those a move would wrap through) are broken at
+ * every step, making the ring a segment with reflecting ends and the torus a
+ * box with reflecting walls.
+ * Returns 0, or -1 on bad arguments / allocation failure / a displacement
+ * table without opposite pairs.
+ */
+int orc_evolve_rbl(int64_t Lx, int64_t Ly, int d, const int *disp, const double *coin, double *psi_io,
+                   int64_t T, int64_t step0, uint64_t thr, uint64_t seed, uint64_t realization, int walls) {
+    size_t n = (size_t)Lx * (size_t)Ly * (size_t)d;
+    const cx *C = (const cx *)coin;
+    cx *a = (cx *)psi_io, *b, *phi;
+    int opp[4], positive[4], pair[4], np;
+    int64_t s, x, y;
+    if (Lx < 1 || Ly < 1 || d < 1 || d > 4 || T < 0 || step0 < 0 || thr > ((uint64_t)1 << 32)) return -1;
+    np = rbl_pairs(d, disp, opp, positive, pair);
+    if (np < 0) return -1;
+    if (T == 0) return 0;
+    b = (cx *)calloc(n, sizeof(cx));
+    phi = (cx *)calloc(n, sizeof(cx));
+    if (!b || !phi) { free(b); free(phi); return -1; }
+    for (s = 0; s < T; s++) {
+        cx *tmp;
+        /* coin on every site: phi = (I (x) C) psi */
+        for (y = 0; y < Ly; y++)
+            for (x = 0; x < Lx; x++) {
+                int c, cp;
+                const cx *site = a + (y * Lx + x) * d;
+                for (c = 0; c < d; c++) {
+                    cx acc = c_make(0.0, 0.0);
+                    for (cp = 0; cp < d; cp++) acc = c_add(acc, c_mul(C[c * d + cp], site[cp]));
+                    phi[(y * Lx + x) * d + c] = acc;
+                }
+            }
+        /* shift with this step's broken links */
+        for (y = 0; y < Ly; y++)
+            for (x = 0; x < Lx; x++) {
+                int c;
+                for (c = 0; c < d; c++) {
+                    int64_t sx = wrap(x - disp[2 * c], Lx), sy = wrap(y - disp[2 * c + 1], Ly);
+                    /* the move along c from (sx, sy) into (x, y): for the positive
+                     * member the link belongs to the start site, else to the
+                     * site the move arrives at */
+                    int64_t lx = positive[c] ? sx : x, ly = positive[c] ? sy : y;
+                    uint64_t link = (uint64_t)(ly * Lx + lx) * (uint64_t)np + (uint64_t)pair[c];
+                    /* walls: the links that close the lattice periodically are
+                     * always broken (a finite segment / box, Sec. 3 and Fig. 3) */
+                    int64_t rx = x - disp[2 * c], ry = y - disp[2 * c + 1];
+                    int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);
+                    if (edge || link_broken(link, (uint64_t)(step0 + s), realization, seed, thr))
+                        b[(y * Lx + x) * d + c] = phi[(y * Lx + x) * d + opp[c]];
+                    else
+                        b[(y * Lx + x) * d + c] = phi[(sy * Lx + sx) * d + c];
+                }
+            }
+        tmp = a; a = b; b = tmp;
+    }
+    if (a != (cx *)psi_io) {
+        memcpy(psi_io, a, n * sizeof(cx));
+        free(a);
+    } else {
+        free(b);
+    }
+    free(phi);
     return 0;
 }

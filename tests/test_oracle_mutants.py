@@ -14,6 +14,7 @@ import pytest
 import oracle
 from paper_1003_3779_amd import inputs
 from tests import test_oracle_pins as P
+from tests import test_oracle_rbl as RB
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "qw_oracle.c")
 
@@ -36,6 +37,19 @@ MUTANTS = {
                         "c_mul(C[cp * d + c], a[(sy * Lx + sx) * d + cp])"),
     "inverse_shift_sign": ("int64_t sx = wrap(x + disp[2 * cp], Lx);", "int64_t sx = wrap(x - disp[2 * cp], Lx);"),
     "bin_left_offset": ("int64_t offl = -(h - b) * w + k;", "int64_t offl = -(h - b) * w + k + 1;"),
+    "rbl_link_owner": ("int64_t lx = positive[c] ? sx : x, ly = positive[c] ? sy : y;",
+                       "int64_t lx = x, ly = y;"),
+    "rbl_reflect_same_component": ("b[(y * Lx + x) * d + c] = phi[(y * Lx + x) * d + opp[c]];",
+                                   "b[(y * Lx + x) * d + c] = phi[(y * Lx + x) * d + c];"),
+    "philox_multiplier": ("const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;",
+                          "const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D55u;"),
+    "philox_key_schedule": ("if (r > 0) { k0 += W0; k1 += W1; }", "if (r > 1) { k0 += W0; k1 += W1; }"),
+    "rbl_step_counter": ("link_broken(link, (uint64_t)(step0 + s), realization, seed, thr)",
+                         "link_broken(link, (uint64_t)step0, realization, seed, thr)"),
+    "wall_edge_test": ("int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);",
+                       "int edge = walls && (rx < 0 || rx > Lx || ry < 0 || ry >= Ly);"),
+    "wall_reflects_wrong_side": ("int64_t rx = x - disp[2 * c], ry = y - disp[2 * c + 1];",
+                                 "int64_t rx = x + disp[2 * c], ry = y + disp[2 * c + 1];"),
 }
 
 ONE = lambda rng: inputs.haar_unitary(rng, 2)          # noqa: E731
@@ -56,6 +70,16 @@ BATTERY = [
     lambda: P.test_exact_reversal("PAIR"),
     lambda: P.test_inverse_matches_matrix_inverse(),
     lambda: P.test_binning_symmetric_and_complete(),
+    lambda: RB.test_philox_known_answers(),
+    lambda: RB.test_no_broken_link_is_the_plain_walk("PAIR"),
+    lambda: RB.test_every_link_broken_freezes_the_walker("EQ8"),
+    lambda: RB.test_each_step_is_a_reflecting_shift("DIAG"),
+    lambda: RB.test_each_step_is_a_reflecting_shift("RING"),
+    lambda: RB.test_reflection_frequency_matches_p(),
+    lambda: RB.test_steps_compose("PAIR"),
+    lambda: RB.test_walls_two_site_segment_by_hand(),
+    lambda: RB.test_walls_segment_never_wraps(),
+    lambda: RB.test_walls_reflect_exactly_at_the_edge("PAIR"),
 ]
 
 

@@ -1,0 +1,287 @@
+"""Pins of the oracle's random-broken-link walk (Sec. 3, Eqs. (9)-(10)).
+
+The random source is Philox4x32-10, pinned by its published known-answer
+vectors.  The walk is pinned by special cases (no link broken: the plain walk;
+every link broken: the walker never moves and the coin register evolves by the
+reflected coin), by the unitarity and permutation structure of every step's
+shift, rebuilt as an explicit matrix from single-site basis states, and by the
+frequency of reflected moves.  CPU only.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_3779_amd import inputs
+
+KAT = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+TABLES = {"RING": (inputs.RING, 2), "PAIR": (inputs.PAIR, 4), "EQ8": (inputs.EQ8, 4), "DIAG": (inputs.DIAG, 4)}
+
+
+def _kat():
+    rows = []
+    with open(KAT) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(v, 16) for v in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat()
+    assert len(rows) == 3
+    for ctr, key, out in rows:
+        assert [int(v) for v in oracle.philox(ctr, key)] == out
+
+
+def _opposite(disp):
+    d = len(disp)
+    return [next(k for k in range(d) if tuple(disp[k]) == (-disp[c][0], -disp[c][1])) for c in range(d)]
+
+
+def _coin(d, rng):
+    return inputs.haar_unitary(rng, d)
+
+
+@pytest.mark.parametrize("table", list(TABLES))
+def test_no_broken_link_is_the_plain_walk(table):
+    disp, d = TABLES[table]
+    rng = np.random.default_rng(1)
+    C = _coin(d, rng)
+    ext = (9,) if d == 2 else (7, 6)
+    Lx, Ly = (ext[0], 1) if d == 2 else ext
+    psi = oracle.initial_state(Lx, Ly, d, (3, 2 % Ly), inputs.haar_state(rng, d))
+    a = oracle.evolve(psi, disp, C, 11)
+    b = oracle.evolve_rbl(psi, disp, C, 11, p=0.0, seed=5)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("table", list(TABLES))
+def test_every_link_broken_freezes_the_walker(table):
+    """p = 1: every move is reflected, so psi_T(x0) = (F C)^T psi_0 with F the
+    permutation c -> cbar, and nothing leaves x0."""
+    disp, d = TABLES[table]
+    rng = np.random.default_rng(2)
+    C = _coin(d, rng)
+    Lx, Ly = (11, 1) if d == 2 else (5, 7)
+    x0 = (4, 3 % Ly)
+    psi0 = inputs.haar_state(rng, d)
+    psi = oracle.initial_state(Lx, Ly, d, x0, psi0)
+    T = 23
+    out = oracle.evolve_rbl(psi, disp, C, T, p=1.0, seed=9, realization=4)
+    F = np.zeros((d, d))
+    for c, o in enumerate(_opposite(disp)):
+        F[c, o] = 1.0
+    want = np.linalg.matrix_power(F @ C, T) @ psi0
+    assert np.max(np.abs(out[x0[1], x0[0]] - want)) <= 1e-12
+    rest = out.copy()
+    rest[x0[1], x0[0]] = 0.0
+    assert np.max(np.abs(rest)) == 0.0
+
+
+def _step_matrix(Lx, Ly, disp, C, p, seed, step, realization):
+    """U_step as an explicit matrix: the oracle applied to every basis state."""
+    d = C.shape[0]
+    V = Lx * Ly * d
+    U = np.zeros((V, V), dtype=np.complex128)
+    for j in range(V):
+        e = np.zeros(V, dtype=np.complex128)
+        e[j] = 1.0
+        out = oracle.evolve_rbl(e.reshape(Ly, Lx, d), disp, C, 1, p=p, seed=seed, realization=realization,
+                                step0=step)
+        U[:, j] = out.ravel()
+    return U
+
+
+@pytest.mark.parametrize("table", list(TABLES))
+def test_each_step_is_a_reflecting_shift(table):
+    """Every step is U = S_t (I (x) C) with S_t a permutation that moves (x - e_c, c)
+    to (x, c) or, when the link is broken, (x, cbar) to (x, c); a broken link
+    reflects both of the moves that cross it."""
+    disp, d = TABLES[table]
+    rng = np.random.default_rng(3)
+    C = _coin(d, rng)
+    Lx, Ly = (6, 1) if d == 2 else (4, 3)
+    opp = _opposite(disp)
+    IC = np.kron(np.eye(Lx * Ly), C)
+    idx = lambda x, y, c: ((y % Ly) * Lx + (x % Lx)) * d + c
+    seen_reflect = seen_move = 0
+    for step in range(6):
+        U = _step_matrix(Lx, Ly, disp, C, 0.5, 77, step, 2)
+        assert np.max(np.abs(U.conj().T @ U - np.eye(U.shape[0]))) <= 1e-12
+        S = U @ IC.conj().T
+        assert np.max(np.abs(S - np.round(S.real))) <= 1e-12
+        S = np.round(S.real).astype(int)
+        assert np.all(S.sum(axis=0) == 1) and np.all(S.sum(axis=1) == 1)
+        reflected = {}
+        for y in range(Ly):
+            for x in range(Lx):
+                for c in range(d):
+                    sx, sy = x - disp[c][0], y - disp[c][1]
+                    moved = S[idx(x, y, c), idx(sx, sy, c)] == 1
+                    refl = S[idx(x, y, c), idx(x, y, opp[c])] == 1
+                    assert moved != refl or (idx(sx, sy, c) == idx(x, y, opp[c]))
+                    reflected[(x, y, c)] = refl and not moved
+        # the move along c into (x, y) crosses the same link as the move along
+        # cbar from (x, y) into (x - e_c): both are reflected or neither is
+        for (x, y, c), r in reflected.items():
+            sx, sy = (x - disp[c][0]) % Lx, (y - disp[c][1]) % Ly
+            assert reflected[(sx, sy, opp[c])] == r
+            seen_reflect += r
+            seen_move += not r
+    assert seen_reflect > 0 and seen_move > 0
+
+
+@pytest.mark.parametrize("table", ["RING", "PAIR"])
+def test_steps_compose(table):
+    """T steps in one call are T single steps with step indices step0 .. step0+T-1
+    (each step draws its own links; a realization is a different draw)."""
+    disp, d = TABLES[table]
+    rng = np.random.default_rng(6)
+    C = _coin(d, rng)
+    Lx, Ly = (13, 1) if d == 2 else (6, 5)
+    psi = oracle.initial_state(Lx, Ly, d, (5, 2 % Ly), inputs.haar_state(rng, d))
+    one = oracle.evolve_rbl(psi, disp, C, 7, p=0.4, seed=11, realization=3, step0=2)
+    seq = psi
+    for s in range(7):
+        seq = oracle.evolve_rbl(seq, disp, C, 1, p=0.4, seed=11, realization=3, step0=2 + s)
+    assert np.array_equal(one, seq)
+    other = oracle.evolve_rbl(psi, disp, C, 7, p=0.4, seed=11, realization=4, step0=2)
+    assert not np.array_equal(one, other)
+
+
+def test_reflection_frequency_matches_p():
+    """On a ring of 401 sites over 200 steps (80200 link draws) the fraction of
+    reflected moves is p within five standard deviations."""
+    rng = np.random.default_rng(4)
+    C = _coin(2, rng)
+    N, T, p = 401, 200, 0.3
+    count = 0
+    for step in range(T):
+        # a state with amplitude 1 in component 0 everywhere: after one step the
+        # component-0 amplitude at x came through the link (x-1, x) unless reflected
+        psi = np.zeros((1, N, 2), dtype=np.complex128)
+        psi[0, :, 0] = 1.0
+        Cid = np.eye(2)
+        out = oracle.evolve_rbl(psi, inputs.RING, Cid, 1, p=p, seed=123, realization=0, step0=step)
+        count += int(np.sum(np.abs(out[0, :, 0]) < 0.5))     # reflected: component 0 lost there
+    n = N * T
+    frac = count / n
+    assert abs(frac - p) <= 5 * np.sqrt(p * (1 - p) / n)
+
+
+def test_norm_kept_and_spreading_slowed():
+    """Broken links keep the walk unitary; averaged over realizations the
+    spreading is slower than the ballistic (1 - 1/sqrt 2) t^2 of the Hadamard walk."""
+    C = oracle.coin(oracle.HADAMARD, 2)
+    N, T, x0 = 301, 120, 150
+    psi = oracle.initial_state(N, 1, 2, (x0, 0), inputs.PSI0_LR)
+    m2 = []
+    for r in range(8):
+        out = oracle.evolve_rbl(psi, inputs.RING, C, T, p=0.2, seed=31, realization=r)
+        P = oracle.prob(out)[0]
+        assert abs(P.sum() - 1.0) <= 1e-12
+        dx = np.arange(N) - x0
+        m2.append(np.sum(P * dx * dx))
+    ballistic = (1 - 1 / np.sqrt(2)) * T * T
+    assert np.mean(m2) < 0.5 * ballistic
+
+
+def test_rbl_rejects_tables_without_opposites():
+    C = np.eye(2)
+    psi = np.zeros((1, 5, 2), dtype=np.complex128)
+    with pytest.raises(ValueError):
+        oracle.evolve_rbl(psi, [(1, 0), (1, 0)], C, 1, p=0.5)
+    with pytest.raises(ValueError):
+        oracle.rbl_threshold(1.5)
+    assert oracle.rbl_threshold(1.0) == 2 ** 32 and oracle.rbl_threshold(0.0) == 0
+
+
+# ---------------------------------------------------------------------------
+# the finite segment / box: the links across the lattice edge always broken
+# (reflecting ends, the "segment" walk of Sec. 3 and Fig. 3)
+# ---------------------------------------------------------------------------
+def test_walls_two_site_segment_by_hand():
+    """N = 2 with walls: the transition written out by hand (R moves +1, L -1):
+    psi'(0,R) = (C psi)(0,L), psi'(1,R) = (C psi)(0,R), psi'(0,L) = (C psi)(1,L),
+    psi'(1,L) = (C psi)(1,R)."""
+    rng = np.random.default_rng(12)
+    C = _coin(2, rng)
+    psi = (rng.normal(size=(1, 2, 2)) + 1j * rng.normal(size=(1, 2, 2)))
+    psi /= np.linalg.norm(psi)
+    ref = psi[0].copy()
+    for _ in range(9):
+        phi = ref @ C.T                              # phi[x] = C psi[x]
+        ref = np.array([[phi[0, 1], phi[1, 1]], [phi[0, 0], phi[1, 0]]])
+    out = oracle.evolve_rbl(psi, inputs.RING, C, 9, p=0.0, walls=True)
+    assert np.max(np.abs(out[0] - ref)) <= 1e-13
+
+
+def test_walls_segment_never_wraps():
+    C = oracle.coin(oracle.HADAMARD, 2)
+    N, x0, T = 50, 2, 10
+    psi = oracle.initial_state(N, 1, 2, (x0, 0), inputs.PSI0_LR)
+    ring = oracle.prob(oracle.evolve_rbl(psi, inputs.RING, C, T, p=0.0))[0]
+    seg = oracle.prob(oracle.evolve_rbl(psi, inputs.RING, C, T, p=0.0, walls=True))[0]
+    assert ring[N - 8:].sum() > 1e-3                 # the ring walk wraps to the far end
+    assert np.all(seg[x0 + T + 1:] == 0.0)           # the segment walk cannot
+    assert abs(seg.sum() - 1.0) <= 1e-12
+
+
+def test_walls_segment_keeps_mirror_symmetry():
+    """The symmetric Hadamard walk stays mirror symmetric between symmetric walls,
+    long after it has hit both of them."""
+    C = oracle.coin(oracle.HADAMARD, 2)
+    N = 41
+    x0 = 20
+    psi = oracle.initial_state(N, 1, 2, (x0, 0), inputs.PSI0_LR)
+    P = oracle.prob(oracle.evolve_rbl(psi, inputs.RING, C, 157, p=0.0, walls=True))[0]
+    assert np.max(np.abs(P - P[::-1])) <= 1e-12
+    assert abs(P.sum() - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("table", list(TABLES))
+def test_walls_reflect_exactly_at_the_edge(table):
+    """With walls and p = 0 each step's shift reflects the moves that would wrap
+    and only those."""
+    disp, d = TABLES[table]
+    rng = np.random.default_rng(13)
+    C = _coin(d, rng)
+    Lx, Ly = (5, 1) if d == 2 else (4, 3)
+    V = Lx * Ly * d
+    opp = _opposite(disp)
+    IC = np.kron(np.eye(Lx * Ly), C)
+    U = np.zeros((V, V), dtype=np.complex128)
+    for j in range(V):
+        e = np.zeros(V, dtype=np.complex128)
+        e[j] = 1.0
+        U[:, j] = oracle.evolve_rbl(e.reshape(Ly, Lx, d), disp, C, 1, p=0.0, walls=True).ravel()
+    S = np.round((U @ IC.conj().T).real).astype(int)
+    idx = lambda x, y, c: ((y % Ly) * Lx + (x % Lx)) * d + c
+    for y in range(Ly):
+        for x in range(Lx):
+            for c in range(d):
+                rx, ry = x - disp[c][0], y - disp[c][1]
+                wraps = not (0 <= rx < Lx and 0 <= ry < Ly)
+                if wraps:
+                    assert S[idx(x, y, c), idx(x, y, opp[c])] == 1
+                else:
+                    assert S[idx(x, y, c), idx(rx, ry, c)] == 1
+
+
+def test_walls_with_random_links_compose():
+    """Walls and random links together: unitary, and T steps in one call equal
+    single steps with their step indices."""
+    disp, d = TABLES["PAIR"]
+    rng = np.random.default_rng(14)
+    C = _coin(d, rng)
+    psi = oracle.initial_state(6, 5, d, (0, 4), inputs.haar_state(rng, d))
+    one = oracle.evolve_rbl(psi, disp, C, 9, p=0.3, seed=2, realization=1, walls=True)
+    seq = psi
+    for s in range(9):
+        seq = oracle.evolve_rbl(seq, disp, C, 1, p=0.3, seed=2, realization=1, step0=s, walls=True)
+    assert np.array_equal(one, seq)
+    assert abs(np.sum(np.abs(one) ** 2) - 1.0) <= 1e-12
