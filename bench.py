@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="ragged_rings: run the autotuner first")
     ap.add_argument("--prec", default=None, choices=["c128", "c64"])
     ap.add_argument("--depth", type=int, default=0, help="steps per launch (0 = library default)")
+    ap.add_argument("--prefetch", type=int, default=0, help="torus kernel: rows requested ahead (0 = default)")
+    ap.add_argument("--waves", type=int, default=0, help="torus kernel: waves per launch (0 = default)")
+    ap.add_argument("--broken-links", type=float, default=0.0, metavar="P",
+                    help="random broken links: each link breaks with probability P at every step")
     ap.add_argument("--cpu-sample-steps", type=int, default=900)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -60,8 +64,43 @@ def parse():
     return ap.parse_args()
 
 
+def hbm_reference(nbytes: int = 1 << 30) -> dict:
+    """Plain streaming kernels of known size on this GPU (torch's): a copy
+    (read + write), a read-only reduction and a write-only fill of nbytes each,
+    best of 10 launches.  The practical HBM ceiling next to the published peak."""
+    import torch
+    n = nbytes // 16
+    a = torch.ones(n, 2, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    r = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms)
+
+    t_copy = best(lambda: b.copy_(a))
+    t_read = best(lambda: torch.sum(a, dim=(0, 1), out=r))
+    t_write = best(lambda: b.fill_(0.5))
+    nb = n * 16
+    out = {"bytes": nb, "copy_GBps": round(2 * nb / (t_copy * 1e-3) / 1e9, 1),
+           "read_GBps": round(nb / (t_read * 1e-3) / 1e9, 1),
+           "write_GBps": round(nb / (t_write * 1e-3) / 1e9, 1), "copy_ms": t_copy}
+    del a, b
+    return out
+
+
 def copy_reference(nbytes: int):
-    """A plain copy kernel of known size: torch's elementwise copy of nbytes."""
+    """A plain copy kernel of known size: torch's elementwise copy of nbytes
+    (the reference for the HBM counters)."""
     import torch
     n = nbytes // 16
     a = torch.ones(n, 2, dtype=torch.float64, device="cuda")
@@ -179,45 +218,85 @@ def surrogate(args):
     if args.save:
         s.save(args.save)
     Nev, Tev, Aev, Pev = _surrogate_walks(55, args.eval_walks)
+    ne = args.eval_walks
     print("# surrogate: evaluating", file=sys.stderr, flush=True)
-    # the plain walk: best variant (whole rings in registers), one persistent launch
-    plain(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])     # warm-up
+    # outputs stay in HBM for both paths (the timed figures); host-output
+    # variants are reported beside them
+    dev_out = torch.empty((ne, 512), dtype=torch.float32, device="cuda")
+
+    def plain_dev(N, T, ang, psi0):
+        b = qwalk.Batch(N, T, ang, psi0, prec=qwalk.QW_C64, nbins=512)
+        b.run()
+        b.binned(out=dev_out[:len(N)])
+        ms = b.info().last_run_ms
+        b.destroy()
+        torch.cuda.synchronize()
+        return ms
+
+    plain_dev(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])     # warm-up
     tp0 = time.perf_counter()
-    Yev, plain_ms = plain(Nev, Tev, Aev, Pev)
+    plain_ms = plain_dev(Nev, Tev, Aev, Pev)
     tp1 = time.perf_counter()
+    Yev = dev_out.cpu().numpy()
+    th0 = time.perf_counter()
+    Yev_h, _ = plain(Nev, Tev, Aev, Pev)
+    th1 = time.perf_counter()
+    assert np.array_equal(Yev, Yev_h)
     net = s.forward(s.features(Nev, Tev, Aev, Pev), Tev)
     tvd = 0.5 * np.abs(net.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
-    s.predict(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024])   # warm-up
-    ts0 = time.perf_counter()
-    out, fb, st = s.predict(Nev, Tev, Aev, Pev)
-    ts1 = time.perf_counter()
-    tvd_out = 0.5 * np.abs(out.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
+    # what the network adds over answers that ignore the coin and the start
+    # state: the mean training distribution, and the mean over training walks
+    # whose T lies in the same 32-step bin
+    Ytr64 = Ytr.astype(np.float64)
+    ybar = Ytr64.mean(axis=0)
+    tvd_mean = 0.5 * np.abs(ybar[None, :] - Yev.astype(np.float64)).sum(axis=1)
+    tb_tr, tb_ev = Ttr // 32, Tev // 32
+    ybin = {k: Ytr64[tb_tr == k].mean(axis=0) for k in np.unique(tb_ev)}
+    tvd_tbin = np.array([0.5 * np.abs(ybin[k] - y).sum() for k, y in zip(tb_ev, Yev.astype(np.float64))])
+    s.predict(Nev[:1024], Tev[:1024], Aev[:1024], Pev[:1024], out=dev_out[:1024])   # warm-up
+
+    def surr_run(tol, on_device=True):
+        ta = time.perf_counter()
+        o, f, st_ = s.predict(Nev, Tev, Aev, Pev, tvd_tol=tol, out=dev_out if on_device else None)
+        if on_device:
+            torch.cuda.synchronize()
+        tb = time.perf_counter()
+        o = dev_out.cpu().numpy() if on_device else o
+        tv = 0.5 * np.abs(o.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
+        return tb - ta, f, st_, tv
+
+    ts, fb, st, tvd_out = surr_run(1e-3)
+    ts_h, _, _, _ = surr_run(1e-3, on_device=False)
+    plain_wps = ne / (tp1 - tp0)
+    surr_wps = ne / ts
     looser = {}
     for tol in (1e-2, 1e-1, 3e-1):
-        ta = time.perf_counter()
-        o2, f2, s2 = s.predict(Nev, Tev, Aev, Pev, tvd_tol=tol)
-        tb = time.perf_counter()
-        t2 = 0.5 * np.abs(o2.astype(np.float64) - Yev.astype(np.float64)).sum(axis=1)
-        looser[f"{tol:g}"] = {"walks_per_s": args.eval_walks / (tb - ta), "fallback_rate": float(f2.mean()),
-                              "tvd_median": float(np.median(t2)), "tvd_max": float(t2.max())}
+        tt, f2, s2, tv2 = surr_run(tol)
+        looser[f"{tol:g}"] = {"walks_per_s": ne / tt, "fallback_rate": float(f2.mean()),
+                              "speedup": ne / tt / plain_wps, "network_ms": s2.ms_network,
+                              "tvd_median": float(np.median(tv2)), "tvd_max": float(tv2.max())}
     s.destroy()
-    plain_wps = args.eval_walks / (tp1 - tp0)
-    surr_wps = args.eval_walks / (ts1 - ts0)
     res = {
         "metric": "surrogate vs plain walks/s at TVD<=1e-3", "value": surr_wps, "unit": "walks/s",
         "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 (network), f32 (plain walk)",
         "data": "synthetic",
         "config": {"workload": f"surrogate: rings N=4097, T in [256, 2048], SU(2), Haar start; "
-                               f"{args.train_walks} training walks (seed 5), {args.eval_walks} held-out (seed 55)"},
+                               f"{args.train_walks} training walks (seed 5), {ne} held-out (seed 55); "
+                               f"bins written to HBM"},
         "plain_walks_per_s": plain_wps, "plain_kernel_ms": plain_ms,
         "surrogate_walks_per_s": surr_wps, "speedup": surr_wps / plain_wps,
+        "host_output": {"plain_walks_per_s": ne / (th1 - th0), "surrogate_walks_per_s": ne / ts_h},
         "fallback_rate": float(fb.mean()), "failed_chunks": int(st.failed_chunks),
         "recheck_max_tvd": st.max_tvd_sampled,
         "network_ms": st.ms_network, "recheck_ms": st.ms_recheck, "fallback_ms": st.ms_fallback,
+        "network_only_speedup": (plain_ms / st.ms_network) if st.ms_network > 0 else None,
         "tvd_network": {"median": float(np.median(tvd)), "p90": float(np.quantile(tvd, 0.9)),
                         "p99": float(np.quantile(tvd, 0.99)), "max": float(tvd.max()),
                         "frac_le_1e-3": float(np.mean(tvd <= 1e-3)), "frac_le_1e-2": float(np.mean(tvd <= 1e-2))},
         "tvd_output_max": float(tvd_out.max()),
+        "tvd_baselines_median": {"mean_training_distribution": float(np.median(tvd_mean)),
+                                 "mean_over_same_T_bin": float(np.median(tvd_tbin)),
+                                 "network": float(np.median(tvd))},
         "at_looser_tolerance": looser,
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
         "train_s": t2 - t1, "datagen_ms": gen_ms, "setup_s": t1 - t0,
@@ -246,9 +325,22 @@ def traffic_from_profile(kernel_sha: str):
 
 
 def kernel_source_sha():
-    h = hashlib.sha256()
+    """sha256 of the torus streaming kernel's source: the regions of
+    qw_kernels.hip between its begin / end markers (device code and launcher)."""
     with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", "qw_kernels.hip"), "rb") as f:
-        h.update(f.read())
+        src = f.read()
+    begin, end = b"// ---- torus streaming kernel: begin ----", b"// ---- torus streaming kernel: end ----"
+    h = hashlib.sha256()
+    pos = 0
+    while True:
+        i = src.find(begin, pos)
+        if i < 0:
+            break
+        j = src.find(end, i)
+        if j < 0:
+            break
+        h.update(src[i:j])
+        pos = j + len(end)
     return h.hexdigest()
 
 
@@ -287,8 +379,10 @@ def main():
     d = len(disp)
 
     w = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=prec)
-    if args.depth:
-        w.set_options(block_depth=args.depth)
+    if args.depth or args.prefetch or args.waves:
+        w.set_options(block_depth=args.depth, prefetch_rows=args.prefetch, stream_waves=args.waves)
+    if args.broken_links > 0.0:
+        w.set_broken_links(args.broken_links, seed=1, realization=0)
     P = torch.empty(V, dtype=torch.float64, device="cuda")
 
     def one_walk():
@@ -332,6 +426,7 @@ def main():
     sha = kernel_source_sha()
     traffic = traffic_from_profile(sha) if (dom == "stream2d" and args.workload == "grover2d"
                                             and prec == qwalk.QW_C128 and not args.depth) else None
+    ref = hbm_reference()
     roofline = {
         "bound": "hbm", "kernel": dom,
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -340,6 +435,12 @@ def main():
         "launches": pk["launches"], "avg_launch_ms": round(avg_ms, 5),
         "alg_bytes_per_launch": round(bytes_per_launch),
         "kernel_share_of_step": round(pk["ms"] / (elapsed * 1e3), 4),
+        "measured_ceiling": ref,
+        "frac_of_copy": round(achieved / ref["copy_GBps"], 4),
+        # the least any launch of this kernel must move: its box read once and
+        # written once (halo re-reads excluded)
+        "min_bytes_per_launch": round(2 * pk["bytes_written"] / launches),
+        "frac_min_bytes": round(2 * pk["bytes_written"] / launches / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
     }
 
     out = {
@@ -351,7 +452,8 @@ def main():
         "config": {"workload": f"{args.workload}: {'x'.join(str(e) for e in ext)} "
                                f"{'ring' if cfg['dim'] == 1 else 'torus'}, T={T}, {prec_name}",
                    "lattice": list(ext), "T": T, "coin_dim": d, "precision": prec_name,
-                   "block_depth": args.depth or "library default", "parallelism": "single GPU"},
+                   "block_depth": args.depth or "library default", "parallelism": "single GPU",
+                   **({"broken_link_probability": args.broken_links} if args.broken_links > 0 else {})},
         "roofline": roofline,
         "updates_per_walk": updates_per_walk,
         "dense_equiv_updates_per_s": V * d * T * args.steps / elapsed,
@@ -360,7 +462,7 @@ def main():
         "origin_probability": origin_p,
     }
 
-    if not args.no_extras and args.workload.startswith("grover2d"):
+    if not args.no_extras and args.workload.startswith("grover2d") and args.broken_links == 0.0:
         extras = {}
         # unblocked kernel, for the HBM roofline of one step per launch
         w.set_options(block_depth=1, profile=1)
@@ -401,7 +503,7 @@ def main():
         w2.destroy()
         out["extras"] = extras
 
-    if not args.no_cpu_baseline and cfg["dim"] == 2:
+    if not args.no_cpu_baseline and cfg["dim"] == 2 and args.broken_links == 0.0:
         import oracle
         Ts = args.cpu_sample_steps
         Lx, Ly = ext

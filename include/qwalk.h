@@ -92,7 +92,7 @@ typedef struct {
 
 /* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
  * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
- * renorm_tol 1e-7, profile 0. */
+ * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3). */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
                               or 2, 4, 8, 16 (temporal blocking) */
@@ -103,6 +103,11 @@ typedef struct {
     double renorm_tol;
     int32_t profile;       /* 1: bracket every step-kernel launch with HIP events on the
                               walk's stream (read back by walk_profile) */
+    int32_t prefetch_rows; /* torus streaming kernel: input rows each wave has requested
+                              ahead of the row it computes; 0 = default (3), 1 or 3 */
+    int32_t stream_waves;  /* torus streaming kernel: target waves per launch (rows are split
+                              into segments of at least 4 K rows to reach it); 0 = default
+                              (16384 for QW_C128, 4096 for QW_C64) */
     int32_t reserved;
 } qw_options;
 
@@ -185,6 +190,35 @@ int walk_get_state(qw_walk_t w, double *out, int32_t out_on_device);
  * is switched to the whole lattice; t is kept. */
 int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device);
 
+/* Random broken links (Sec. 3, Eq. (9) and the evolution equation (10)): at
+ * every step each link of the lattice is broken with probability p, and a
+ * component that would cross a broken link stays on its site with its coin
+ * index complemented (reflected): psi'(x, c) = (C psi)(x, cbar) instead of
+ * (C psi)(x - e_c, c), e_cbar = -e_c.  The draws are Philox4x32-10 (Salmon et
+ * al., SC'11) at counter (link id low and high 32 bits, step index, realization)
+ * with key (seed low and high 32 bits); a link is broken when the first output
+ * word is below floor(p * 2^32).  Links: the components form opposite pairs; in
+ * each pair the positive member has e.x > 0, or e.x = 0 and e.y > 0, and pairs
+ * are numbered by it in component order; the link that a move along the
+ * positive member leaves site (x, y) by has id (y * Lx + x) * npairs + pair, and
+ * the move back across it (the negative member, from the other end) uses the
+ * same id.  Step indices count from 0 at t = 0.
+ * p = 0 switches the links back to intact.  Call at t = 0 (after walk_create or
+ * walk_reset; walk_reset keeps the setting).  While links break: one step per
+ * kernel launch, walk_step_inverse is refused, walk_set_state only at t = 0.
+ * QW_EINVAL: p outside [0, 1], t != 0, or a table without opposite pairs;
+ * QW_ERANGE: realization >= 2^32. */
+int walk_set_broken_links(qw_walk_t w, double p, uint64_t seed, uint64_t realization);
+
+/* Reflecting walls (the finite "segment" walk of Sec. 3 and Fig. 3, and its 2D
+ * box): on = 1 breaks, at every step, the links through which a move would wrap
+ * around the periodic lattice, so the ring becomes a segment of N sites and the
+ * torus an Lx x Ly box whose edges reflect (a broken link as in
+ * walk_set_broken_links; combines with random links).  on = 0: periodic again.
+ * Call at t = 0; walk_reset keeps it; the same restrictions as broken links.
+ * QW_EINVAL: on not 0/1, t != 0, or a table without opposite pairs. */
+int walk_set_reflecting_walls(qw_walk_t w, int32_t on);
+
 int walk_set_options(qw_walk_t w, const qw_options *opt);
 int walk_get_options(qw_walk_t w, qw_options *opt);
 /* Steps taken so far. */
@@ -234,7 +268,12 @@ typedef struct {
                                     0 = default (every 64 steps in QW_C64, never in QW_C128),
                                     > 0 = every so many steps (rings held whole; longer rings
                                     check after every K-step block), < 0 = never */
-    int32_t reserved;
+    int32_t whole_max_sites;     /* which rings are held whole in one workgroup's registers
+                                    (all N sites every step; at most 4608 sites in QW_C64,
+                                    2048 in QW_C128) instead of running tiled over their light
+                                    cone.  0 = default: rings shorter than 2048 sites, and
+                                    rings whose cone wraps (2T >= N); > 0: rings of at most
+                                    max(this, 2047) sites */
 } qw_batch_opts;
 
 typedef struct {
@@ -313,7 +352,8 @@ typedef struct {
     double tvd_tol;       /* a chunk falls back when a re-checked walk is farther (default 1e-3) */
     int64_t chunk;        /* walks per chunk (default 1024) */
     uint64_t seed;        /* choice of the re-checked walks */
-    int64_t reserved;
+    int32_t out_on_device;  /* 1: out is device memory (n x 512 floats on the handle's GPU) */
+    int32_t reserved;
 } qw_predict_opts;
 
 typedef struct {
@@ -353,10 +393,12 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int
 /* Inputs accepted without fallback: ring size N, T in [tmin, tmax]. */
 int surr_set_range(qw_surr_t s, int64_t N, int32_t tmin, int32_t tmax);
 /* Binned P of n walks (host arrays as for walk_batch_create; x0 = N/2) into
- * out (host, n x 512): the network answers; walks outside the training range
- * and every chunk whose seeded re-check sample exceeds tvd_tol are answered by
- * the plain walk (complex64 batch); used_fallback (host, n bytes, may be NULL)
- * marks them.  Re-checked walks keep their plain result.  Synchronises. */
+ * out (n x 512 floats; host, or device memory with opts->out_on_device): the
+ * network answers; walks outside the training range and every chunk whose
+ * seeded re-check sample exceeds tvd_tol are answered by the plain walk
+ * (complex64 batch); used_fallback (host, n bytes, may be NULL) marks them.
+ * Re-checked walks keep their plain result.  Everything between the upload of
+ * the walk parameters and the final copy stays in HBM.  Synchronises. */
 int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles,
                  const double *psi0, const qw_predict_opts *opts, float *out, uint8_t *used_fallback,
                  qw_predict_stats *stats);

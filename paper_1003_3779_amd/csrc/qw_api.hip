@@ -198,6 +198,9 @@ struct qw_walk {
     bool full[2] = {false, false};
     int emin[2] = {0, 0}, emax[2] = {0, 0};
     qw_options opt;
+    // random broken links (walk_set_broken_links); rbl.step is filled per launch
+    bool rbl_on = false;
+    Links rbl{};
     int64_t since_check = 0;
     int64_t checks = 0, launches = 0, updates = 0;
     // profiling: event pairs pending read-back, a pool of spare events, totals per kernel kind
@@ -277,7 +280,9 @@ void *oth_buf(qw_walk *w) { return w->buf[1 - w->cur]; }
 
 int default_depth(const qw_walk *w) {
     if (w->dim == 1) return 16;
-    return 8;
+    // torus: complex128 fits 8 levels in registers; complex64 16 (measured on
+    // the 4096^2 Grover walk: 16 is ~3% faster than 8 in complex64)
+    return w->prec == C64 ? 16 : 8;
 }
 
 hipEvent_t take_event(qw_walk *w) {
@@ -346,9 +351,12 @@ int stepK(qw_walk *w, int K, bool ring) {
         QW_HIP(launch_ring_tiles(w->prec, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream, &li),
                "ring tile kernel");
     else
-        QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream,
-                               &li),
+    {
+        const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves};
+        QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
+                               w->stream, &li),
                "2D streaming kernel");
+    }
     tm.done(ring ? QW_KERNEL_RING_TILES : QW_KERNEL_STREAM2D, li, (double)upd);
     w->cur ^= 1;
     w->launches++;
@@ -356,8 +364,75 @@ int stepK(qw_walk *w, int K, bool ring) {
     return QW_OK;
 }
 
+// the links of the shift pending in a_t: those of step t - 1 (none at t = 0)
+Links pending_links(const qw_walk *w) {
+    Links L = w->rbl;
+    L.step = w->rbl_on ? w->t - 1 : -1;
+    if (!w->rbl_on) {
+        L.thr = 0;
+        L.walls = 0;
+    }
+    return L;
+}
+
+// opposite pairs of the displacement table into L (opp, pos, pair, np); the
+// positive member has e.x > 0, or e.x = 0 and e.y > 0; pairs are numbered by
+// it in component order.  Returns QW_OK or sets the error.
+int link_tables(const qw_walk *w, Links &L) {
+    int np = 0;
+    for (int c = 0; c < w->d; ++c) {
+        const int ex = w->g.ex[c], ey = w->g.ey[c];
+        if (ex == 0 && ey == 0) return fail(QW_EINVAL, "broken links need nonzero displacements");
+        L.opp[c] = -1;
+        for (int k = 0; k < w->d; ++k)
+            if (k != c && w->g.ex[k] == -ex && w->g.ey[k] == -ey) L.opp[c] = k;
+        if (L.opp[c] < 0)
+            return fail(QW_EINVAL, "broken links need every displacement's opposite in the table (component %d)", c);
+        L.pos[c] = ex > 0 || (ex == 0 && ey > 0);
+        L.pair[c] = -1;
+    }
+    for (int c = 0; c < w->d; ++c)
+        if (L.pos[c]) {
+            L.pair[c] = np;
+            L.pair[L.opp[c]] = np;
+            ++np;
+        }
+    L.np = np;
+    return QW_OK;
+}
+
+// one step with broken links: the pending shift (links of step t - 1), then the coin
+int step1_rbl(qw_walk *w) {
+    const Links L = pending_links(w);
+    grow_forward(w, 1);
+    const Box b = state_box(w);
+    LaunchInfo li;
+    Timed tm(w);
+    QW_HIP(launch_step_rbl(w->prec, w->coin_impl, cur_buf(w), oth_buf(w), w->g, b, w->C, L, w->stream, &li),
+           "broken-link step kernel");
+    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d);
+    w->cur ^= 1;
+    w->launches++;
+    w->updates += box_sites(b) * w->d;
+    w->t += 1;  // the next step's pending links follow this step's index
+    return QW_OK;
+}
+
 int run_forward(qw_walk *w, int64_t n) {
     if (n <= 0) return QW_OK;
+    if (w->rbl_on) {
+        // one step per launch: every step draws its own links
+        const int64_t t0 = w->t;
+        for (int64_t k = 0; k < n; ++k) {
+            int rc = step1_rbl(w);
+            if (rc) {
+                w->t = t0;
+                return rc;
+            }
+        }
+        w->t = t0;  // the caller advances t by n
+        return QW_OK;
+    }
     int depth = w->opt.block_depth ? w->opt.block_depth : default_depth(w);
     if (w->dim == 1 && w->ring_std && depth > 1 && w->g.Lx <= ring_whole_max_sites(w->prec)) {
         // the whole ring in one workgroup: all n steps in one launch (every
@@ -500,7 +575,8 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     w->opt.renorm_every = prec == QW_C64 ? 64 : 0;
     w->opt.renorm_tol = 1e-7;
     w->opt.profile = 0;
-    w->opt.reserved = 0;
+    w->opt.prefetch_rows = 0;
+    w->opt.stream_waves = 0;
     for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
     set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
@@ -637,6 +713,7 @@ int walk_step(qw_walk_t w, int64_t T) {
 int walk_step_inverse(qw_walk_t w, int64_t T) {
     if (!w) return fail(QW_EINVAL, "walk handle is NULL");
     if (T < 0) return fail(QW_EINVAL, "step count must be >= 0 (got %lld)", (long long)T);
+    if (w->rbl_on) return fail(QW_EINVAL, "inverse steps are not available while links break at random");
     DeviceGuard dg(w->device);
     for (int64_t s = 0; s < T; ++s) {
         grow_inverse(w, 1);
@@ -670,7 +747,11 @@ int walk_probabilities(qw_walk_t w, double *out, int32_t out_on_device) {
     }
     const Box pb = psi_box(w);
     if (box_sites(pb) < w->g.ps) QW_HIP(launch_fill_zero(P, pbytes, w->stream), "fill kernel");
-    QW_HIP(launch_prob_norm(w->prec, cur_buf(w), w->g, pb, P, w->scr, w->stream), "probability kernel");
+    if (w->rbl_on && w->t > 0)
+        QW_HIP(launch_prob_norm_rbl(w->prec, cur_buf(w), w->g, pb, P, w->scr, pending_links(w), w->stream),
+               "probability kernel");
+    else
+        QW_HIP(launch_prob_norm(w->prec, cur_buf(w), w->g, pb, P, w->scr, w->stream), "probability kernel");
     if (!out_on_device) {
         QW_HIP(hipMemcpyAsync(out, P, pbytes, hipMemcpyDeviceToHost, w->stream), "copy of P(x) to the host");
         QW_HIP(hipStreamSynchronize(w->stream), "stream synchronise");
@@ -701,7 +782,9 @@ int walk_get_state(qw_walk_t w, double *out, int32_t out_on_device) {
             return fail(QW_ENOMEM, "hipMalloc of the state staging buffer failed: %s", hipGetErrorString(e));
         }
     }
-    hipError_t e = launch_get_state(w->prec, cur_buf(w), w->g, dst, w->stream);
+    hipError_t e = (w->rbl_on && w->t > 0)
+                       ? launch_get_state_rbl(w->prec, cur_buf(w), w->g, dst, pending_links(w), w->stream)
+                       : launch_get_state(w->prec, cur_buf(w), w->g, dst, w->stream);
     if (e == hipSuccess && !out_on_device) {
         e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, w->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
@@ -714,6 +797,8 @@ int walk_get_state(qw_walk_t w, double *out, int32_t out_on_device) {
 int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device) {
     if (!w) return fail(QW_EINVAL, "walk handle is NULL");
     if (!in) return fail(QW_EINVAL, "input pointer is NULL");
+    if (w->rbl_on && w->t > 0)
+        return fail(QW_EINVAL, "with broken links the state can be set only at t = 0 (walk_reset first)");
     DeviceGuard dg(w->device);
     const size_t bytes = (size_t)w->g.ps * w->d * 2 * sizeof(double);
     const double *src = in;
@@ -758,6 +843,13 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
     if (o->renorm_every < 0) return fail(QW_EINVAL, "renorm_every must be >= 0");
     if (!(o->renorm_tol >= 0.0)) return fail(QW_EINVAL, "renorm_tol must be >= 0");
     if (o->profile != 0 && o->profile != 1) return fail(QW_EINVAL, "profile must be 0 or 1");
+    {
+        const int pr = o->prefetch_rows;
+        if (!(pr == 0 || pr == 1 || pr == 3))
+            return fail(QW_EINVAL, "prefetch_rows must be 0, 1 or 3 (got %d)", o->prefetch_rows);
+    }
+    if (o->stream_waves < 0 || o->stream_waves > (1 << 20))
+        return fail(QW_EINVAL, "stream_waves must be in [0, 2^20] (got %d)", o->stream_waves);
     w->opt = *o;
     w->since_check = 0;
     return QW_OK;
@@ -767,6 +859,42 @@ int walk_get_options(qw_walk_t w, qw_options *o) {
     if (!w) return fail(QW_EINVAL, "walk handle is NULL");
     if (!o) return fail(QW_EINVAL, "options pointer is NULL");
     *o = w->opt;
+    return QW_OK;
+}
+
+int walk_set_broken_links(qw_walk_t w, double p, uint64_t seed, uint64_t realization) {
+    if (!w) return fail(QW_EINVAL, "walk handle is NULL");
+    if (!(p >= 0.0 && p <= 1.0)) return fail(QW_EINVAL, "link breaking probability must lie in [0, 1]");
+    if (w->t != 0) return fail(QW_EINVAL, "broken links can be set only at t = 0 (after walk_create or walk_reset)");
+    if (realization > 0xFFFFFFFFull) return fail(QW_ERANGE, "realization must fit in 32 bits");
+    Links L = w->rbl;
+    if (p > 0.0) {
+        int rc = link_tables(w, L);
+        if (rc) return rc;
+    }
+    L.thr = (uint64_t)floor(p * 4294967296.0);
+    L.key0 = (uint32_t)seed;
+    L.key1 = (uint32_t)(seed >> 32);
+    L.realization = (uint32_t)realization;
+    L.step = -1;
+    w->rbl = L;
+    w->rbl_on = L.thr != 0 || L.walls != 0;
+    return QW_OK;
+}
+
+int walk_set_reflecting_walls(qw_walk_t w, int32_t on) {
+    if (!w) return fail(QW_EINVAL, "walk handle is NULL");
+    if (on != 0 && on != 1) return fail(QW_EINVAL, "on must be 0 or 1");
+    if (w->t != 0) return fail(QW_EINVAL, "walls can be set only at t = 0 (after walk_create or walk_reset)");
+    Links L = w->rbl;
+    if (on) {
+        int rc = link_tables(w, L);
+        if (rc) return rc;
+    }
+    L.walls = on;
+    L.step = -1;
+    w->rbl = L;
+    w->rbl_on = L.thr != 0 || L.walls != 0;
     return QW_OK;
 }
 

@@ -188,6 +188,21 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
         if (m < cnt && x == p0) { a0[m].x = (R)w.pre[0]; a0[m].y = (R)w.pim[0]; }
         if (m < cnt && x == p1) { a1[m].x = (R)w.pre[1]; a1[m].y = (R)w.pim[1]; }
     }
+    // light cone: after step s the state vanishes farther than s + 2 sites
+    // (ring distance) from x0, so a wave all of whose sites lie farther than
+    // that keeps its zeros and skips the coin (wave-uniform branch); it still
+    // takes part in the neighbour exchange
+    int dmin = 0;
+    {
+        const int wlo = (j >> 6) * 64 * M;
+        const int whi = min(N, wlo + 64 * M) - 1;
+        auto ring_dist = [&](int x) {
+            const int d = x > w.x0 ? x - w.x0 : w.x0 - x;
+            return d < N - d ? d : N - d;
+        };
+        if (wlo >= N) dmin = N;
+        else if (w.x0 < wlo || w.x0 > whi) dmin = min(ring_dist(wlo), ring_dist(whi));
+    }
     // T steps, then one more exchange round for P (parity continues)
     int npar = 0;
     for (int s = 0; s <= w.T; ++s) {
@@ -221,7 +236,7 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
             L1[p][j] = a1[0];
         }
         __syncthreads();
-        if (active) {
+        if (active && (s == w.T || dmin <= s + 2)) {
             const cv<R> left = L0[p][jl], right = L1[p][jr];
             if (s < w.T) {
                 // in place, ascending m: a0[m-1] is carried, a1[m+1] is still old
@@ -442,6 +457,7 @@ __global__ void k_queue_reset(unsigned int *q) {
     q[1] = 0u;
 }
 
+constexpr int kMinTiledSites = 2048;  // shorter rings are always held whole
 constexpr int kMaxMC128 = 4;   // whole-ring sites per thread (register budget)
 constexpr int kMaxMC64 = 9;
 
@@ -556,7 +572,10 @@ struct qw_batch {
     int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int bucket_cfg[3] = {3, 3, 3};
+    // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (512 sites, 32
+    // steps) for the short rings, (1024, 64) for the long ones -- what the tuner
+    // picks on the 4096-ring workload
+    int bucket_cfg[3] = {1, 3, 3};
     double last_ms = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool own_stream = false;
@@ -656,6 +675,7 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         return bfail(QW_EINVAL, "nbins must be 0 or even and <= %d (got %d)", kMaxBins, o.nbins);
     if (o.tiled_variant < 0 || o.tiled_variant > kNumCfg)
         return bfail(QW_EINVAL, "tiled_variant must be 0 (tuned) or 1..%d", kNumCfg);
+    if (o.whole_max_sites < 0) return bfail(QW_EINVAL, "whole_max_sites must be >= 0");
     qw_batch *b = new (std::nothrow) qw_batch();
     if (!b) return bfail(QW_ENOMEM, "host allocation failed");
     b->prec = prec;
@@ -718,8 +738,19 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         w.pim[0] = psi0[4 * i + 1];
         w.pre[1] = cd * psi0[4 * i + 2] - sd * psi0[4 * i + 3];
         w.pim[1] = sd * psi0[4 * i + 2] + cd * psi0[4 * i + 3];
+        // whole ring in registers, or tiled over the light cone?  The whole-ring
+        // path updates all N sites every step with no memory traffic; the tiled
+        // path updates only the cone (on average about T sites of the N) at a
+        // higher cost per update.  Measured on 65536 rings of 4097 sites
+        // (T in [256, 2048]): tiled 80 ms, whole 142 ms.  Default: tiled unless
+        // the ring is short or the cone wraps it (2T >= N: no cone to save).
         const int64_t m = (N[i] + kBT - 1) / kBT;
-        if (m <= mmax) {
+        bool whole = m <= mmax;
+        if (o.whole_max_sites > 0)
+            whole = whole && N[i] <= std::max<int64_t>(o.whole_max_sites, kMinTiledSites - 1);
+        else
+            whole = whole && (N[i] < kMinTiledSites || 2 * T[i] >= N[i]);
+        if (whole) {
             w.cfg = -1;
             w.m = (int32_t)m;
         } else {

@@ -66,12 +66,45 @@ hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
                              const Box &out_box, const CoinF64 &C, int K, hipStream_t s,
                              LaunchInfo *info);
 // K steps on a torus with the row-streaming register kernel
+// Random broken links (Sec. 3, Eqs. (9)-(10)) of one step: a link is broken
+// when word 0 of Philox4x32-10 at counter (link id lo, hi, step, realization),
+// key (seed lo, hi), is below thr.  step < 0 or thr == 0: every link intact.
+// Link of the move along component c into site y: positive member of the
+// pair (pos[c]): the link of the start site y - e_c; otherwise the link of y;
+// id = site * np + pair[c].  A broken move delivers component opp[c] of y.
+// walls != 0: the links a move would wrap through are always broken (finite
+// segment / box with reflecting walls).
+struct Links {
+    uint64_t thr;            // in [0, 2^32]
+    uint32_t key0, key1;
+    uint32_t realization;
+    int32_t np;
+    int64_t step;
+    int32_t opp[4], pos[4], pair[4];
+    int32_t walls;
+};
+
+// launch shape of the torus streaming kernel
+struct StreamTune {
+    int prefetch;  // input rows read ahead, in registers: 1 or 3
+    int waves;     // waves to launch (0 = default)
+};
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out,
                            const Geom &g, const Box &out_box, const CoinF64 &C, int K,
-                           hipStream_t s, LaunchInfo *info);
+                           const StreamTune &tune, hipStream_t s, LaunchInfo *info);
 bool stream2d_supported(int prec, int table, int K);
 // P(x) (if P != nullptr) and the fp64 norm into scratch->norm.  psi_box: the box
 // outside which psi is zero.
+// one step with random broken links: the pending shift of a_t uses the links
+// of L (the previous step), then the coin: a_{t+1}(y, c) = sum C[c][c'] (S_L a_t)(y, c')
+hipError_t launch_step_rbl(int prec, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                           const CoinF64 &C, const Links &L, hipStream_t s, LaunchInfo *info);
+// P(x) and the norm of psi = S_L a (box b), as launch_prob_norm
+hipError_t launch_prob_norm_rbl(int prec, const void *state, const Geom &g, const Box &b, double *P, Scratch *scr,
+                                const Links &L, hipStream_t s);
+// psi = S_L a over the whole lattice as complex128 (d, Ly, Lx)
+hipError_t launch_get_state_rbl(int prec, const void *state, const Geom &g, void *out, const Links &L,
+                                hipStream_t s);
 hipError_t launch_prob_norm(int prec, const void *state, const Geom &g, const Box &psi_box,
                             double *P, Scratch *scr, hipStream_t s);
 // norm of the state (no shift needed: S is a permutation) into scratch->norm

@@ -246,27 +246,32 @@ __host__ __device__ constexpr int tab_ey(int table, int c) {
                                : ((c & 1) == 0 ? 1 : -1);  // TABLE_DIAG
 }
 
+// ---- torus streaming kernel: begin ----
 template <typename R, int K, int M> struct StreamRegs {
     cv<R> v[K][3][4][M];  // [level][row slot][component][column]
 };
 
-template <typename R, int K, int M, int TABLE, int COIN, int PH>
-__device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)[4][M], const cv<R> *__restrict__ in,
+// PD: rows of read-ahead held in registers (1 or 3)
+template <typename R, int K, int M, int TABLE, int COIN, int PD, int PH>
+__device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)[PD][4][M],
+                                            const cv<R> *__restrict__ in,
                                             cv<R> *__restrict__ out, const Geom &g, const int (&xcol)[M],
                                             const bool (&store_col)[M], int row_next, int row_out,
                                             bool do_store, const CoinR<R> &C) {
     // slot PH receives the newest row, slot (PH+2)%3 holds the row before it
     // (the row being computed at the next level), slot (PH+1)%3 the oldest.
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
-    // this iteration's input row was loaded one iteration ago; the next one is
-    // requested now so that its HBM latency overlaps the K levels below
+    // this iteration's input row was requested PD iterations ago; the row PD
+    // ahead is requested now into the slot it frees, so that PD rows of loads
+    // are in flight while the K levels below are computed
     cv<R> cur[4][M];
+    constexpr int PS = PH % PD;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            cur[c][m] = pf[c][m];
-            pf[c][m] = in[(int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol[m]];
+            cur[c][m] = pf[PS][c][m];
+            pf[PS][c][m] = in[(int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol[m]];
         }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -312,9 +317,10 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
     }
 }
 
-template <typename R, int K, int M, int TABLE, int COIN>
+template <typename R, int K, int M, int TABLE, int COIN, int PD>
 __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
                                                   Geom g, Box b, int seg_rows, int nstrips, CoinR<R> C) {
+    static_assert(PD == 1 || PD == 3, "the stream loop is unrolled by 3: read-ahead 1 or 3 rows");
     constexpr int TW = 64 * M - 2 * K;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -342,31 +348,37 @@ __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, 
 #pragma unroll
                 for (int m = 0; m < M; ++m) st.v[s][r][c][m] = czero<R>();
     const int niter = nrows + 2 * K;
-    int row_in = (b.y0 + r0 - K) % g.Ly;
-    row_in = row_in < 0 ? row_in + g.Ly : row_in;
-    int row_out = (b.y0 + r0 - 2 * K) % g.Ly;  // advanced in step with row_in
+    int row_ld = (b.y0 + r0 - K) % g.Ly;  // next input row to request
+    row_ld = row_ld < 0 ? row_ld + g.Ly : row_ld;
+    int row_out = (b.y0 + r0 - 2 * K) % g.Ly;  // advanced in step with the input
     row_out = row_out < 0 ? row_out + g.Ly : row_out;
-    cv<R> pf[4][M];  // the next input row, loaded one iteration ahead
+    cv<R> pf[PD][4][M];  // input rows requested ahead of use
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < PD; ++p) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) pf[c][m] = in[(int64_t)c * g.ps + (int64_t)row_in * g.Lx + xcol[m]];
-    // (rows past the segment end are loaded too -- in bounds, modulo Ly -- and never used)
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < M; ++m) pf[p][c][m] = in[(int64_t)c * g.ps + (int64_t)row_ld * g.Lx + xcol[m]];
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+    }
+    // (rows past the segment end are requested too -- in bounds, modulo Ly -- and never used)
     for (int i = 0; i < niter; i += 3) {
-        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
-        stream_iter<R, K, M, TABLE, COIN, 0>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
-                                             i >= 2 * K && i < niter, C);
+        stream_iter<R, K, M, TABLE, COIN, PD, 0>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                 i >= 2 * K && i < niter, C);
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
-        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
-        stream_iter<R, K, M, TABLE, COIN, 1>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
-                                             i + 1 >= 2 * K && i + 1 < niter, C);
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+        stream_iter<R, K, M, TABLE, COIN, PD, 1>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                 i + 1 >= 2 * K && i + 1 < niter, C);
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
-        row_in = row_in + 1 == g.Ly ? 0 : row_in + 1;
-        stream_iter<R, K, M, TABLE, COIN, 2>(st, pf, in, out, g, xcol, store_col, row_in, row_out,
-                                             i + 2 >= 2 * K && i + 2 < niter, C);
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+        stream_iter<R, K, M, TABLE, COIN, PD, 2>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                 i + 2 >= 2 * K && i + 2 < niter, C);
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
     }
 }
+
+// ---- torus streaming kernel: end ----
 
 // =====================================================================
 // reductions (fp64): P(x), the norm, renormalisation
@@ -490,6 +502,105 @@ __global__ __launch_bounds__(256) void k_set_state(cv<R> *__restrict__ a, Geom g
         }
     const double s = block_sum256(acc);
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// =====================================================================
+// random broken links (Sec. 3, Eqs. (9)-(10))
+// =====================================================================
+// Philox4x32-10 (Salmon et al., SC'11), first output word: ten rounds of two
+// 32x32 -> 64-bit products of counter words 0 and 2 with the round
+// multipliers, the high halves mixed into the other words and the key, the
+// key advanced by the Weyl increments after every round.
+__device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
+        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
+        c0 = h1 ^ c1 ^ k0;
+        c1 = l1;
+        c2 = h0 ^ c3 ^ k1;
+        c3 = l0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
+// psi(x, y, c) = (S_L a)(x, y, c): the value that the step's shift delivers to
+// component c of site (x, y)
+template <typename R>
+__device__ __forceinline__ cv<R> shifted(const cv<R> *__restrict__ a, const Geom &g, const Links &L, int x, int y,
+                                         int c) {
+    const int rx = x - g.ex[c], ry = y - g.ey[c];
+    const int sx = wrapi(rx, g.Lx), sy = wrapi(ry, g.Ly);
+    if (L.step >= 0) {
+        bool broken = L.walls && (rx < 0 || rx >= g.Lx || ry < 0 || ry >= g.Ly);
+        if (!broken && L.thr != 0) {
+            const uint64_t site = L.pos[c] ? (uint64_t)sy * (uint64_t)g.Lx + (uint64_t)sx
+                                           : (uint64_t)y * (uint64_t)g.Lx + (uint64_t)x;
+            const uint64_t link = site * (uint64_t)L.np + (uint64_t)L.pair[c];
+            const uint32_t w0 = philox_w0((uint32_t)link, (uint32_t)(link >> 32), (uint32_t)L.step,
+                                          L.realization, L.key0, L.key1);
+            broken = (uint64_t)w0 < L.thr;
+        }
+        if (broken) return a[(int64_t)L.opp[c] * g.ps + (int64_t)y * g.Lx + x];
+    }
+    return a[(int64_t)c * g.ps + (int64_t)sy * g.Lx + sx];
+}
+
+template <typename R, int D, int COIN>
+__global__ __launch_bounds__(256) void k_step_rbl(const cv<R> *__restrict__ in, cv<R> *__restrict__ out, Geom g,
+                                                  Box b, CoinR<R> C, Links L) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= b.wx) return;
+    int x = b.x0 + i;
+    x = x >= g.Lx ? x - g.Lx : x;
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        cv<R> v[D], o[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = shifted<R>(in, g, L, x, y, c);
+        Coin<R, D, COIN>::apply(v, o, C);
+        const int64_t o0 = (int64_t)y * g.Lx + x;
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[(int64_t)c * g.ps + o0] = o[c];
+    }
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_prob_rbl(const cv<R> *__restrict__ a, Geom g, Box b, Links L,
+                                                  double *__restrict__ P, double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int j = blockIdx.y; j < b.wy; j += gridDim.y) {
+        int y = b.y0 + j;
+        y = y >= g.Ly ? y - g.Ly : y;
+        for (int i = blockIdx.x * 256 + threadIdx.x; i < b.wx; i += gridDim.x * 256) {
+            int x = b.x0 + i;
+            x = x >= g.Lx ? x - g.Lx : x;
+            double p = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) p += abs2<R>(shifted<R>(a, g, L, x, y, c));
+            if (P) P[(int64_t)y * g.Lx + x] = p;
+            acc += p;
+        }
+    }
+    const double s = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_get_state_rbl(const cv<R> *__restrict__ a, Geom g, Links L,
+                                                       double2 *__restrict__ out) {
+    for (int y = blockIdx.y; y < g.Ly; y += gridDim.y)
+        for (int x = blockIdx.x * 256 + threadIdx.x; x < g.Lx; x += gridDim.x * 256) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const cv<R> v = shifted<R>(a, g, L, x, y, c);
+                out[(int64_t)c * g.ps + (int64_t)y * g.Lx + x] = make_double2((double)v.x, (double)v.y);
+            }
+        }
 }
 
 // grid for box-shaped reductions: at most kRedBlocks blocks
@@ -671,14 +782,18 @@ hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
     return hipGetLastError();
 }
 
-template <typename R, int K, int M, int TABLE, int COIN>
-static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, hipStream_t s,
-                     LaunchInfo *info) {
+// ---- torus streaming kernel: begin ----
+template <typename R, int K, int M, int TABLE, int COIN, int PD>
+static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
+                     const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
     constexpr int TW = 64 * M - 2 * K;
     const int nstrips = (b.wx + TW - 1) / TW;
-    // rows per segment: enough waves to fill the chip (~2 per SIMD), but
-    // segments no shorter than 4K rows (the 2K-row re-read stays <= 50%)
-    const long target_waves = 2048;
+    // rows per segment: many short segments (down to 4K rows, the 2K-row
+    // re-read then stays <= 50%) run faster than a few long ones: the launch
+    // drains in many small waves instead of a long tail, and more loads are in
+    // flight (measured on the 4096^2 torus: 16384 target waves for complex128,
+    // 4096 for complex64)
+    const long target_waves = tu.waves > 0 ? tu.waves : (sizeof(R) == 8 ? 16384 : 4096);
     long segs = (target_waves + nstrips - 1) / nstrips;
     int seg_rows = (int)((b.wy + segs - 1) / segs);
     if (seg_rows < 4 * K) seg_rows = 4 * K;
@@ -690,27 +805,34 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
         info->bytes_read = (double)nstrips * 64 * M * ((double)b.wy + 2.0 * K * nseg) * 4 * sizeof(cv<R>);
         info->bytes_written = (double)b.wx * b.wy * 4 * sizeof(cv<R>);
     }
-    hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
                        (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C));
 }
 
-template <typename R, int K, int M, int TABLE>
+template <typename R, int K, int M, int TABLE, int PD>
 static void stream_coin(int coin_impl, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
-                        hipStream_t s, LaunchInfo *info) {
-    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4>(in, out, g, b, C, s, info);
-    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4>(in, out, g, b, C, s, info);
-    else stream_t<R, K, M, TABLE, COIN_DENSE>(in, out, g, b, C, s, info);
+                        const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
+    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4, PD>(in, out, g, b, C, tu, s, info);
+    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4, PD>(in, out, g, b, C, tu, s, info);
+    else stream_t<R, K, M, TABLE, COIN_DENSE, PD>(in, out, g, b, C, tu, s, info);
+}
+
+template <typename R, int K, int M, int PD>
+static bool stream_table(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                         const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
+    switch (table) {
+    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
+    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
+    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
+    default: return false;
+    }
 }
 
 template <typename R, int K, int M>
-static bool stream_table(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
-                         const CoinF64 &C, hipStream_t s, LaunchInfo *info) {
-    switch (table) {
-    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR>(coin_impl, in, out, g, b, C, s, info); return true;
-    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8>(coin_impl, in, out, g, b, C, s, info); return true;
-    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG>(coin_impl, in, out, g, b, C, s, info); return true;
-    default: return false;
-    }
+static bool stream_pd(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                      const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
+    return tu.prefetch == 1 ? stream_table<R, K, M, 1>(table, coin_impl, in, out, g, b, C, tu, s, info)
+                            : stream_table<R, K, M, 3>(table, coin_impl, in, out, g, b, C, tu, s, info);
 }
 
 bool stream2d_supported(int prec, int table, int K) {
@@ -720,24 +842,27 @@ bool stream2d_supported(int prec, int table, int K) {
 }
 
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
-                           const Box &b, const CoinF64 &C, int K, hipStream_t s, LaunchInfo *info) {
+                           const Box &b, const CoinF64 &C, int K, const StreamTune &tu, hipStream_t s,
+                           LaunchInfo *info) {
     if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
     if (!stream2d_supported(prec, table, K)) return hipErrorInvalidValue;
+    if (tu.prefetch != 1 && tu.prefetch != 3) return hipErrorInvalidValue;
     // a strip must not meet itself across the periodic x boundary
+    if (g.Lx < 64) return hipErrorInvalidValue;
     bool ok = false;
     if (prec == C128) {
-        if (g.Lx < 64) return hipErrorInvalidValue;
-        if (K == 4) ok = stream_table<double, 4, 1>(table, coin_impl, in, out, g, b, C, s, info);
-        else ok = stream_table<double, 8, 1>(table, coin_impl, in, out, g, b, C, s, info);
+        if (K == 4) ok = stream_pd<double, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
+        else ok = stream_pd<double, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
     } else {
-        if (g.Lx < 64) return hipErrorInvalidValue;
-        if (K == 4) ok = stream_table<float, 4, 1>(table, coin_impl, in, out, g, b, C, s, info);
-        else if (K == 8) ok = stream_table<float, 8, 1>(table, coin_impl, in, out, g, b, C, s, info);
-        else ok = stream_table<float, 16, 1>(table, coin_impl, in, out, g, b, C, s, info);
+        if (K == 4) ok = stream_pd<float, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
+        else if (K == 8) ok = stream_pd<float, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
+        else ok = stream_pd<float, 16, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
     }
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
+
+// ---- torus streaming kernel: end ----
 
 hipError_t launch_prob_norm(int prec, const void *state, const Geom &g, const Box &b, double *P, Scratch *scr,
                             hipStream_t s) {
@@ -814,6 +939,85 @@ hipError_t launch_set_state(int prec, void *state, const Geom &g, const double *
             hipLaunchKernelGGL((k_set_state<float, 4>), grid, dim3(256), 0, s, (float2 *)state, g, (const double2 *)in, scr->partial);
     }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const double *)scr->partial, nparts, &scr->norm);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- broken links
+template <typename R, int D, int COIN>
+static void step_rbl_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, const Links &L,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_step_rbl<R, D, COIN>), step_grid(b), dim3(256), 0, s, (const cv<R> *)in, (cv<R> *)out, g,
+                       b, to_coin<R>(C), L);
+}
+
+hipError_t launch_step_rbl(int prec, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
+                           const CoinF64 &C, const Links &L, hipStream_t s, LaunchInfo *info) {
+    if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
+    if (info) {
+        const double bytes = (double)b.wx * b.wy * g.d * (prec == C128 ? 16.0 : 8.0);
+        info->bytes_read = bytes;
+        info->bytes_written = bytes;
+    }
+    if (g.d == 2) {
+        if (prec == C128) step_rbl_t<double, 2, COIN_DENSE>(in, out, g, b, C, L, s);
+        else step_rbl_t<float, 2, COIN_DENSE>(in, out, g, b, C, L, s);
+    } else {
+        if (prec == C128) {
+            if (coin_impl == COIN_GROVER4) step_rbl_t<double, 4, COIN_GROVER4>(in, out, g, b, C, L, s);
+            else if (coin_impl == COIN_HH4) step_rbl_t<double, 4, COIN_HH4>(in, out, g, b, C, L, s);
+            else step_rbl_t<double, 4, COIN_DENSE>(in, out, g, b, C, L, s);
+        } else {
+            if (coin_impl == COIN_GROVER4) step_rbl_t<float, 4, COIN_GROVER4>(in, out, g, b, C, L, s);
+            else if (coin_impl == COIN_HH4) step_rbl_t<float, 4, COIN_HH4>(in, out, g, b, C, L, s);
+            else step_rbl_t<float, 4, COIN_DENSE>(in, out, g, b, C, L, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prob_norm_rbl(int prec, const void *state, const Geom &g, const Box &b, double *P, Scratch *scr,
+                                const Links &L, hipStream_t s) {
+    dim3 grid;
+    red_grid(b.wx, b.wy, grid);
+    const int nparts = grid.x * grid.y;
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_prob_rbl<double, 2>), grid, dim3(256), 0, s, (const double2 *)state, g, b, L, P,
+                               scr->partial);
+        else
+            hipLaunchKernelGGL((k_prob_rbl<float, 2>), grid, dim3(256), 0, s, (const float2 *)state, g, b, L, P,
+                               scr->partial);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_prob_rbl<double, 4>), grid, dim3(256), 0, s, (const double2 *)state, g, b, L, P,
+                               scr->partial);
+        else
+            hipLaunchKernelGGL((k_prob_rbl<float, 4>), grid, dim3(256), 0, s, (const float2 *)state, g, b, L, P,
+                               scr->partial);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const double *)scr->partial, nparts, &scr->norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state_rbl(int prec, const void *state, const Geom &g, void *out, const Links &L,
+                                hipStream_t s) {
+    dim3 grid;
+    red_grid(g.Lx, g.Ly, grid);
+    if (g.d == 2) {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_get_state_rbl<double, 2>), grid, dim3(256), 0, s, (const double2 *)state, g, L,
+                               (double2 *)out);
+        else
+            hipLaunchKernelGGL((k_get_state_rbl<float, 2>), grid, dim3(256), 0, s, (const float2 *)state, g, L,
+                               (double2 *)out);
+    } else {
+        if (prec == C128)
+            hipLaunchKernelGGL((k_get_state_rbl<double, 4>), grid, dim3(256), 0, s, (const double2 *)state, g, L,
+                               (double2 *)out);
+        else
+            hipLaunchKernelGGL((k_get_state_rbl<float, 4>), grid, dim3(256), 0, s, (const float2 *)state, g, L,
+                               (double2 *)out);
+    }
     return hipGetLastError();
 }
 

@@ -166,12 +166,27 @@ __global__ void k_f32_to_bf16(const float *__restrict__ in, bf16_t *__restrict__
         out[i] = f2bf(in[i]);
 }
 
-// db[n] = sum_b dz[b][n] (fixed order over b)
-__global__ void k_colsum(const float *__restrict__ dz, int B, int N, float *__restrict__ db) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// db[n] = sum_b dz[b][n] in two passes (fixed order, so deterministic): pass 1 sums
+// chunk r of ceil(B / kColChunks) rows of every column into part[r][n] over a
+// grid of (columns / 256) x kColChunks blocks; pass 2 adds the chunks in order
+constexpr int kColChunks = 64;
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ dz, int B, int N,
+                                                     float *__restrict__ part) {
+    const int n = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (n >= N) return;
+    const int rows = (B + kColChunks - 1) / kColChunks;
+    const int b0 = r * rows, b1 = min(B, b0 + rows);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += dz[(int64_t)b * N + n];
+    part[(int64_t)r * N + n] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const float *__restrict__ part, int N,
+                                                      float *__restrict__ db) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += dz[(int64_t)b * N + n];
+    for (int r = 0; r < kColChunks; ++r) s += part[(int64_t)r * N + n];
     db[n] = s;
 }
 
@@ -398,16 +413,6 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, 
     if (t < 19) part[(int64_t)b * 19 + t] = red[t][0];
 }
 
-// sum over samples of the per-sample head gradients (fixed order)
-__global__ void k_head_reduce(const float *__restrict__ part, int B, float *__restrict__ gcw, float *__restrict__ gcb) {
-    const int k = threadIdx.x;
-    if (k >= 19) return;
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += part[(int64_t)b * 19 + k];
-    if (k < 18) gcw[k] = s;
-    else gcb[0] = s;
-}
-
 // Adam on fp32 master weights; writes the bf16 copy used by the GEMMs
 __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ g, bf16_t *__restrict__ pb, int64_t n, float lr, float b1,
@@ -441,25 +446,60 @@ __global__ void k_gather(const float *__restrict__ X, const float *__restrict__ 
 // global phase removed, (|a|, Re b', Im b'), b' = b e^{-i arg a}; T/N; cos and
 // sin of delta = arg b - arg a + chi - phi (the relative phase that, with theta
 // and |a|, fixes P); zeros up to 32.
+// the 32 features of walk i (fp64 arithmetic, rounded to fp32)
+__device__ __forceinline__ void feature_row(int64_t i, const int64_t *__restrict__ N, const int64_t *__restrict__ T,
+                                            const double *__restrict__ ang, const double *__restrict__ psi0,
+                                            float (&x)[kF]) {
+    const double th = ang[3 * i], ph = ang[3 * i + 1], ch = ang[3 * i + 2];
+    const double ar = psi0[4 * i], ai = psi0[4 * i + 1], br = psi0[4 * i + 2], bi = psi0[4 * i + 3];
+    const double aa = sqrt(ar * ar + ai * ai);
+    const double arga = aa > 0.0 ? atan2(ai, ar) : 0.0;
+    const double argb = (br != 0.0 || bi != 0.0) ? atan2(bi, br) : 0.0;
+    const double ca = cos(arga), sa = sin(arga);
+    const double bpr = br * ca + bi * sa, bpi = bi * ca - br * sa;  // b e^{-i arg a}
+    const double dl = argb - arga + ch - ph;
+    x[0] = (float)sin(th); x[1] = (float)cos(th);
+    x[2] = (float)sin(ph); x[3] = (float)cos(ph);
+    x[4] = (float)sin(ch); x[5] = (float)cos(ch);
+    x[6] = (float)aa; x[7] = (float)bpr; x[8] = (float)bpi;
+    x[9] = (float)((double)T[i] / (double)N[i]);
+    x[10] = (float)cos(dl); x[11] = (float)sin(dl);
+    for (int k = 12; k < kF; ++k) x[k] = 0.0f;
+}
+
 __global__ void k_features(int64_t n, const int64_t *__restrict__ N, const int64_t *__restrict__ T,
                            const double *__restrict__ ang, const double *__restrict__ psi0, float *__restrict__ X) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double th = ang[3 * i], ph = ang[3 * i + 1], ch = ang[3 * i + 2];
-        const double ar = psi0[4 * i], ai = psi0[4 * i + 1], br = psi0[4 * i + 2], bi = psi0[4 * i + 3];
-        const double aa = sqrt(ar * ar + ai * ai);
-        const double arga = aa > 0.0 ? atan2(ai, ar) : 0.0;
-        const double argb = (br != 0.0 || bi != 0.0) ? atan2(bi, br) : 0.0;
-        const double ca = cos(arga), sa = sin(arga);
-        const double bpr = br * ca + bi * sa, bpi = bi * ca - br * sa;  // b e^{-i arg a}
-        const double dl = argb - arga + ch - ph;
-        float *x = X + i * kF;
-        x[0] = (float)sin(th); x[1] = (float)cos(th);
-        x[2] = (float)sin(ph); x[3] = (float)cos(ph);
-        x[4] = (float)sin(ch); x[5] = (float)cos(ch);
-        x[6] = (float)aa; x[7] = (float)bpr; x[8] = (float)bpi;
-        x[9] = (float)((double)T[i] / (double)N[i]);
-        x[10] = (float)cos(dl); x[11] = (float)sin(dl);
-        for (int k = 12; k < kF; ++k) x[k] = 0.0f;
+        float x[kF];
+        feature_row(i, N, T, ang, psi0, x);
+        for (int k = 0; k < kF; ++k) X[i * kF + k] = x[k];
+    }
+}
+
+// network inputs of n walks, padded with zero rows to npad: bf16 features and
+// the step counts clamped to the head's site table
+__global__ void k_net_inputs(int64_t n, int64_t npad, const int64_t *__restrict__ N, const int64_t *__restrict__ T,
+                             const double *__restrict__ ang, const double *__restrict__ psi0, bf16_t *__restrict__ Xb,
+                             int32_t *__restrict__ T32) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad; i += (int64_t)gridDim.x * blockDim.x) {
+        float x[kF];
+        if (i < n) {
+            feature_row(i, N, T, ang, psi0, x);
+            T32[i] = (int32_t)min(max(T[i], (int64_t)0), (int64_t)(kMaxSites - 1));
+        } else {
+            for (int k = 0; k < kF; ++k) x[k] = 0.0f;
+            T32[i] = 0;
+        }
+        for (int k = 0; k < kF; ++k) Xb[i * kF + k] = f2bf(x[k]);
+    }
+}
+
+// the same for features given as fp32 rows (steps already int32)
+__global__ void k_rows_to_inputs(int64_t n, int64_t npad, const float *__restrict__ X, const int32_t *__restrict__ T,
+                                 bf16_t *__restrict__ Xb, int32_t *__restrict__ T32) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < kF; ++k) Xb[i * kF + k] = f2bf(i < n ? X[i * kF + k] : 0.0f);
+        T32[i] = i < n ? min(max(T[i], 0), kMaxSites - 1) : 0;
     }
 }
 
@@ -477,6 +517,20 @@ __global__ __launch_bounds__(256) void k_tvd(const float *__restrict__ p, const 
         __syncthreads();
     }
     if (t == 0) out[r] = 0.5 * red[0];
+}
+
+// dst[j] = src[idx[j]] (rows of nb floats), one block per row
+__global__ __launch_bounds__(256) void k_gather_rows(const float *__restrict__ src, const int64_t *__restrict__ idx,
+                                                     int nb, float *__restrict__ dst) {
+    const int64_t j = blockIdx.x, r = idx[j];
+    for (int i = threadIdx.x; i < nb; i += 256) dst[j * nb + i] = src[r * nb + i];
+}
+
+// dst[idx[j]] = src[j] (rows of nb floats; idx distinct), one block per row
+__global__ __launch_bounds__(256) void k_scatter_rows(const float *__restrict__ src, const int64_t *__restrict__ idx,
+                                                      int nb, float *__restrict__ dst) {
+    const int64_t j = blockIdx.x, r = idx[j];
+    for (int i = threadIdx.x; i < nb; i += 256) dst[r * nb + i] = src[j * nb + i];
 }
 
 }  // namespace
@@ -549,6 +603,7 @@ struct qw_surr {
     bf16_t *dzb = nullptr, *dzT = nullptr, *hT = nullptr;
     int32_t *idx = nullptr;
     int32_t *tb = nullptr;                     // steps of the batch rows
+    float *colpart = nullptr;                  // kColChunks x 1024 partial column sums
     int64_t adam_t = 0;
     uint64_t seed = 0;
     int64_t train_n = 4097;   // the ring size the network was trained on
@@ -560,7 +615,8 @@ namespace {
 void free_surr(qw_surr *s) {
     if (!s) return;
     void *bufs[] = {s->p, s->m, s->v, s->g, s->pb, s->W2T, s->W3T, s->W4T, s->xb, s->h1, s->h2, s->h3,
-                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx, s->tb};
+                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx, s->tb,
+                    s->colpart};
     for (void *b : bufs) (void)hipFree(b);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -572,6 +628,14 @@ hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int l
     GemmArgs a{A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb};
     dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
     hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// db[n] = sum_b dz[b][n] for N <= 1024 columns (two deterministic passes)
+hipError_t colsum(hipStream_t st, const float *dz, int B, int N, float *part, float *db) {
+    if (N > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 255) / 256, kColChunks), dim3(256), 0, st, dz, B, N, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, st, (const float *)part, N, db);
     return hipGetLastError();
 }
 
@@ -592,9 +656,15 @@ hipError_t refresh_weights(qw_surr *s) {
 }
 
 // forward of B rows already in s->xb; y (device, B x 512) optional -> dl, lrow
-hipError_t forward(qw_surr *s, int B, int Bscale, const float *y) {
+// network forward on B rows (a multiple of 128): inputs xin / tin (default:
+// the handle's batch buffers), output p into qout (default: s->q)
+hipError_t forward(qw_surr *s, int B, int Bscale, const float *y, const bf16_t *xin = nullptr,
+                   const int32_t *tin = nullptr, float *qout = nullptr) {
     hipStream_t st = s->stream;
-    hipError_t e = gemm(st, s->xb, kF, s->pb + L.W1, kF, B, kH1, kF, 1.0f, s->p + L.b1, nullptr, 0, 1, nullptr, 0, s->h1, kH1);
+    if (!xin) xin = s->xb;
+    if (!tin) tin = s->tb;
+    if (!qout) qout = s->q;
+    hipError_t e = gemm(st, xin, kF, s->pb + L.W1, kF, B, kH1, kF, 1.0f, s->p + L.b1, nullptr, 0, 1, nullptr, 0, s->h1, kH1);
     if (e == hipSuccess)
         e = gemm(st, s->h1, kH1, s->pb + L.W2, kH1, B, kH2, kH1, 1.0f, s->p + L.b2, nullptr, 0, 1, nullptr, 0, s->h2, kH2);
     if (e == hipSuccess)
@@ -604,18 +674,48 @@ hipError_t forward(qw_surr *s, int B, int Bscale, const float *y) {
     if (e != hipSuccess) return e;
     const int w = (int)(((s->train_n - 1) / 2) / (kBins / 2));
     hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
-                       (const float *)(s->p + L.cb), (const int32_t *)s->tb, w < 1 ? 1 : w, s->q, y, s->dl, s->lrow,
-                       Bscale);
+                       (const float *)(s->p + L.cb), tin, w < 1 ? 1 : w, qout, y, s->dl, s->lrow, Bscale);
     return hipGetLastError();
 }
+
+// network output of n rows whose inputs are on the device (Xb: npad x 32
+// bf16, T32: npad, npad = n rounded up to 128) into dout (device, npad x 512);
+// no synchronisation
+hipError_t forward_rows(qw_surr *s, int64_t npad, const bf16_t *Xb, const int32_t *T32, float *dout) {
+    for (int64_t r0 = 0; r0 < npad; r0 += s->bmax) {
+        const int bp = (int)std::min<int64_t>(s->bmax, npad - r0);
+        hipError_t e = forward(s, bp, bp, nullptr, Xb + r0 * kF, T32 + r0, dout + r0 * kBins);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// device scratch of one network-only pass over n walks
+struct NetBufs {
+    int64_t npad = 0;
+    bf16_t *xb = nullptr;
+    int32_t *t32 = nullptr;
+    float *out = nullptr;
+    ~NetBufs() { (void)hipFree(xb); (void)hipFree(t32); (void)hipFree(out); }
+    hipError_t alloc(int64_t n) {
+        npad = (n + 127) / 128 * 128;
+        hipError_t e = hipMalloc((void **)&xb, sizeof(bf16_t) * npad * kF);
+        if (e == hipSuccess) e = hipMalloc((void **)&t32, sizeof(int32_t) * npad);
+        if (e == hipSuccess) e = hipMalloc((void **)&out, sizeof(float) * npad * kBins);
+        return e;
+    }
+};
 
 // backward of the batch of the last forward (with targets): gradients into s->g
 hipError_t backward(qw_surr *s, int B) {
     hipStream_t st = s->stream;
     hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
                        (const float *)s->dl, s->dz, s->part);
-    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(64), 0, st, (const float *)s->part, B, s->g + L.cw, s->g + L.cb);
+    // per-sample conv-head partials (B x 19: 18 tap weights, then the bias) ->
+    // their gradients, which follow each other in the parameter vector
+    static_assert(2 * kTaps + 1 == 19, "conv head: 18 taps and one bias");
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = colsum(st, (const float *)s->part, B, 19, s->colpart, s->g + L.cw);
     if (e != hipSuccess) return e;
     struct Lay {
         const bf16_t *hin;  // layer input activation (B x kin)
@@ -631,8 +731,8 @@ hipError_t backward(qw_surr *s, int B) {
     for (int li = 3; li >= 0; --li) {
         const Lay &ly = lays[li];
         // s->dz holds dZ of this layer (fp32, B x kout)
-        hipLaunchKernelGGL(k_colsum, dim3((ly.kout + 255) / 256), dim3(256), 0, st, (const float *)s->dz, B, ly.kout,
-                           s->g + ly.b);
+        e = colsum(st, (const float *)s->dz, B, ly.kout, s->colpart, s->g + ly.b);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, s->dzb, (int64_t)B * ly.kout);
         e = hipGetLastError();
         if (e == hipSuccess) e = transpose(st, s->dzb, B, ly.kout, ly.kout, s->dzT, B);
@@ -686,6 +786,7 @@ int alloc_surr(qw_surr *s) {
         {(void **)&s->dz, sizeof(float) * B * 1024}, {(void **)&s->dzb, sizeof(bf16_t) * B * 1024},
         {(void **)&s->dzT, sizeof(bf16_t) * B * 1024}, {(void **)&s->hT, sizeof(bf16_t) * B * 1024},
         {(void **)&s->idx, sizeof(int32_t) * B}, {(void **)&s->tb, sizeof(int32_t) * B},
+        {(void **)&s->colpart, sizeof(float) * kColChunks * 1024},
     };
     for (auto &a : list) {
         hipError_t e = hipMalloc(a.p, a.bytes);
@@ -820,16 +921,25 @@ int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, co
 
 int surr_forward(qw_surr_t s, int64_t n, const float *X, const int32_t *T, float *out) {
     if (!s || !X || !T || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
-    for (int64_t r0 = 0; r0 < n; r0 += s->bmax) {
-        const int b = (int)std::min<int64_t>(s->bmax, n - r0);
-        const int bp = (b + 127) / 128 * 128;
-        int rc = upload_rows(s, X + r0 * kF, T + r0, b, bp);
-        if (rc) return rc;
-        QS_HIP(forward(s, bp, bp, nullptr), "surrogate forward");
-        QS_HIP(hipMemcpyAsync(out + r0 * kBins, s->q, sizeof(float) * b * kBins, hipMemcpyDeviceToHost, s->stream),
-               "copy of the bins");
-        QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
+    NetBufs nb;
+    float *dX = nullptr;
+    int32_t *dT = nullptr;
+    hipError_t e = nb.alloc(n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dX, sizeof(float) * n * kF);
+    if (e == hipSuccess) e = hipMalloc((void **)&dT, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dX, X, sizeof(float) * n * kF, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dT, T, sizeof(int32_t) * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_rows_to_inputs, dim3((unsigned)std::min<int64_t>(4096, (nb.npad + 255) / 256)), dim3(256),
+                           0, s->stream, n, nb.npad, (const float *)dX, (const int32_t *)dT, nb.xb, nb.t32);
+        e = hipGetLastError();
     }
+    if (e == hipSuccess) e = forward_rows(s, nb.npad, nb.xb, nb.t32, nb.out);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, nb.out, sizeof(float) * n * kBins, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(dX);
+    (void)hipFree(dT);
+    if (e != hipSuccess) return sfail(QW_EHIP, "surr_forward: %s", hipGetErrorString(e));
     return QW_OK;
 }
 
@@ -890,10 +1000,7 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int
             if (e == hipSuccess) e = forward(s, B, B, s->yb);
             if (e == hipSuccess) e = backward(s, B);
             if (e == hipSuccess) e = adam_step(s, lr, o->weight_decay);
-            if (e == hipSuccess) {
-                hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1), 0, s->stream, (const float *)s->lrow, B, 1, eloss + k);
-                e = hipGetLastError();
-            }
+            if (e == hipSuccess) e = colsum(s->stream, (const float *)s->lrow, B, 1, s->colpart, eloss + k);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), eloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -963,28 +1070,54 @@ int surr_set_range(qw_surr_t s, int64_t N, int32_t tmin, int32_t tmax) {
 int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, const double *angles, const double *psi0,
                  const qw_predict_opts *po, float *out, uint8_t *used_fallback, qw_predict_stats *stats) {
     if (!s || !N || !T || !angles || !psi0 || !out || n < 1) return sfail(QW_EINVAL, "bad arguments");
-    qw_predict_opts o = {0.01, 1e-3, 1024, 1, 0};
+    qw_predict_opts o = {0.01, 1e-3, 1024, 1, 0, 0};
     if (po) o = *po;
     if (o.chunk < 1 || !(o.recheck_frac >= 0.0) || !(o.tvd_tol > 0.0)) return sfail(QW_EINVAL, "bad predict options");
+    if (o.out_on_device != 0 && o.out_on_device != 1) return sfail(QW_EINVAL, "out_on_device must be 0 or 1");
+    if (n > (1LL << 31) - 1) return sfail(QW_ERANGE, "too many walks");
     qw_predict_stats ps;
     memset(&ps, 0, sizeof ps);
-    hipEvent_t e0, e1;
-    QS_HIP(hipEventCreate(&e0), "hipEventCreate");
-    QS_HIP(hipEventCreate(&e1), "hipEventCreate");
-    // 1. network on every walk
-    std::vector<float> X((size_t)n * kF);
-    int rc = surr_features(s, n, N, T, angles, psi0, X.data());
-    if (rc) return rc;
-    std::vector<int32_t> T32(n);
-    for (int64_t i = 0; i < n; ++i) T32[i] = (int32_t)std::min<int64_t>(T[i], kMaxSites - 1);
-    QS_HIP(hipEventRecord(e0, s->stream), "event");
-    rc = surr_forward(s, n, X.data(), T32.data(), out);
-    if (rc) return rc;
-    QS_HIP(hipEventRecord(e1, s->stream), "event");
-    QS_HIP(hipEventSynchronize(e1), "event");
+    struct Ev {
+        hipEvent_t e = nullptr;
+        ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } ev0, ev1;
+    QS_HIP(hipEventCreate(&ev0.e), "hipEventCreate");
+    QS_HIP(hipEventCreate(&ev1.e), "hipEventCreate");
+    hipEvent_t e0 = ev0.e, e1 = ev1.e;
+    // device scratch released on every return path
+    struct DevBuf {
+        void *p = nullptr;
+        ~DevBuf() { (void)hipFree(p); }
+    } dN, dT, dA, dP, dIdx, dPlain, dNet, dTv;
+    // 1. network on every walk: parameters up, features and forward on the
+    //    device; the bins stay in HBM (nb.out) until the final copy
+    NetBufs nb;
+    {
+        hipError_t e = nb.alloc(n);
+        if (e == hipSuccess) e = hipMalloc(&dN.p, 8 * n);
+        if (e == hipSuccess) e = hipMalloc(&dT.p, 8 * n);
+        if (e == hipSuccess) e = hipMalloc(&dA.p, 24 * n);
+        if (e == hipSuccess) e = hipMalloc(&dP.p, 32 * n);
+        if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dN.p, N, 8 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dT.p, T, 8 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dA.p, angles, 24 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dP.p, psi0, 32 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_net_inputs, dim3((unsigned)std::min<int64_t>(4096, (nb.npad + 255) / 256)), dim3(256),
+                               0, s->stream, n, nb.npad, (const int64_t *)dN.p, (const int64_t *)dT.p,
+                               (const double *)dA.p, (const double *)dP.p, nb.xb, nb.t32);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = forward_rows(s, nb.npad, nb.xb, nb.t32, nb.out);
+        if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e != hipSuccess) return sfail(QW_EHIP, "surrogate network pass: %s", hipGetErrorString(e));
+    }
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     ps.ms_network = ms;
+    int rc = QW_OK;
     // 2. range check and the seeded re-check sample of every chunk
     std::vector<uint8_t> fb(n, 0);
     std::vector<int64_t> sample;
@@ -1009,25 +1142,34 @@ int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, con
             sample.push_back(inr[j]);
         }
     }
-    auto plain_bins = [&](const std::vector<int64_t> &ids, std::vector<float> &bins, double &msp) -> int {
-        std::vector<int64_t> n1(ids.size()), t1(ids.size());
-        std::vector<double> a1(3 * ids.size()), p1(4 * ids.size());
-        for (size_t j = 0; j < ids.size(); ++j) {
+    // the plain walk (batched, complex64) of the walks ids into dPlain (device,
+    // ids.size() x 512), and ids into dIdx
+    auto plain_bins = [&](const std::vector<int64_t> &ids, double &msp) -> int {
+        const size_t m = ids.size();
+        std::vector<int64_t> n1(m), t1(m);
+        std::vector<double> a1(3 * m), p1(4 * m);
+        for (size_t j = 0; j < m; ++j) {
             n1[j] = N[ids[j]];
             t1[j] = T[ids[j]];
             for (int q = 0; q < 3; ++q) a1[3 * j + q] = angles[3 * ids[j] + q];
             for (int q = 0; q < 4; ++q) p1[4 * j + q] = psi0[4 * ids[j] + q];
         }
+        (void)hipFree(dPlain.p);
+        (void)hipFree(dIdx.p);
+        dPlain.p = dIdx.p = nullptr;
+        hipError_t e = hipMalloc(&dPlain.p, sizeof(float) * m * kBins);
+        if (e == hipSuccess) e = hipMalloc(&dIdx.p, sizeof(int64_t) * m);
+        if (e == hipSuccess) e = hipMemcpyAsync(dIdx.p, ids.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return sfail(QW_EHIP, "plain walk buffers: %s", hipGetErrorString(e));
         qw_batch_opts bo;
         memset(&bo, 0, sizeof bo);
         bo.nbins = kBins;
         qw_batch_t bt = nullptr;
-        int r = walk_batch_create((int64_t)ids.size(), n1.data(), t1.data(), a1.data(), p1.data(), nullptr, QW_C64, &bo,
+        int r = walk_batch_create((int64_t)m, n1.data(), t1.data(), a1.data(), p1.data(), nullptr, QW_C64, &bo,
                                   s->stream, &bt);
         if (r) return sfail(r, "plain walk batch: %s", walk_batch_last_error());
         r = walk_batch_run(bt);
-        bins.resize(ids.size() * kBins);
-        if (!r) r = walk_batch_binned(bt, bins.data(), 0);
+        if (!r) r = walk_batch_binned(bt, (float *)dPlain.p, 1);
         qw_batch_info bi;
         if (!r) r = walk_batch_info(bt, &bi);
         if (!r) msp += bi.last_run_ms;
@@ -1035,22 +1177,34 @@ int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, con
         if (r) return sfail(r, "plain walk batch: %s", walk_batch_last_error());
         return QW_OK;
     };
-    // 3. re-check: a chunk fails when any sampled walk is farther than tvd_tol from the plain walk
+    // 3. re-check: a chunk fails when any sampled walk is farther than tvd_tol
+    //    from the plain walk (TVD in fp64 on the device); re-checked walks keep
+    //    the plain result
     std::vector<uint8_t> chunk_bad(nch, 0);
     if (!sample.empty()) {
-        std::vector<float> pb;
-        rc = plain_bins(sample, pb, ps.ms_recheck);
+        const size_t m = sample.size();
+        rc = plain_bins(sample, ps.ms_recheck);
         if (rc) return rc;
-        for (size_t j = 0; j < sample.size(); ++j) {
-            double tv = 0.0;
-            for (int q = 0; q < kBins; ++q) tv += fabs((double)out[sample[j] * kBins + q] - (double)pb[j * kBins + q]);
-            tv *= 0.5;
-            ps.max_tvd_sampled = std::max(ps.max_tvd_sampled, tv);
-            if (tv > o.tvd_tol) chunk_bad[sample[j] / o.chunk] = 1;
-            // the re-checked walks keep the plain result
-            memcpy(out + sample[j] * kBins, pb.data() + j * kBins, sizeof(float) * kBins);
+        std::vector<double> tv(m);
+        hipError_t e = hipMalloc(&dNet.p, sizeof(float) * m * kBins);
+        if (e == hipSuccess) e = hipMalloc(&dTv.p, sizeof(double) * m);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)m), dim3(256), 0, s->stream, (const float *)nb.out,
+                               (const int64_t *)dIdx.p, kBins, (float *)dNet.p);
+            hipLaunchKernelGGL(k_tvd, dim3((unsigned)m), dim3(256), 0, s->stream, (const float *)dNet.p,
+                               (const float *)dPlain.p, kBins, (double *)dTv.p);
+            hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)m), dim3(256), 0, s->stream, (const float *)dPlain.p,
+                               (const int64_t *)dIdx.p, kBins, nb.out);
+            e = hipGetLastError();
         }
-        ps.rechecked = (int64_t)sample.size();
+        if (e == hipSuccess) e = hipMemcpyAsync(tv.data(), dTv.p, sizeof(double) * m, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return sfail(QW_EHIP, "re-check: %s", hipGetErrorString(e));
+        for (size_t j = 0; j < m; ++j) {
+            ps.max_tvd_sampled = std::max(ps.max_tvd_sampled, tv[j]);
+            if (tv[j] > o.tvd_tol) chunk_bad[sample[j] / o.chunk] = 1;
+        }
+        ps.rechecked = (int64_t)m;
     }
     // 4. fallback: failing chunks and out-of-range walks run the plain walk
     std::vector<int64_t> fall;
@@ -1060,17 +1214,21 @@ int surr_predict(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, con
     }
     for (int64_t c = 0; c < nch; ++c) ps.failed_chunks += chunk_bad[c];
     if (!fall.empty()) {
-        std::vector<float> pb;
-        rc = plain_bins(fall, pb, ps.ms_fallback);
+        rc = plain_bins(fall, ps.ms_fallback);
         if (rc) return rc;
-        for (size_t j = 0; j < fall.size(); ++j) memcpy(out + fall[j] * kBins, pb.data() + j * kBins, sizeof(float) * kBins);
+        hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)fall.size()), dim3(256), 0, s->stream,
+                           (const float *)dPlain.p, (const int64_t *)dIdx.p, kBins, nb.out);
+        QS_HIP(hipGetLastError(), "fallback scatter");
     }
     ps.fallback = (int64_t)fall.size();
+    // 5. the answers: one copy out of HBM
+    QS_HIP(hipMemcpyAsync(out, nb.out, sizeof(float) * n * kBins,
+                          o.out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream),
+           "copy of the bins");
+    QS_HIP(hipStreamSynchronize(s->stream), "stream synchronise");
     if (used_fallback)
         for (int64_t i = 0; i < n; ++i) used_fallback[i] = fb[i];
     if (stats) *stats = ps;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     return QW_OK;
 }
 

@@ -29,7 +29,7 @@ ABI_SYMBOLS = (
     "walk_create", "walk_create_ext", "walk_state_bytes", "walk_step", "walk_step_inverse",
     "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
     "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
-    "walk_reset", "walk_profile",
+    "walk_reset", "walk_profile", "walk_set_broken_links", "walk_set_reflecting_walls",
     "walk_batch_create", "walk_batch_run", "walk_batch_moments", "walk_batch_binned",
     "walk_batch_probabilities", "walk_batch_info", "walk_batch_tune", "walk_batch_destroy",
     "walk_batch_last_error",
@@ -59,7 +59,8 @@ class Coin(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("block_depth", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("prefetch_rows", ctypes.c_int32),
+                ("stream_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -70,7 +71,7 @@ class KernelProfile(ctypes.Structure):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int32), ("keep_probabilities", ctypes.c_int32),
                 ("tiled_variant", ctypes.c_int32), ("no_graph", ctypes.c_int32),
-                ("renorm_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("renorm_every", ctypes.c_int32), ("whole_max_sites", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -89,7 +90,7 @@ class TrainOpts(ctypes.Structure):
 
 class PredictOpts(ctypes.Structure):
     _fields_ = [("recheck_frac", ctypes.c_double), ("tvd_tol", ctypes.c_double), ("chunk", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int64)]
+                ("seed", ctypes.c_uint64), ("out_on_device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PredictStats(ctypes.Structure):
@@ -133,6 +134,8 @@ def load():
         "walk_destroy": [P],
         "walk_reset": [P, P, P],
         "walk_profile": [P, P, I32],
+        "walk_set_broken_links": [P, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64],
+        "walk_set_reflecting_walls": [P, I32],
         "walk_batch_create": [I64, P, P, P, P, P, I32, P, P, P],
         "walk_batch_run": [P],
         "walk_batch_moments": [P, P, I32],
@@ -288,6 +291,16 @@ class Walk:
         x0a = (ctypes.c_int64 * 2)(int(x0[0]), int(x0[1]) if len(x0) > 1 else 0)
         _check(self._lib.walk_reset(self.h, p0.ctypes.data, x0a))
 
+    def set_broken_links(self, p: float, seed: int = 0, realization: int = 0):
+        """Random broken links (probability p per link and step; p = 0: intact).
+        Only at t = 0; walk_reset keeps the setting."""
+        _check(self._lib.walk_set_broken_links(self.h, float(p), int(seed), int(realization)))
+
+    def set_reflecting_walls(self, on: bool = True):
+        """Finite segment / box: the links across the lattice edge always broken.
+        Only at t = 0; walk_reset keeps the setting."""
+        _check(self._lib.walk_set_reflecting_walls(self.h, int(bool(on))))
+
     def profile(self, reset: bool = False) -> dict:
         """Per-kernel totals of the launches timed while the profile option was on."""
         arr = (KernelProfile * len(KERNEL_NAMES))()
@@ -300,8 +313,13 @@ class Walk:
 
     def set_options(self, block_depth: int | None = None, window: int | None = None,
                     renorm_every: int | None = None, renorm_tol: float | None = None,
-                    profile: int | None = None):
+                    profile: int | None = None, prefetch_rows: int | None = None,
+                    stream_waves: int | None = None):
         o = self.get_options()
+        if stream_waves is not None:
+            o.stream_waves = int(stream_waves)
+        if prefetch_rows is not None:
+            o.prefetch_rows = int(prefetch_rows)
         if profile is not None:
             o.profile = int(profile)
         if block_depth is not None:
@@ -366,7 +384,7 @@ class Batch:
 
     def __init__(self, N, T, angles, psi0, x0=None, prec: int = QW_C64, nbins: int = 0,
                  keep_probabilities: bool = False, tiled_variant: int = 0, no_graph: bool = False,
-                 renorm_every: int = 0, stream=None):
+                 renorm_every: int = 0, stream=None, whole_max_sites: int = 0):
         lib = load()
         self._lib = lib
         self.N = np.ascontiguousarray(np.asarray(N, dtype=np.int64))
@@ -377,7 +395,7 @@ class Batch:
         xa = None if x0 is None else np.ascontiguousarray(np.asarray(x0, dtype=np.int64))
         self.n, self.nbins, self.keep = n, nbins, keep_probabilities
         o = BatchOpts(nbins, int(bool(keep_probabilities)), int(tiled_variant), int(bool(no_graph)),
-                      int(renorm_every), 0)
+                      int(renorm_every), int(whole_max_sites))
         h = ctypes.c_void_p()
         _bcheck(lib.walk_batch_create(n, self.N.ctypes.data, self.T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
                                       None if xa is None else xa.ctypes.data, prec, ctypes.byref(o),
@@ -524,14 +542,24 @@ class Surrogate:
         _scheck(self._lib.surr_set_range(self.h, int(N), int(tmin), int(tmax)))
 
     def predict(self, N, T, angles, psi0, recheck_frac: float = 0.01, tvd_tol: float = 1e-3, chunk: int = 1024,
-                seed: int = 1):
+                seed: int = 1, out=None):
+        """Binned P of the walks; out: None (a new host array) or a contiguous
+        float32 CUDA tensor of n x 512 that receives the bins on the device."""
         n, N, T, ang, p0 = _walk_arrays(N, T, angles, psi0)
-        out = np.empty((n, self.NBINS), dtype=np.float32)
+        on_dev = out is not None
+        if on_dev:
+            if (not out.is_cuda or str(out.dtype) != "torch.float32" or not out.is_contiguous()
+                    or tuple(out.shape) != (n, self.NBINS)):
+                raise ValueError("out must be a contiguous float32 CUDA tensor of shape (n, 512)")
+            ptr = out.data_ptr()
+        else:
+            out = np.empty((n, self.NBINS), dtype=np.float32)
+            ptr = out.ctypes.data
         fb = np.zeros(n, dtype=np.uint8)
         st = PredictStats()
-        o = PredictOpts(recheck_frac, tvd_tol, chunk, seed, 0)
+        o = PredictOpts(recheck_frac, tvd_tol, chunk, seed, 1 if on_dev else 0, 0)
         _scheck(self._lib.surr_predict(self.h, n, N.ctypes.data, T.ctypes.data, ang.ctypes.data, p0.ctypes.data,
-                                       ctypes.byref(o), out.ctypes.data, fb.ctypes.data, ctypes.byref(st)))
+                                       ctypes.byref(o), ptr, fb.ctypes.data, ctypes.byref(st)))
         return out, fb.astype(bool), st
 
     def save(self, path: str):

@@ -126,6 +126,8 @@ def test_unnormalised_start(lib):
 def test_null_handles(lib):
     assert lib.walk_step(None, 1) == qwalk.QW_EINVAL
     assert lib.walk_norm(None, None) == qwalk.QW_EINVAL
+    assert lib.walk_set_broken_links(None, 0.5, 1, 0) == qwalk.QW_EINVAL
+    assert lib.walk_set_reflecting_walls(None, 1) == qwalk.QW_EINVAL
     assert lib.walk_destroy(None) == qwalk.QW_OK
     assert lib.walk_create(None, None, None, None, 0, None, None) == qwalk.QW_EINVAL
 

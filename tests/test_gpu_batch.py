@@ -67,6 +67,29 @@ def test_batch_mixed_sizes(prec, tol, variant):
     b.destroy()
 
 
+@pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
+@pytest.mark.parametrize("variant", [1, 4])
+def test_batch_short_rings_tiled(prec, tol, variant):
+    """whole_max_sites = 1: every ring of 2048 sites or more runs tiled over its
+    light cone (rings 2048..4608 are otherwise held whole), shorter ones whole."""
+    rng = np.random.default_rng(70 + variant)
+    N, T, ang, psi0, x0 = _mixed(31 + variant)
+    extra = np.array([2048, 2049, 2500, 3000, 4097, 4097, 4097, 4608], dtype=np.int64)
+    Te = np.array([0, 1500, 1023, 1499, 256, 2048, 1200, 2303], dtype=np.int64)  # N = 2049: 2T > N wraps
+    N = np.concatenate([N, extra])
+    T = np.concatenate([T, Te])
+    ang = np.concatenate([ang, inputs.su2_angles(rng, extra.size)])
+    psi0 = np.concatenate([psi0, np.stack([inputs.haar_state(rng, 2) for _ in range(extra.size)])])
+    x0 = np.concatenate([x0, np.array([int(rng.integers(0, k)) for k in extra], dtype=np.int64)])
+    b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True, tiled_variant=variant,
+                    whole_max_sites=1)
+    b.run()
+    _check_walks(b, N, T, ang, psi0, x0, tol, 64)
+    info = b.info()
+    assert info.whole_ring_walks == int(np.sum(N < 2048))
+    b.destroy()
+
+
 def test_batch_variants_and_graph_replay_bitwise():
     N, T, ang, psi0, x0 = _mixed(5, n_extra=20)
     ref = None

@@ -206,6 +206,31 @@ def test_torus_blocked_equals_unblocked_bitwise():
             assert np.array_equal(r, res[0])
 
 
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+@pytest.mark.parametrize("table", ["PAIR", "EQ8", "DIAG"])
+def test_torus_prefetch_depth_is_bitwise_neutral(prec, table):
+    """The torus kernel's read-ahead (1 or 3 rows) and its segment length
+    (waves per launch) change only when loads are issued and how rows are
+    split: every block depth gives the same amplitudes bit for bit."""
+    disp = getattr(inputs, table)
+    rng = np.random.default_rng(len(table) * 10 + prec)
+    U = inputs.haar_unitary(rng, 4)
+    psi0 = inputs.haar_state(rng, 4)
+    ext, x0, T = (211, 90), (100, 7), 97          # ragged strips and segments, wraps in y
+    depths = (4, 8) if prec == qwalk.QW_C128 else (4, 8, 16)
+    for depth in depths:
+        res = []
+        for pd, waves in ((1, 0), (3, 0), (3, 37), (1, 5000)):
+            _, psi, _, _ = _run_gpu(ext, disp, qwalk.DENSE, psi0, x0, T, prec, dense=U, block_depth=depth,
+                                    prefetch_rows=pd, stream_waves=waves, renorm_every=0)
+            res.append(psi)
+        for r in res[1:]:
+            assert np.array_equal(res[0], r), depth
+        if prec == qwalk.QW_C128:
+            Pr, psir = _oracle_run(ext, disp, U, psi0, x0, T)
+            assert np.max(np.abs(_as_oracle_layout(res[1]) - psir)) <= TOL64
+
+
 def test_torus_wraps_around():
     """Cone larger than the torus: the walk wraps through the periodic boundary."""
     rng = np.random.default_rng(8)

@@ -128,3 +128,21 @@ def test_predict_fallback_semantics():
     assert rechecked.sum() >= st2.rechecked - 1     # re-checked walks carry the plain result
     assert np.array_equal(out2[keep & ~rechecked], net[keep & ~rechecked])
     s.destroy()
+
+
+def test_predict_device_output_matches_host_output():
+    """The bins written to device memory equal the host-output call bit for
+    bit, including the re-checked and fallback rows."""
+    torch = pytest.importorskip("torch")
+    n = 1500                                           # ragged last chunk and padded network rows
+    N, T, ang, psi0 = _walk_params(6, n)
+    N[:3] = 2001                                       # out of range: plain walk
+    s = qwalk.Surrogate(seed=13)
+    for tol in (1e-3, 2.0):                            # every chunk falls back / none does
+        host, fb_h, st_h = s.predict(N, T, ang, psi0, chunk=512, tvd_tol=tol)
+        dev = torch.empty((n, 512), dtype=torch.float32, device="cuda")
+        out, fb_d, st_d = s.predict(N, T, ang, psi0, chunk=512, tvd_tol=tol, out=dev)
+        assert out is dev
+        assert np.array_equal(dev.cpu().numpy(), host)
+        assert np.array_equal(fb_h, fb_d) and st_h.failed_chunks == st_d.failed_chunks
+    s.destroy()
