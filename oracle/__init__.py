@@ -20,6 +20,10 @@ Functions and the passages they follow (see ``qw_oracle.c`` for the details):
   rbl_threshold(p)          floor(p * 2^32): a link is broken when Philox's word 0 is below it
   evolve_rbl(psi, ...)      T steps with random broken links, Sec. 3 Eqs. (9)-(10), and
                             the finite segment / box with reflecting walls (Fig. 3)
+  graph_reverse(off, tgt)   the other end of every arc's edge (general graphs)
+  graph_evolve(off, tgt, kind, psi, T)  T steps of U = S (I (x) C) on a general graph,
+                            Sec. 2.1 Eqs. (1)-(3) (one amplitude per arc)
+  graph_prob(off, psi)      P(v) = sum over v's arcs of |psi|^2
 """
 from __future__ import annotations
 
@@ -72,6 +76,12 @@ def _open(path: str):
     u64 = ctypes.c_uint64
     lib.orc_evolve_rbl.argtypes = [i64, i64, i32, ip, dp, dp, i64, i64, u64, u64, u64, i32]
     lib.orc_evolve_rbl.restype = i32
+    lib.orc_graph_reverse.argtypes = [i64, dp, dp, dp]
+    lib.orc_graph_reverse.restype = i32
+    lib.orc_graph_evolve.argtypes = [i64, dp, dp, i32, i32, dp, dp, i64]
+    lib.orc_graph_evolve.restype = i32
+    lib.orc_graph_prob.argtypes = [i64, dp, dp, dp]
+    lib.orc_graph_prob.restype = None
     return lib
 
 
@@ -215,3 +225,50 @@ def evolve_rbl(psi: np.ndarray, disp, C: np.ndarray, T: int, p: float, seed: int
     if rc != 0:
         raise ValueError("orc_evolve_rbl: bad arguments (every component needs an opposite)")
     return out
+
+
+def _graph_arrays(off, tgt):
+    o = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    t = np.ascontiguousarray(np.asarray(tgt, dtype=np.int64))
+    if o.ndim != 1 or o.size < 2 or o[0] != 0 or o[-1] != t.size:
+        raise ValueError("offsets must start at 0 and end at the number of arcs")
+    return o, t
+
+
+def graph_reverse(off, tgt) -> np.ndarray:
+    """rev[k]: the arc at the other end of arc k's edge (a self-loop is its own)."""
+    lib = _load()
+    o, t = _graph_arrays(off, tgt)
+    rev = np.zeros(t.size, dtype=np.int64)
+    if lib.orc_graph_reverse(o.size - 1, _ptr(o), _ptr(t), _ptr(rev)) != 0:
+        raise ValueError("arcs do not pair into undirected edges")
+    return rev
+
+
+def graph_evolve(off, tgt, kind: int, psi, T: int, dense=None) -> np.ndarray:
+    """T steps of the coined walk on a general graph (one amplitude per arc).
+    kind: GROVER, FOURIER or DENSE (dense: list of d x d matrices for d = 1 .. dmax)."""
+    lib = _load()
+    o, t = _graph_arrays(off, tgt)
+    out = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128)).copy()
+    if out.size != t.size:
+        raise ValueError("one amplitude per arc")
+    table, dmax = None, 0
+    if dense is not None:
+        dmax = len(dense)
+        table = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.complex128).reshape(-1)
+                                                     for m in dense]))
+    rc = lib.orc_graph_evolve(o.size - 1, _ptr(o), _ptr(t), int(kind), int(dmax),
+                              _ptr(table) if table is not None else None, _ptr(out), int(T))
+    if rc != 0:
+        raise ValueError("orc_graph_evolve: bad graph or coin")
+    return out
+
+
+def graph_prob(off, psi) -> np.ndarray:
+    lib = _load()
+    o = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    p = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    P = np.empty(o.size - 1, dtype=np.float64)
+    lib.orc_graph_prob(o.size - 1, _ptr(o), _ptr(p), _ptr(P))
+    return P

@@ -444,3 +444,132 @@ int orc_evolve_rbl(int64_t Lx, int64_t Ly, int d, const int *disp, const double 
     free(phi);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Coined walks on general graphs (Sec. 2.1, Eqs. (1)-(3)).
+ *
+ * The graph is given by arcs in compressed rows: vertex v owns the arcs
+ * off[v] .. off[v+1]-1, arc k leading to tgt[k].  An undirected edge {v, w}
+ * with v != w appears once in each endpoint's row; the k-th arc v -> w (in row
+ * order) and the k-th arc w -> v are the two ends of one edge.  A self-loop
+ * v -> v is an edge with both ends at v and a single coin state.  The coin
+ * space of v (Eq. (1)) is spanned by the arcs of its row, in row order; the
+ * state psi holds one complex amplitude per arc.
+ *
+ * One step U = S (I (x) C) (Eq. (2)): the degree-d coin C_d acts on the
+ * amplitudes of each vertex's row, then S|v, e> = |v', e> for l(e) = {v, v'}
+ * (Eq. (3)) moves the amplitude of arc k to the other end of its edge, rev[k]:
+ *   psi'(rev[k]) = (C_{d(v)} psi_v)(k).
+ * Coins by degree d: Grover 2/d - delta (kind GROVER), the d-point Fourier
+ * matrix exp(2 pi i a b / d) / sqrt(d) (kind FOURIER), or a caller table of
+ * d x d matrices for d = 1 .. dmax (kind DENSE, concatenated by degree).
+ * ------------------------------------------------------------------------ */
+
+/* rev[k] = the other end of arc k's edge; -1 on an unmatched arc or a bad target */
+int orc_graph_reverse(int64_t nv, const int64_t *off, const int64_t *tgt, int64_t *rev) {
+    int64_t v, k;
+    for (v = 0; v < nv; v++) {
+        for (k = off[v]; k < off[v + 1]; k++) {
+            int64_t w = tgt[k], occ = 0, j, found = -1, seen = 0;
+            if (w < 0 || w >= nv) return -1;
+            if (w == v) { rev[k] = k; continue; }
+            for (j = off[v]; j < k; j++)
+                if (tgt[j] == w) occ++;
+            for (j = off[w]; j < off[w + 1]; j++)
+                if (tgt[j] == v) {
+                    if (seen == occ) { found = j; break; }
+                    seen++;
+                }
+            if (found < 0) return -1;
+            rev[k] = found;
+        }
+    }
+    return 0;
+}
+
+/* the degree-d coin of the given kind into out (d x d complex, row-major) */
+static int graph_coin(int kind, int d, int dmax, const double *dense, cx *out) {
+    int a, b;
+    if (kind == 2) {          /* GROVER */
+        for (a = 0; a < d; a++)
+            for (b = 0; b < d; b++) out[a * d + b] = c_make(2.0 / d - (a == b ? 1.0 : 0.0), 0.0);
+        return 0;
+    }
+    if (kind == 4) {          /* FOURIER */
+        const double pi = 3.14159265358979323846, s = 1.0 / sqrt((double)d);
+        for (a = 0; a < d; a++)
+            for (b = 0; b < d; b++) {
+                const double t = 2.0 * pi * (double)((a * b) % d) / (double)d;
+                out[a * d + b] = c_make(s * cos(t), s * sin(t));
+            }
+        return 0;
+    }
+    if (kind == 5) {          /* DENSE: matrices for d = 1 .. dmax, concatenated */
+        int64_t o = 0;
+        int e;
+        if (d > dmax || !dense) return -1;
+        for (e = 1; e < d; e++) o += (int64_t)e * e;
+        memcpy(out, dense + 2 * o, sizeof(cx) * d * d);
+        return 0;
+    }
+    return -1;
+}
+
+/* T steps on psi (narcs complex, in place); 0, or -1 on bad input */
+int orc_graph_evolve(int64_t nv, const int64_t *off, const int64_t *tgt, int kind, int dmax, const double *dense,
+                     double *psi_io, int64_t T) {
+    int64_t narcs, v, k, s, maxd = 0;
+    int64_t *rev;
+    cx *a = (cx *)psi_io, *b, *C;
+    if (nv < 1 || T < 0) return -1;
+    narcs = off[nv];
+    for (v = 0; v < nv; v++) {
+        if (off[v + 1] < off[v]) return -1;
+        if (off[v + 1] - off[v] > maxd) maxd = off[v + 1] - off[v];
+    }
+    rev = (int64_t *)malloc(sizeof(int64_t) * (narcs > 0 ? narcs : 1));
+    b = (cx *)calloc(narcs > 0 ? narcs : 1, sizeof(cx));
+    C = (cx *)malloc(sizeof(cx) * (maxd > 0 ? maxd * maxd : 1));
+    if (!rev || !b || !C || orc_graph_reverse(nv, off, tgt, rev) != 0) {
+        free(rev); free(b); free(C);
+        return -1;
+    }
+    for (s = 0; s < T; s++) {
+        cx *tmp;
+        for (v = 0; v < nv; v++) {
+            const int64_t k0 = off[v];
+            const int d = (int)(off[v + 1] - k0);
+            int i, j;
+            if (d == 0) continue;
+            if (graph_coin(kind, d, dmax, dense, C) != 0) {
+                free(rev); free(b); free(C);
+                return -1;
+            }
+            for (i = 0; i < d; i++) {
+                cx acc = c_make(0.0, 0.0);
+                for (j = 0; j < d; j++) acc = c_add(acc, c_mul(C[i * d + j], a[k0 + j]));
+                b[rev[k0 + i]] = acc;   /* the shift: to the other end of the edge */
+            }
+        }
+        tmp = a; a = b; b = tmp;
+    }
+    if (a != (cx *)psi_io) {
+        memcpy(psi_io, a, (size_t)narcs * sizeof(cx));
+        free(a);
+    } else {
+        free(b);
+    }
+    free(rev); free(C);
+    (void)k;
+    return 0;
+}
+
+/* P(v) = sum over v's arcs of |psi|^2, in row order */
+void orc_graph_prob(int64_t nv, const int64_t *off, const double *psi, double *P) {
+    int64_t v, k;
+    for (v = 0; v < nv; v++) {
+        double s = 0.0;
+        for (k = off[v]; k < off[v + 1]; k++) s += psi[2 * k] * psi[2 * k] + psi[2 * k + 1] * psi[2 * k + 1];
+        P[v] = s;
+    }
+}

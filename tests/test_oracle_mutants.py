@@ -15,6 +15,7 @@ import oracle
 from paper_1003_3779_amd import inputs
 from tests import test_oracle_pins as P
 from tests import test_oracle_rbl as RB
+from tests import test_oracle_graph as GR
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "qw_oracle.c")
 
@@ -48,6 +49,15 @@ MUTANTS = {
                          "link_broken(link, (uint64_t)step0, realization, seed, thr)"),
     "wall_edge_test": ("int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);",
                        "int edge = walls && (rx < 0 || rx > Lx || ry < 0 || ry >= Ly);"),
+    "graph_no_shift": ("b[rev[k0 + i]] = acc;   /* the shift: to the other end of the edge */",
+                       "b[k0 + i] = acc;"),
+    "graph_grover_weight": ("out[a * d + b] = c_make(2.0 / d - (a == b ? 1.0 : 0.0), 0.0);",
+                            "out[a * d + b] = c_make(1.0 / d - (a == b ? 1.0 : 0.0), 0.0);"),
+    "graph_fourier_sign": ("out[a * d + b] = c_make(s * cos(t), s * sin(t));",
+                           "out[a * d + b] = c_make(s * cos(t), -s * sin(t));"),
+    "graph_pairing": ("if (seen == occ) { found = j; break; }", "if (seen == 0) { found = j; break; }"),
+    "graph_coin_transposed": ("for (j = 0; j < d; j++) acc = c_add(acc, c_mul(C[i * d + j], a[k0 + j]));",
+                              "for (j = 0; j < d; j++) acc = c_add(acc, c_mul(C[j * d + i], a[k0 + j]));"),
     "wall_reflects_wrong_side": ("int64_t rx = x - disp[2 * c], ry = y - disp[2 * c + 1];",
                                  "int64_t rx = x + disp[2 * c], ry = y + disp[2 * c + 1];"),
 }
@@ -80,6 +90,10 @@ BATTERY = [
     lambda: RB.test_walls_two_site_segment_by_hand(),
     lambda: RB.test_walls_segment_never_wraps(),
     lambda: RB.test_walls_reflect_exactly_at_the_edge("PAIR"),
+    lambda: GR.test_dense_matrix_power_random_graphs(oracle.DENSE, 1),
+    lambda: GR.test_dense_matrix_power_random_graphs(oracle.FOURIER, 2),
+    lambda: GR.test_grover_keeps_the_uniform_arc_state(),
+    lambda: GR.test_unitary_on_random_graphs_and_bad_input(),
 ]
 
 
