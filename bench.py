@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grover2d",
-                    choices=["grover2d", "grover2d_uniform", "hh2d", "ring1d", "ragged_rings", "surrogate"])
+                    choices=["grover2d", "grover2d_uniform", "hh2d", "fourier2d_diag", "fourier2d_natural",
+                             "fourier2d_diag_4096", "ring1d", "ragged_rings", "surrogate", "graph_torus",
+                             "graph_random"])
     ap.add_argument("--train-walks", type=int, default=1 << 18, help="surrogate: training walks")
     ap.add_argument("--eval-walks", type=int, default=65536, help="surrogate: held-out walks")
     ap.add_argument("--epochs", type=int, default=30, help="surrogate: training epochs")
@@ -344,6 +346,92 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
+def _graph_workload(name: str, seed: int = 7):
+    """Arcs in compressed rows: the 2048^2 torus as a graph (rows +x, -x, +y, -y),
+    or a random multigraph of 2^21 vertices and 2^23 edges (self-loops and
+    parallel edges allowed, average degree 8)."""
+    import numpy as np
+    if name == "graph_torus":
+        L = 2048
+        nv = L * L
+        v = np.arange(nv, dtype=np.int64)
+        x, y = v % L, v // L
+        tgt = np.stack([y * L + (x + 1) % L, y * L + (x - 1) % L, ((y + 1) % L) * L + x, ((y - 1) % L) * L + x],
+                       axis=1).ravel()
+        off = np.arange(0, 4 * nv + 1, 4, dtype=np.int64)
+        return nv, off, tgt
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nv, ne = 1 << 21, 1 << 23
+    a = rng.integers(0, nv, size=ne)
+    b = rng.integers(0, nv, size=ne)
+    loop = a == b
+    src = np.concatenate([a, b[~loop]])
+    dst = np.concatenate([b, a[~loop]])
+    order = np.argsort(src, kind="stable")
+    tgt = dst[order].astype(np.int64)
+    off = np.zeros(nv + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=nv), out=off[1:])
+    return nv, off, tgt
+
+
+def graph_bench(args):
+    """Grover walks on a large graph: arc updates per second (every arc's amplitude
+    per step), the step kernel against the HBM roofline, the oracle on a sample."""
+    import numpy as np
+
+    from paper_1003_3779_amd import qwalk
+    nv, off, tgt = _graph_workload(args.workload)
+    narcs = tgt.size
+    rng = np.random.Generator(np.random.PCG64(11))
+    v0 = nv // 2 + (int(np.sqrt(nv)) // 2 if args.workload == "graph_torus" else 0)
+    d0 = int(off[v0 + 1] - off[v0])
+    psi0 = np.zeros(narcs, dtype=np.complex128)
+    z = rng.normal(size=d0) + 1j * rng.normal(size=d0)
+    psi0[off[v0]:off[v0 + 1]] = z / np.linalg.norm(z)
+    T = 256
+    print(f"# graph: {args.workload} nv={nv} arcs={narcs} T={T}", file=sys.stderr, flush=True)
+    g = qwalk.GraphWalk(off, tgt, qwalk.GROVER, psi0, prec=qwalk.QW_C128)
+    g.step(8)                                  # warm-up
+    g.reset(psi0)
+    i0 = g.info()
+    t0 = time.perf_counter()
+    g.step(T)
+    n = g.norm()
+    t1 = time.perf_counter()
+    i1 = g.info()
+    step_ms = (i1.step_ms - i0.step_ms) / T
+    achieved = i1.bytes_per_step / (step_ms * 1e-3) / 1e9
+    # parity on a short sample against the oracle, then the oracle's own rate
+    Ts = 3
+    g.reset(psi0)
+    g.step(Ts)
+    Pg = g.probabilities()
+    g.destroy()
+    import oracle
+    tc0 = time.perf_counter()
+    ref = oracle.graph_evolve(off, tgt, oracle.GROVER, psi0, Ts)
+    tc1 = time.perf_counter()
+    dP = float(np.max(np.abs(Pg - oracle.graph_prob(off, ref))))
+    out = {
+        "metric": "arc (site·coin) updates/s & HBM GB/s", "value": narcs * T / (t1 - t0),
+        "unit": "arc updates/s", "n_gpus": 1, "steps": T, "warmup": 8,
+        "ms_per_step": round(1e3 * (t1 - t0) / T, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {nv} vertices, {narcs} arcs, Grover coins, T={T}, c128",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "graph_grover", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "avg_launch_ms": round(step_ms, 5),
+                     "alg_bytes_per_launch": round(i1.bytes_per_step)},
+        "norm_error": abs(n - 1.0),
+        "max_abs_dP_vs_oracle": {"T": Ts, "c128": dP},
+        "cpu_baseline": {"value": narcs * Ts / (tc1 - tc0), "unit": "arc updates/s", "cores": 1, "kind": "oracle",
+                         "sample": f"the oracle (plain C, fp64, 1 thread) on the same graph, {Ts} steps "
+                                   f"({tc1 - tc0:.1f} s)"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -368,6 +456,9 @@ def main():
         return
     if args.workload == "surrogate":
         surrogate(args)
+        return
+    if args.workload in ("graph_torus", "graph_random"):
+        graph_bench(args)
         return
     cfg = inputs.config(args.workload)
     prec_name = args.prec or cfg["prec"]
@@ -505,9 +596,10 @@ def main():
 
     if not args.no_cpu_baseline and cfg["dim"] == 2 and args.broken_links == 0.0:
         import oracle
-        Ts = args.cpu_sample_steps
+        Ts = min(args.cpu_sample_steps, T)
         Lx, Ly = ext
-        okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2}[cfg["coin"]]
+        okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2,
+                 qwalk.FOURIER: oracle.FOURIER}[cfg["coin"]]
         C = oracle.coin(okind, 4)
         psi_init = oracle.initial_state(Lx, Ly, 4, x0, psi0)
         tc0 = time.perf_counter()

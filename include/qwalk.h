@@ -408,6 +408,66 @@ int surr_load(const char *path, void *stream, qw_surr_t *out);
 int surr_destroy(qw_surr_t s);
 const char *surr_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Coined walks on general graphs (Sec. 2.1, Eqs. (1)-(3)).
+ *
+ * The graph: nv vertices, arcs in compressed rows -- vertex v owns arcs
+ * offsets[v] .. offsets[v+1]-1 (offsets: nv + 1 int64, offsets[0] = 0), arc k
+ * leads to targets[k].  Every undirected edge {v, w}, v != w, appears once in
+ * each endpoint's row; the k-th arc v -> w (in row order) and the k-th arc
+ * w -> v are the two ends of one edge (parallel edges pair in order).  A
+ * self-loop v -> v is one arc, its own other end.  Rows need not be sorted.
+ * The coin space of v (Eq. (1)) is spanned by v's arcs in row order; the state
+ * is one complex amplitude per arc, psi0 / get_state: 2 * narcs doubles
+ * (re, im) in arc order, on the host.
+ *
+ * One step U = S (I (x) C) (Eq. (2)): the coin of the vertex's degree d acts
+ * on its row, then S|v, e> = |v', e> for l(e) = {v, v'} (Eq. (3)) moves each
+ * arc's amplitude to the other end of its edge.  Coins by degree:
+ *   QW_COIN_GROVER   2/d - delta, any degree;
+ *   QW_COIN_FOURIER  exp(2 pi i a b / d) / sqrt(d), degrees <= 16;
+ *   QW_COIN_DENSE    dense: the caller's d x d matrices for d = 1 .. dense_max_degree,
+ *                    concatenated (row-major complex128 pairs), each unitary to
+ *                    1e-12; degrees <= 16.
+ * prec as for walk_create (QW_C64: complex64 amplitudes, fp64 reductions).
+ * Errors: QW_EINVAL (bad offsets, a target out of range, an arc without a
+ * reverse arc, a missing or non-unitary dense coin), QW_ERANGE (more than
+ * 2^31 - 1 arcs, a Fourier / dense degree above 16), QW_ENOTNORM (psi0 not
+ * normalised to 1e-12), QW_ENOMEM, QW_EHIP.  The handle owns its device
+ * buffers; stream NULL: a private stream.
+ * ------------------------------------------------------------------------ */
+typedef struct qw_graph *qw_graph_t;
+
+typedef struct {
+    int64_t nv, narcs;
+    int32_t max_degree;
+    int32_t reserved;
+    int64_t t;               /* steps taken */
+    int64_t launches;        /* step kernel launches */
+    double step_ms;          /* HIP-event time of all graph_walk_step calls */
+    double bytes_per_step;   /* HBM bytes of one step by construction: every arc's
+                                amplitude read and written, its reverse index read,
+                                the row offsets read */
+} qw_graph_info;
+
+int graph_walk_create(int64_t nv, const int64_t *offsets, const int64_t *targets, int32_t coin_kind,
+                      const double *dense, int32_t dense_max_degree, const double *psi0, int32_t prec,
+                      void *stream, qw_graph_t *out);
+/* Replace the state by psi0 (2 * narcs doubles, host, normalised) at t = 0. */
+int graph_walk_reset(qw_graph_t g, const double *psi0);
+/* T >= 0 steps; synchronises (the steps are timed with HIP events). */
+int graph_walk_step(qw_graph_t g, int64_t T);
+/* P(v) = sum of |psi|^2 over v's arcs (fp64, row order): nv doubles, device
+ * memory if out_on_device (asynchronous), else host (synchronises). */
+int graph_walk_probabilities(qw_graph_t g, double *out, int32_t out_on_device);
+/* sum_v P(v) (fp64, deterministic); synchronises. */
+int graph_walk_norm(qw_graph_t g, double *out);
+/* The state as complex128 (2 * narcs doubles), device or host. */
+int graph_walk_get_state(qw_graph_t g, double *out, int32_t out_on_device);
+int graph_walk_info(qw_graph_t g, qw_graph_info *out);
+int graph_walk_destroy(qw_graph_t g);
+const char *graph_walk_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

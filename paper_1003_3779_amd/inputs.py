@@ -36,6 +36,9 @@ PSI0_LR = np.array([1j * SQRT1_2, SQRT1_2], dtype=np.complex128)
 # 2D Grover start states in the PAIR ordering
 PSI0_GROVER_LOC = np.array([0.5, -0.5, -0.5, 0.5], dtype=np.complex128)
 PSI0_GROVER_UNI = np.array([0.5, 0.5, 0.5, 0.5], dtype=np.complex128)
+# the "Fourier initial state" of the Fourier-coin walks (Fig. 4): read as the
+# Fourier coin applied to |0>, i.e. the uniform coin state
+PSI0_FOURIER = np.array([0.5, 0.5, 0.5, 0.5], dtype=np.complex128)
 
 
 def haar_state(rng: np.random.Generator, d: int) -> np.ndarray:
@@ -84,6 +87,15 @@ def config(name: str) -> dict:
     if name == "grover2d_uniform":
         return dict(dim=2, extent=(4096, 4096), disp=PAIR, coin=GROVER, x0=(2048, 2048),
                     psi0=PSI0_GROVER_UNI, T=2048, prec="c128")
+    if name == "fourier2d_diag":     # the paper's 2D workload shape (Fig. 4, Tables 2-3): diagonal
+        return dict(dim=2, extent=(500, 500), disp=DIAG, coin=FOURIER, x0=(250, 250),   # lattice,
+                    psi0=PSI0_FOURIER, T=250, prec="c128")                              # Size 500
+    if name == "fourier2d_natural":  # the same walk on the natural lattice of Eq. (8)
+        return dict(dim=2, extent=(500, 500), disp=EQ8, coin=FOURIER, x0=(250, 250),
+                    psi0=PSI0_FOURIER, T=250, prec="c128")
+    if name == "fourier2d_diag_4096":  # the diagonal Fourier walk at the benchmark torus size
+        return dict(dim=2, extent=(4096, 4096), disp=DIAG, coin=FOURIER, x0=(2048, 2048),
+                    psi0=PSI0_FOURIER, T=2048, prec="c128")
     if name == "hh2d":          # 2D H(x)H torus 16384^2, T = 4096, complex64, Haar start (seed 3)
         rng = np.random.Generator(np.random.PCG64(3))
         return dict(dim=2, extent=(16384, 16384), disp=PAIR, coin=HADAMARD2, x0=(8192, 8192),

@@ -36,8 +36,16 @@ ABI_SYMBOLS = (
     "surr_num_params", "surr_create", "surr_get_params", "surr_set_params", "surr_features", "surr_forward",
     "surr_loss_grad", "surr_train", "surr_set_range", "surr_predict", "surr_save", "surr_load",
     "surr_destroy", "surr_last_error",
+    "graph_walk_create", "graph_walk_reset", "graph_walk_step", "graph_walk_probabilities", "graph_walk_norm",
+    "graph_walk_get_state", "graph_walk_info", "graph_walk_destroy", "graph_walk_last_error",
 )
 KERNEL_NAMES = ("step", "ring_whole", "ring_tiles", "stream2d")
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("narcs", ctypes.c_int64), ("max_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("step_ms", ctypes.c_double), ("bytes_per_step", ctypes.c_double)]
 
 
 class QWError(RuntimeError):
@@ -156,6 +164,14 @@ def load():
         "surr_save": [P, ctypes.c_char_p],
         "surr_load": [ctypes.c_char_p, P, P],
         "surr_destroy": [P],
+        "graph_walk_create": [I64, P, P, I32, P, I32, P, I32, P, P],
+        "graph_walk_reset": [P, P],
+        "graph_walk_step": [P, I64],
+        "graph_walk_probabilities": [P, P, I32],
+        "graph_walk_norm": [P, P],
+        "graph_walk_get_state": [P, P, I32],
+        "graph_walk_info": [P, P],
+        "graph_walk_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -163,7 +179,7 @@ def load():
         f.restype = ctypes.c_int
     lib.surr_num_params.argtypes = []
     lib.surr_num_params.restype = ctypes.c_int64
-    for name in ("walk_last_error", "walk_batch_last_error", "surr_last_error"):
+    for name in ("walk_last_error", "walk_batch_last_error", "surr_last_error", "graph_walk_last_error"):
         f = getattr(lib, name)
         f.argtypes = []
         f.restype = ctypes.c_char_p
@@ -576,6 +592,77 @@ class Surrogate:
 
     def __exit__(self, *exc):
         self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _gcheck(rc: int):
+    if rc != QW_OK:
+        msg = load().graph_walk_last_error().decode(errors="replace")
+        raise QWError(rc, msg)
+
+
+class GraphWalk:
+    """Coined walk on a general graph (graph_walk_*): arcs in compressed rows,
+    one amplitude per arc; coins by degree (GROVER, FOURIER or DENSE)."""
+
+    def __init__(self, offsets, targets, coin_kind: int, psi0, prec: int = QW_C128, dense=None, stream=None):
+        lib = load()
+        self._lib = lib
+        self.off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        self.nv = self.off.size - 1
+        p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+        table, dmax = None, 0
+        if dense is not None:
+            dmax = len(dense)
+            table = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.complex128).ravel() for m in dense]))
+        self._table = table
+        h = ctypes.c_void_p()
+        _gcheck(lib.graph_walk_create(self.nv, self.off.ctypes.data, self.tgt.ctypes.data if self.tgt.size else None,
+                                      int(coin_kind), table.ctypes.data if table is not None else None, dmax,
+                                      p0.ctypes.data, int(prec), _stream_of(stream), ctypes.byref(h)))
+        self.h = h
+
+    def reset(self, psi0):
+        p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+        _gcheck(self._lib.graph_walk_reset(self.h, p0.ctypes.data))
+
+    def step(self, T: int):
+        _gcheck(self._lib.graph_walk_step(self.h, int(T)))
+
+    def probabilities(self, out=None):
+        if out is not None:
+            _gcheck(self._lib.graph_walk_probabilities(self.h, _ptr_of(out), 1))
+            return out
+        P = np.empty(self.nv, dtype=np.float64)
+        _gcheck(self._lib.graph_walk_probabilities(self.h, P.ctypes.data, 0))
+        return P
+
+    def norm(self) -> float:
+        n = ctypes.c_double()
+        _gcheck(self._lib.graph_walk_norm(self.h, ctypes.byref(n)))
+        return n.value
+
+    def get_state(self) -> np.ndarray:
+        psi = np.empty(self.tgt.size, dtype=np.complex128)
+        _gcheck(self._lib.graph_walk_get_state(self.h, psi.ctypes.data, 0))
+        return psi
+
+    def info(self) -> GraphInfo:
+        i = GraphInfo()
+        _gcheck(self._lib.graph_walk_info(self.h, ctypes.byref(i)))
+        return i
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            rc = self._lib.graph_walk_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            _gcheck(rc)
 
     def __del__(self):
         try:

@@ -27,7 +27,7 @@ def lib():
 def header_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:walk|surr)_\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:graph_walk|walk|surr)_\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_header_lists_the_binding_symbols():
@@ -121,6 +121,34 @@ def test_unnormalised_start(lib):
     lat = _lat((16,), inputs.RING)
     rc, msg = _create(lib, lat, psi0=np.array([1.0, 1e-6]))
     assert rc == qwalk.QW_ENOTNORM
+
+
+def test_graph_walk_validation(lib):
+    """Graph walks: bad rows, unpaired arcs and bad coins are refused on the host."""
+    h = ctypes.c_void_p()
+    psi = np.zeros(4, dtype=np.complex128)
+    psi[0] = 1.0
+    def create(off, tgt, kind=qwalk.GROVER, p=psi, dense=None, dmax=0, prec=qwalk.QW_C128):
+        o = np.asarray(off, dtype=np.int64)
+        t = np.asarray(tgt, dtype=np.int64)
+        d = None if dense is None else np.ascontiguousarray(dense, dtype=np.complex128)
+        return lib.graph_walk_create(o.size - 1, o.ctypes.data, t.ctypes.data if t.size else None, kind,
+                                     d.ctypes.data if d is not None else None, dmax, p.ctypes.data, prec, None,
+                                     ctypes.byref(h))
+    assert create([1, 2, 4], [1, 1, 0, 0]) == qwalk.QW_EINVAL          # offsets[0] != 0
+    assert create([0, 3, 2], [1, 1, 0, 0]) == qwalk.QW_EINVAL          # decreasing offsets
+    assert create([0, 2, 4], [1, 2, 0, 0]) == qwalk.QW_EINVAL          # target out of range
+    assert create([0, 2, 4], [1, 1, 0, 1]) == qwalk.QW_EINVAL          # arc 0 -> 1 twice, 1 -> 0 once
+    assert b"reverse" in lib.graph_walk_last_error()
+    assert create([0, 2, 4], [1, 1, 0, 0], kind=qwalk.HADAMARD) == qwalk.QW_EINVAL
+    assert create([0, 2, 4], [1, 1, 0, 0], p=psi * 2) == qwalk.QW_ENOTNORM
+    bad = [np.eye(1), np.array([[1.0, 1.0], [0.0, 1.0]])]              # degree-2 coin not unitary
+    table = np.concatenate([m.ravel() for m in bad]).astype(np.complex128)
+    assert create([0, 2, 4], [1, 1, 0, 0], kind=qwalk.DENSE, dense=table, dmax=2) == qwalk.QW_EINVAL
+    assert b"unitary" in lib.graph_walk_last_error()
+    assert create([0, 2, 4], [1, 1, 0, 0], kind=qwalk.DENSE, dense=table[:1], dmax=1) == qwalk.QW_EINVAL
+    assert lib.graph_walk_step(None, 1) == qwalk.QW_EINVAL
+    assert lib.graph_walk_destroy(None) == qwalk.QW_OK
 
 
 def test_null_handles(lib):

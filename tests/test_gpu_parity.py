@@ -340,3 +340,20 @@ def test_grover_4096_t2048_properties(prec):
     assert abs(P[x0[1], x0[0]] - lim) <= (1e-5 if prec == qwalk.QW_C128 else 3e-5)
     yy, xx = np.meshgrid(np.arange(P.shape[0]) - x0[1], np.arange(P.shape[1]) - x0[0], indexing="ij")
     assert np.all(P[(xx + yy - cfg["T"]) % 2 != 0] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["fourier2d_diag", "fourier2d_natural"])
+def test_fourier_workloads_full_size(name):
+    """The paper's 2D workload shape (Fourier coin, diagonal and natural
+    lattices, Size 500) at full size against the oracle."""
+    cfg = inputs.config(name)
+    ext, T, x0 = cfg["extent"], cfg["T"], cfg["x0"]
+    P, psi, n, _ = _run_gpu(ext, cfg["disp"], cfg["coin"], cfg["psi0"], x0, T, qwalk.QW_C128)
+    Pr, psir = _oracle_run(ext, cfg["disp"], _oracle_coin(oracle.FOURIER, 4), cfg["psi0"], x0, T)
+    assert np.max(np.abs(P - Pr)) <= TOL64
+    assert np.max(np.abs(_as_oracle_layout(psi) - psir)) <= TOL64
+    assert abs(n - 1.0) <= TOL64
+    # the diagonal lattice moves both coordinates every step: site parity (x + y) even
+    if cfg["disp"] == inputs.DIAG:
+        yy, xx = np.indices(P.shape)
+        assert np.all(P[((xx - x0[0]) + (yy - x0[1])) % 2 == 1] == 0.0)
