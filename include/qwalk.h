@@ -194,15 +194,16 @@ int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device);
  * every step each link of the lattice is broken with probability p, and a
  * component that would cross a broken link stays on its site with its coin
  * index complemented (reflected): psi'(x, c) = (C psi)(x, cbar) instead of
- * (C psi)(x - e_c, c), e_cbar = -e_c.  The draws are Philox4x32-10 (Salmon et
- * al., SC'11) at counter (link id low and high 32 bits, step index, realization)
- * with key (seed low and high 32 bits); a link is broken when the first output
- * word is below floor(p * 2^32).  Links: the components form opposite pairs; in
- * each pair the positive member has e.x > 0, or e.x = 0 and e.y > 0, and pairs
- * are numbered by it in component order; the link that a move along the
- * positive member leaves site (x, y) by has id (y * Lx + x) * npairs + pair, and
- * the move back across it (the negative member, from the other end) uses the
- * same id.  Step indices count from 0 at t = 0.
+ * (C psi)(x - e_c, c), e_cbar = -e_c.  Links: the components form opposite
+ * pairs; in each pair the positive member has e.x > 0, or e.x = 0 and e.y > 0,
+ * and pairs are numbered (0, 1) by it in component order; site (x, y) owns, for
+ * each pair, the link it is left by along the positive member, and the move
+ * back across that link (the negative member, from the other end) sees the
+ * same link.  At every step one Philox4x32-10 call (Salmon et al., SC'11) per
+ * site, at counter (site low and high 32 bits, step index, realization) with
+ * key (seed low and high 32 bits), site = y * Lx + x, draws the links the site
+ * owns: the link of pair q is broken when output word q is below
+ * floor(p * 2^32).  Step indices count from 0 at t = 0.
  * p = 0 switches the links back to intact.  Call at t = 0 (after walk_create or
  * walk_reset; walk_reset keeps the setting).  While links break: one step per
  * kernel launch, walk_step_inverse is refused, walk_set_state only at t = 0.

@@ -337,8 +337,9 @@ int step1(qw_walk *w) {
     return QW_OK;
 }
 
-// K fused steps with a blocked kernel; returns QW_OK
-int stepK(qw_walk *w, int K, bool ring) {
+// K fused steps with a blocked kernel; returns QW_OK.  links: broken links /
+// walls of a torus walk (then w->t is the walk time at the launch)
+int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     int64_t upd = 0;
     for (int s = 1; s <= K; ++s) {
         grow_forward(w, 1);
@@ -354,7 +355,7 @@ int stepK(qw_walk *w, int K, bool ring) {
     {
         const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves};
         QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
-                               w->stream, &li),
+                               w->stream, &li, links, w->t),
                "2D streaming kernel");
     }
     tm.done(ring ? QW_KERNEL_RING_TILES : QW_KERNEL_STREAM2D, li, (double)upd);
@@ -421,9 +422,24 @@ int step1_rbl(qw_walk *w) {
 int run_forward(qw_walk *w, int64_t n) {
     if (n <= 0) return QW_OK;
     if (w->rbl_on) {
-        // one step per launch: every step draws its own links
+        // tori: K steps per launch, each level drawing its step's links inside
+        // the streaming kernel; rings and the remainder: one step per launch
         const int64_t t0 = w->t;
-        for (int64_t k = 0; k < n; ++k) {
+        int64_t left = n;
+        const int depth = w->opt.block_depth ? w->opt.block_depth : default_depth(w);
+        if (w->dim == 2 && depth > 1 && w->g.Lx >= 64 && stream2d_supported(w->prec, w->table, depth)) {
+            Links L = w->rbl;
+            while (left >= depth) {
+                int rc = stepK(w, depth, false, &L);
+                if (rc) {
+                    w->t = t0;
+                    return rc;
+                }
+                w->t += depth;
+                left -= depth;
+            }
+        }
+        for (; left > 0; --left) {
             int rc = step1_rbl(w);
             if (rc) {
                 w->t = t0;

@@ -66,12 +66,12 @@ hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
                              const Box &out_box, const CoinF64 &C, int K, hipStream_t s,
                              LaunchInfo *info);
 // K steps on a torus with the row-streaming register kernel
-// Random broken links (Sec. 3, Eqs. (9)-(10)) of one step: a link is broken
-// when word 0 of Philox4x32-10 at counter (link id lo, hi, step, realization),
-// key (seed lo, hi), is below thr.  step < 0 or thr == 0: every link intact.
-// Link of the move along component c into site y: positive member of the
-// pair (pos[c]): the link of the start site y - e_c; otherwise the link of y;
-// id = site * np + pair[c].  A broken move delivers component opp[c] of y.
+// Random broken links (Sec. 3, Eqs. (9)-(10)) of one step: the link of pair q
+// owned by a site is broken when word q of Philox4x32-10 at counter (site lo,
+// hi, step, realization), key (seed lo, hi), is below thr.  step < 0 or
+// thr == 0: every link intact.  The link of the move along component c into
+// site y is owned by the start site y - e_c for the positive member of the
+// pair (pos[c]), by y otherwise.  A broken move delivers component opp[c] of y.
 // walls != 0: the links a move would wrap through are always broken (finite
 // segment / box with reflecting walls).
 struct Links {
@@ -89,9 +89,11 @@ struct StreamTune {
     int prefetch;  // input rows read ahead, in registers: 1 or 3
     int waves;     // waves to launch (0 = default)
 };
+// links != NULL: the walk has broken links / walls; t0 = its time at the launch
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out,
                            const Geom &g, const Box &out_box, const CoinF64 &C, int K,
-                           const StreamTune &tune, hipStream_t s, LaunchInfo *info);
+                           const StreamTune &tune, hipStream_t s, LaunchInfo *info,
+                           const Links *links = nullptr, int64_t t0 = 0);
 bool stream2d_supported(int prec, int table, int K);
 // P(x) (if P != nullptr) and the fp64 norm into scratch->norm.  psi_box: the box
 // outside which psi is zero.

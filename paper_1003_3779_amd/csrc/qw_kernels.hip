@@ -247,17 +247,44 @@ __host__ __device__ constexpr int tab_ey(int table, int c) {
 }
 
 // ---- torus streaming kernel: begin ----
+// opposite component, positive member and pair number of each table entry
+// (the link ownership of the broken-link walk)
+__host__ __device__ constexpr int tab_opp(int table, int c) {
+    return table == TABLE_PAIR ? (c ^ 1) : 3 - c;  // PAIR pairs {0,1}, {2,3}; EQ8, DIAG {0,3}, {1,2}
+}
+__host__ __device__ constexpr bool tab_pos(int table, int c) {
+    return tab_ex(table, c) > 0 || (tab_ex(table, c) == 0 && tab_ey(table, c) > 0);
+}
+__host__ __device__ constexpr int tab_pair(int table, int c) {
+    // pairs numbered by their positive member in component order
+    return table == TABLE_PAIR ? (c >> 1) : (c == 0 || c == 3 ? 0 : 1);
+}
+
 template <typename R, int K, int M> struct StreamRegs {
     cv<R> v[K][3][4][M];  // [level][row slot][component][column]
 };
 
+// Broken links inside the stream (RB): level s advances a_{t0+s} and applies
+// first the shift pending in it, whose links are those of step t0 + s - 1
+// (none when t0 + s = 0).  Every lane draws, per level, the links its site
+// owns in the row entering the level (one generator call: word q = pair q);
+// a window of 2-bit codes per level keeps the rows above, and the
+// neighbouring columns' codes arrive by the same cross-lane moves as the
+// amplitudes.  A broken move takes the opposite component of the site itself.
+struct StreamLinks {
+    Links L;        // probability threshold, key, realization, walls
+    int64_t t0;     // walk time at the launch
+    int row_cons;   // row entering level 0 this iteration (absolute, wrapped)
+};
+
 // PD: rows of read-ahead held in registers (1 or 3)
-template <typename R, int K, int M, int TABLE, int COIN, int PD, int PH>
+template <typename R, int K, int M, int TABLE, int COIN, int PD, int PH, bool RB = false>
 __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)[PD][4][M],
                                             const cv<R> *__restrict__ in,
                                             cv<R> *__restrict__ out, const Geom &g, const int (&xcol)[M],
                                             const bool (&store_col)[M], int row_next, int row_out,
-                                            bool do_store, const CoinR<R> &C) {
+                                            bool do_store, const CoinR<R> &C, int (&lw)[K],
+                                            const StreamLinks &SL) {
     // slot PH receives the newest row, slot (PH+2)%3 holds the row before it
     // (the row being computed at the next level), slot (PH+1)%3 the oldest.
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
@@ -281,6 +308,22 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
             for (int m = 0; m < M; ++m) st.v[s][NEW][c][m] = cur[c][m];
         // gather for the row in slot MID of level s
         cv<R> gth[4][M];
+        int code_new = 0;  // links owned by this lane's site in the entering row
+        int yn = 0;        // that row
+        if constexpr (RB) {
+            static_assert(M == 1, "broken links in the stream: one column per lane");
+            yn = SL.row_cons - s;
+            yn = yn < 0 ? yn + g.Ly : yn;
+            const int64_t step = SL.t0 + s - 1;
+            if (step >= 0 && SL.L.thr != 0) {
+                const uint64_t site = (uint64_t)yn * (uint64_t)g.Lx + (uint64_t)xcol[0];
+                const uint2 w = philox_w01((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)step,
+                                           SL.L.realization, SL.L.key0, SL.L.key1);
+                code_new = ((uint64_t)w.x < SL.L.thr ? 1 : 0) | ((uint64_t)w.y < SL.L.thr ? 2 : 0);
+            }
+            // window: bits 1:0 the entering row (y + 1), 3:2 row y, 5:4 row y - 1
+            lw[s] = ((lw[s] << 2) | code_new) & 0x3F;
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int ey = tab_ey(TABLE, c), ex = tab_ex(TABLE, c);
@@ -296,6 +339,34 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
                 const cv<R> nb = from_right<R>(st.v[s][slot][c][0]);
 #pragma unroll
                 for (int m = 0; m < M; ++m) gth[c][m] = m == M - 1 ? nb : st.v[s][slot][c][m == M - 1 ? m : m + 1];
+            }
+        }
+        if constexpr (RB) {
+            // the row computed here is y = yn - 1; its moves along c come from
+            // y - e_c, across the link owned by y - e_c (positive member) or by
+            // (x, y) (negative member)
+            const int64_t step = SL.t0 + s - 1;
+            if (step >= 0) {
+                int y = yn - 1;
+                y = y < 0 ? y + g.Ly : y;
+                const int x = xcol[0];
+                const int w = lw[s], wl = dpp_from_left(w), wr = dpp_from_right(w);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int ex = tab_ex(TABLE, c), ey = tab_ey(TABLE, c);
+                    const bool pos = tab_pos(TABLE, c);
+                    // owner row: y - ey for the positive member (window slot: ey > 0 -> row y - 1
+                    // at bits 5:4; ey < 0 -> row y + 1 at bits 1:0), else row y (bits 3:2)
+                    const int shift = pos ? (ey > 0 ? 4 : (ey < 0 ? 0 : 2)) : 2;
+                    // owner column: x - ex for the positive member, else x
+                    const int src = pos ? (ex > 0 ? wl : (ex < 0 ? wr : w)) : w;
+                    bool broken = ((src >> (shift + tab_pair(TABLE, c))) & 1) != 0;
+                    if (SL.L.walls) {
+                        const int rx = x - ex, ry = y - ey;
+                        broken = broken || rx < 0 || rx >= g.Lx || ry < 0 || ry >= g.Ly;
+                    }
+                    if (broken) gth[c][0] = st.v[s][MID][tab_opp(TABLE, c)][0];
+                }
             }
         }
 #pragma unroll
@@ -317,9 +388,10 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
     }
 }
 
-template <typename R, int K, int M, int TABLE, int COIN, int PD>
+template <typename R, int K, int M, int TABLE, int COIN, int PD, bool RB = false>
 __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
-                                                  Geom g, Box b, int seg_rows, int nstrips, CoinR<R> C) {
+                                                  Geom g, Box b, int seg_rows, int nstrips, CoinR<R> C,
+                                                  StreamLinks SL) {
     static_assert(PD == 1 || PD == 3, "the stream loop is unrolled by 3: read-ahead 1 or 3 rows");
     constexpr int TW = 64 * M - 2 * K;
     const int lane = threadIdx.x & 63;
@@ -352,6 +424,11 @@ __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, 
     row_ld = row_ld < 0 ? row_ld + g.Ly : row_ld;
     int row_out = (b.y0 + r0 - 2 * K) % g.Ly;  // advanced in step with the input
     row_out = row_out < 0 ? row_out + g.Ly : row_out;
+    int lw[K];  // link-code windows per level (broken links)
+#pragma unroll
+    for (int s = 0; s < K; ++s) lw[s] = 0;
+    int row_cons = (b.y0 + r0 - K) % g.Ly;  // row entering level 0 at the next iteration
+    row_cons = row_cons < 0 ? row_cons + g.Ly : row_cons;
     cv<R> pf[PD][4][M];  // input rows requested ahead of use
 #pragma unroll
     for (int p = 0; p < PD; ++p) {
@@ -363,16 +440,22 @@ __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, 
     }
     // (rows past the segment end are requested too -- in bounds, modulo Ly -- and never used)
     for (int i = 0; i < niter; i += 3) {
-        stream_iter<R, K, M, TABLE, COIN, PD, 0>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
-                                                 i >= 2 * K && i < niter, C);
+        SL.row_cons = row_cons;
+        stream_iter<R, K, M, TABLE, COIN, PD, 0, RB>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                     i >= 2 * K && i < niter, C, lw, SL);
+        row_cons = row_cons + 1 == g.Ly ? 0 : row_cons + 1;
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
         row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
-        stream_iter<R, K, M, TABLE, COIN, PD, 1>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
-                                                 i + 1 >= 2 * K && i + 1 < niter, C);
+        SL.row_cons = row_cons;
+        stream_iter<R, K, M, TABLE, COIN, PD, 1, RB>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                     i + 1 >= 2 * K && i + 1 < niter, C, lw, SL);
+        row_cons = row_cons + 1 == g.Ly ? 0 : row_cons + 1;
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
         row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
-        stream_iter<R, K, M, TABLE, COIN, PD, 2>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
-                                                 i + 2 >= 2 * K && i + 2 < niter, C);
+        SL.row_cons = row_cons;
+        stream_iter<R, K, M, TABLE, COIN, PD, 2, RB>(st, pf, in, out, g, xcol, store_col, row_ld, row_out,
+                                                     i + 2 >= 2 * K && i + 2 < niter, C, lw, SL);
+        row_cons = row_cons + 1 == g.Ly ? 0 : row_cons + 1;
         row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
         row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
     }
@@ -507,26 +590,6 @@ __global__ __launch_bounds__(256) void k_set_state(cv<R> *__restrict__ a, Geom g
 // =====================================================================
 // random broken links (Sec. 3, Eqs. (9)-(10))
 // =====================================================================
-// Philox4x32-10 (Salmon et al., SC'11), first output word: ten rounds of two
-// 32x32 -> 64-bit products of counter words 0 and 2 with the round
-// multipliers, the high halves mixed into the other words and the key, the
-// key advanced by the Weyl increments after every round.
-__device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                              uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
-        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
-        c0 = h1 ^ c1 ^ k0;
-        c1 = l1;
-        c2 = h0 ^ c3 ^ k1;
-        c3 = l0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c0;
-}
-
 // psi(x, y, c) = (S_L a)(x, y, c): the value that the step's shift delivers to
 // component c of site (x, y)
 template <typename R>
@@ -537,12 +600,14 @@ __device__ __forceinline__ cv<R> shifted(const cv<R> *__restrict__ a, const Geom
     if (L.step >= 0) {
         bool broken = L.walls && (rx < 0 || rx >= g.Lx || ry < 0 || ry >= g.Ly);
         if (!broken && L.thr != 0) {
+            // the link's owner: the start site of a move along the positive
+            // member, the arrival site of one along the negative member; one
+            // generator call per (site, step) draws the links of both pairs
             const uint64_t site = L.pos[c] ? (uint64_t)sy * (uint64_t)g.Lx + (uint64_t)sx
                                            : (uint64_t)y * (uint64_t)g.Lx + (uint64_t)x;
-            const uint64_t link = site * (uint64_t)L.np + (uint64_t)L.pair[c];
-            const uint32_t w0 = philox_w0((uint32_t)link, (uint32_t)(link >> 32), (uint32_t)L.step,
-                                          L.realization, L.key0, L.key1);
-            broken = (uint64_t)w0 < L.thr;
+            const uint2 w = philox_w01((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)L.step, L.realization,
+                                       L.key0, L.key1);
+            broken = (uint64_t)(L.pair[c] == 0 ? w.x : w.y) < L.thr;
         }
         if (broken) return a[(int64_t)L.opp[c] * g.ps + (int64_t)y * g.Lx + x];
     }
@@ -785,7 +850,7 @@ hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
 // ---- torus streaming kernel: begin ----
 template <typename R, int K, int M, int TABLE, int COIN, int PD>
 static void stream_t(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
-                     const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
+                     const StreamTune &tu, hipStream_t s, LaunchInfo *info, const StreamLinks *sl) {
     constexpr int TW = 64 * M - 2 * K;
     const int nstrips = (b.wx + TW - 1) / TW;
     // rows per segment: many short segments (down to 4K rows, the 2K-row
@@ -805,34 +870,43 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
         info->bytes_read = (double)nstrips * 64 * M * ((double)b.wy + 2.0 * K * nseg) * 4 * sizeof(cv<R>);
         info->bytes_written = (double)b.wx * b.wy * 4 * sizeof(cv<R>);
     }
+    if (sl) {
+        // broken links: one read-ahead row (the generator's registers take the place of the others)
+        if constexpr (PD == 1)
+            hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, 1, true>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), *sl);
+        return;
+    }
     hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C));
+                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), StreamLinks{});
 }
 
 template <typename R, int K, int M, int TABLE, int PD>
 static void stream_coin(int coin_impl, const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C,
-                        const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
-    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4, PD>(in, out, g, b, C, tu, s, info);
-    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4, PD>(in, out, g, b, C, tu, s, info);
-    else stream_t<R, K, M, TABLE, COIN_DENSE, PD>(in, out, g, b, C, tu, s, info);
+                        const StreamTune &tu, hipStream_t s, LaunchInfo *info, const StreamLinks *sl) {
+    if (coin_impl == COIN_GROVER4) stream_t<R, K, M, TABLE, COIN_GROVER4, PD>(in, out, g, b, C, tu, s, info, sl);
+    else if (coin_impl == COIN_HH4) stream_t<R, K, M, TABLE, COIN_HH4, PD>(in, out, g, b, C, tu, s, info, sl);
+    else stream_t<R, K, M, TABLE, COIN_DENSE, PD>(in, out, g, b, C, tu, s, info, sl);
 }
 
 template <typename R, int K, int M, int PD>
 static bool stream_table(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
-                         const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
+                         const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info,
+                         const StreamLinks *sl) {
     switch (table) {
-    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
-    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
-    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG, PD>(coin_impl, in, out, g, b, C, tu, s, info); return true;
+    case TABLE_PAIR: stream_coin<R, K, M, TABLE_PAIR, PD>(coin_impl, in, out, g, b, C, tu, s, info, sl); return true;
+    case TABLE_EQ8: stream_coin<R, K, M, TABLE_EQ8, PD>(coin_impl, in, out, g, b, C, tu, s, info, sl); return true;
+    case TABLE_DIAG: stream_coin<R, K, M, TABLE_DIAG, PD>(coin_impl, in, out, g, b, C, tu, s, info, sl); return true;
     default: return false;
     }
 }
 
 template <typename R, int K, int M>
 static bool stream_pd(int table, int coin_impl, const void *in, void *out, const Geom &g, const Box &b,
-                      const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info) {
-    return tu.prefetch == 1 ? stream_table<R, K, M, 1>(table, coin_impl, in, out, g, b, C, tu, s, info)
-                            : stream_table<R, K, M, 3>(table, coin_impl, in, out, g, b, C, tu, s, info);
+                      const CoinF64 &C, const StreamTune &tu, hipStream_t s, LaunchInfo *info,
+                      const StreamLinks *sl) {
+    return (tu.prefetch == 1 || sl) ? stream_table<R, K, M, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, sl)
+                                    : stream_table<R, K, M, 3>(table, coin_impl, in, out, g, b, C, tu, s, info, sl);
 }
 
 bool stream2d_supported(int prec, int table, int K) {
@@ -843,7 +917,13 @@ bool stream2d_supported(int prec, int table, int K) {
 
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
                            const Box &b, const CoinF64 &C, int K, const StreamTune &tu, hipStream_t s,
-                           LaunchInfo *info) {
+                           LaunchInfo *info, const Links *links, int64_t t0) {
+    StreamLinks sl{};
+    if (links) {
+        sl.L = *links;
+        sl.t0 = t0;
+    }
+    const StreamLinks *slp = links ? &sl : nullptr;
     if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
     if (!stream2d_supported(prec, table, K)) return hipErrorInvalidValue;
     if (tu.prefetch != 1 && tu.prefetch != 3) return hipErrorInvalidValue;
@@ -851,12 +931,12 @@ hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, v
     if (g.Lx < 64) return hipErrorInvalidValue;
     bool ok = false;
     if (prec == C128) {
-        if (K == 4) ok = stream_pd<double, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
-        else ok = stream_pd<double, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
+        if (K == 4) ok = stream_pd<double, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
+        else ok = stream_pd<double, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
     } else {
-        if (K == 4) ok = stream_pd<float, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
-        else if (K == 8) ok = stream_pd<float, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
-        else ok = stream_pd<float, 16, 1>(table, coin_impl, in, out, g, b, C, tu, s, info);
+        if (K == 4) ok = stream_pd<float, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
+        else if (K == 8) ok = stream_pd<float, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
+        else ok = stream_pd<float, 16, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
     }
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();

@@ -207,3 +207,77 @@ def test_segment_c64_and_walls_off_again():
     w.destroy()
     ref = oracle.prob(oracle.walk(N, 1, inputs.RING, C, (x0, 0), inputs.PSI0_LR, T))[0]
     assert np.max(np.abs(Pp - ref)) <= TOL64
+
+
+# ------------------------------------------ broken links inside the blocked torus kernel
+def _walk_opts(ext, disp, kind, psi0, x0, T, prec, p, seed, real, walls, depth, dense=None):
+    w = qwalk.Walk(ext, disp, kind, psi0, x0, prec=prec, dense=dense)
+    w.set_options(block_depth=depth, renorm_every=0)
+    if walls:
+        w.set_reflecting_walls(True)
+    w.set_broken_links(p, seed, real)
+    w.step(T)
+    psi = np.transpose(w.get_state(), (1, 2, 0))
+    P = w.probabilities()
+    w.destroy()
+    return P, psi
+
+
+@pytest.mark.parametrize("table", ["PAIR", "EQ8", "DIAG"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_blocked_torus_matches_one_step_and_oracle(table, walls):
+    """Tori with broken links run K steps per launch, each level drawing its own
+    step's links: the same amplitudes, bit for bit, as one step per launch, and
+    the oracle's to 1e-12."""
+    disp = getattr(inputs, table)
+    rng = np.random.default_rng(len(table) * 3 + int(walls))
+    U = inputs.haar_unitary(rng, 4)
+    psi0 = inputs.haar_state(rng, 4)
+    ext, x0, T = (150, 70), (10, 60), 67            # ragged strips, wraps in y, 8 blocks + 3 single steps
+    ref_P, ref_psi = None, None
+    for depth in (1, 4, 8):
+        P, psi = _walk_opts(ext, disp, qwalk.DENSE, psi0, x0, T, qwalk.QW_C128, 0.2, 31, 2, walls, depth, dense=U)
+        if ref_psi is None:
+            ref_P, ref_psi = P, psi
+        else:
+            assert np.array_equal(psi, ref_psi), depth
+    # the same walk in pieces: blocks that start at t0 > 0 take that step's links
+    w = qwalk.Walk(ext, disp, qwalk.DENSE, psi0, x0, prec=qwalk.QW_C128, dense=U)
+    w.set_options(block_depth=8, renorm_every=0)
+    if walls:
+        w.set_reflecting_walls(True)
+    w.set_broken_links(0.2, 31, 2)
+    for n in (5, 17, 45):
+        w.step(n)
+    psi_pieces = np.transpose(w.get_state(), (1, 2, 0))
+    w.destroy()
+    assert np.array_equal(psi_pieces, ref_psi)
+    o = oracle.initial_state(ext[0], ext[1], 4, x0, psi0)
+    o = oracle.evolve_rbl(o, disp, U, T, p=0.2, seed=31, realization=2, walls=walls)
+    assert np.max(np.abs(ref_psi - o)) <= TOL64
+    assert np.max(np.abs(ref_P - oracle.prob(o))) <= TOL64
+
+
+def test_blocked_torus_every_link_broken():
+    """p = 1: every link reflects at every step; the walker stays on its sites."""
+    rng = np.random.default_rng(17)
+    psi0 = inputs.haar_state(rng, 4)
+    ext, x0, T = (96, 64), (40, 30), 40
+    P, psi = _walk_opts(ext, inputs.PAIR, qwalk.GROVER, psi0, x0, T, qwalk.QW_C128, 1.0, 2, 0, False, 8)
+    o = oracle.initial_state(ext[0], ext[1], 4, x0, psi0)
+    o = oracle.evolve_rbl(o, inputs.PAIR, oracle.coin(oracle.GROVER, 4), T, p=1.0, seed=2, realization=0)
+    assert np.max(np.abs(psi - o)) <= TOL64
+    assert np.count_nonzero(P > 1e-20) <= 5
+
+
+@pytest.mark.parametrize("kind", [qwalk.GROVER, qwalk.HADAMARD2])
+def test_blocked_torus_c64_all_depths(kind):
+    rng = np.random.default_rng(90 + kind)
+    psi0 = inputs.haar_state(rng, 4)
+    ext, x0, T = (128, 96), (64, 48), 83
+    okind = oracle.GROVER if kind == qwalk.GROVER else oracle.HADAMARD2
+    o = oracle.initial_state(ext[0], ext[1], 4, x0, psi0)
+    ref = oracle.prob(oracle.evolve_rbl(o, inputs.PAIR, oracle.coin(okind, 4), T, p=0.1, seed=5, realization=0))
+    for depth in (4, 8, 16):
+        P, _ = _walk_opts(ext, inputs.PAIR, kind, psi0, x0, T, qwalk.QW_C64, 0.1, 5, 0, False, depth)
+        assert np.max(np.abs(P - ref)) <= TOL32_P, depth

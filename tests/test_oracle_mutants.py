@@ -45,8 +45,9 @@ MUTANTS = {
     "philox_multiplier": ("const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;",
                           "const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D55u;"),
     "philox_key_schedule": ("if (r > 0) { k0 += W0; k1 += W1; }", "if (r > 1) { k0 += W0; k1 += W1; }"),
-    "rbl_step_counter": ("link_broken(link, (uint64_t)(step0 + s), realization, seed, thr)",
-                         "link_broken(link, (uint64_t)step0, realization, seed, thr)"),
+    "rbl_step_counter": ("link_broken(owner, pair[c], (uint64_t)(step0 + s), realization, seed, thr)",
+                         "link_broken(owner, pair[c], (uint64_t)step0, realization, seed, thr)"),
+    "rbl_pair_word": ("return (uint64_t)o[pair] < thr;", "return (uint64_t)o[0] < thr;"),
     "wall_edge_test": ("int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);",
                        "int edge = walls && (rx < 0 || rx > Lx || ry < 0 || ry >= Ly);"),
     "graph_no_shift": ("b[rev[k0 + i]] = acc;   /* the shift: to the other end of the edge */",
@@ -87,6 +88,7 @@ BATTERY = [
     lambda: RB.test_each_step_is_a_reflecting_shift("RING"),
     lambda: RB.test_reflection_frequency_matches_p(),
     lambda: RB.test_steps_compose("PAIR"),
+    lambda: RB.test_links_of_one_site_are_independent(),
     lambda: RB.test_walls_two_site_segment_by_hand(),
     lambda: RB.test_walls_segment_never_wraps(),
     lambda: RB.test_walls_reflect_exactly_at_the_edge("PAIR"),

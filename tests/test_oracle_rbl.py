@@ -173,6 +173,28 @@ def test_reflection_frequency_matches_p():
     assert abs(frac - p) <= 5 * np.sqrt(p * (1 - p) / n)
 
 
+def test_links_of_one_site_are_independent():
+    """The x- and y-links a site owns are drawn from different output words: the
+    fraction of sites with both broken is p^2 (within 5 sigma), not p."""
+    Lx, Ly, p, T = 64, 64, 0.3, 20
+    C = np.eye(4)
+    both = 0
+    for step in range(T):
+        psi = np.zeros((Ly, Lx, 4), dtype=np.complex128)
+        psi[:, :, 0] = 1.0                               # +x component everywhere
+        psi[:, :, 2] = 1.0                               # +y component everywhere
+        out = oracle.evolve_rbl(psi, inputs.PAIR, C, 1, p=p, seed=17, realization=1, step0=step)
+        # the x-link owned by (x, y) reflected the +x move into (x + 1, y); the
+        # y-link owned by (x, y) the +y move into (x, y + 1)
+        xb = np.abs(np.roll(out[:, :, 0], -1, axis=1)) < 0.5
+        yb = np.abs(np.roll(out[:, :, 2], -1, axis=0)) < 0.5
+        both += int(np.sum(xb & yb))
+    n = Lx * Ly * T
+    frac = both / n
+    q = p * p
+    assert abs(frac - q) <= 5 * np.sqrt(q * (1 - q) / n)
+
+
 def test_norm_kept_and_spreading_slowed():
     """Broken links keep the walk unitary; averaged over realizations the
     spreading is slower than the ballistic (1 - 1/sqrt 2) t^2 of the Hadamard walk."""
