@@ -95,7 +95,8 @@ typedef struct {
  * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3). */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
-                              or 2, 4, 8, 16 (temporal blocking) */
+                              or 2, 4, 8, 16 (temporal blocking); auto with broken links
+                              or walls on a torus: 4 */
     int32_t window;        /* 1: update only the light cone of the start site (exact, the
                               rest is zero); 0: sweep the whole lattice every step */
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
@@ -200,13 +201,16 @@ int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device);
  * each pair, the link it is left by along the positive member, and the move
  * back across that link (the negative member, from the other end) sees the
  * same link.  At every step one Philox4x32-10 call (Salmon et al., SC'11) per
- * site, at counter (site low and high 32 bits, step index, realization) with
- * key (seed low and high 32 bits), site = y * Lx + x, draws the links the site
- * owns: the link of pair q is broken when output word q is below
- * floor(p * 2^32).  Step indices count from 0 at t = 0.
+ * column and row pair (2j, 2j + 1), at counter (g low and high 32 bits, step
+ * index, realization) with key (seed low and high 32 bits),
+ * g = (y >> 1) * Lx + x, draws the links of both sites: the link of pair q
+ * owned by (x, y) is broken when output word 2 (y & 1) + q is below
+ * floor(p * 2^32) (on a ring, y = 0: one call per site, word 0).  Step indices
+ * count from 0 at t = 0.
  * p = 0 switches the links back to intact.  Call at t = 0 (after walk_create or
- * walk_reset; walk_reset keeps the setting).  While links break: one step per
- * kernel launch, walk_step_inverse is refused, walk_set_state only at t = 0.
+ * walk_reset; walk_reset keeps the setting).  While links break, tori run K
+ * steps per launch as without them, rings one step per launch;
+ * walk_step_inverse is refused and walk_set_state works only at t = 0.
  * QW_EINVAL: p outside [0, 1], t != 0, or a table without opposite pairs;
  * QW_ERANGE: realization >= 2^32. */
 int walk_set_broken_links(qw_walk_t w, double p, uint64_t seed, uint64_t realization);

@@ -45,7 +45,8 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile qw_oracle.c into liboracle.so with gcc (plain C, fp64)."""
-    if force or not os.path.exists(_LIB_PATH):
+    stale = not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    if force or stale:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call([
             "gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
@@ -88,8 +89,7 @@ def _open(path: str):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=False)
+        build(force=False)                      # compiles when missing or older than the source
         _lib = _open(_LIB_PATH)
     return _lib
 

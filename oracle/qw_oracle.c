@@ -316,10 +316,12 @@ int orc_bin(int64_t N, int64_t x0, const double *P, int nbins, double *out) {
  * Site a owns, for every pair, the link it is left by along the positive
  * member (towards a + e_p); a move along the negative member out of site b
  * crosses the link owned by b + e_c (so both sides see one link).  At each
- * step one generator call per site draws the links it owns:
- *   counter = (site low 32 bits, site high 32 bits, step, realization),
- *   site    = a.y * Lx + a.x,   key = (seed low 32 bits, seed high 32 bits),
- *   the link of pair q is broken  <=>  output word q < thr,
+ * step one generator call draws the four links owned by the two sites of a
+ * column in the row pair (2j, 2j + 1) (the two links of one site on a ring,
+ * where only row 0 exists and only pair 0):
+ *   counter = (g low 32 bits, g high 32 bits, step, realization),
+ *   g       = (a.y >> 1) * Lx + a.x,   key = (seed low 32 bits, seed high 32 bits),
+ *   the link of pair q owned by a is broken  <=>  output word 2 (a.y & 1) + q < thr,
  *   thr = floor(p * 2^32) in [0, 2^32].
  * ------------------------------------------------------------------------ */
 static uint32_t mulhilo32(uint32_t a, uint32_t b, uint32_t *hi) {
@@ -350,14 +352,17 @@ void orc_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-static int link_broken(uint64_t site, int pair, uint64_t step, uint64_t realization, uint64_t seed, uint64_t thr) {
+/* is the link of pair `pair` owned by site (ax, ay) broken at this step? */
+static int link_broken(int64_t ax, int64_t ay, int64_t Lx, int pair, uint64_t step, uint64_t realization,
+                       uint64_t seed, uint64_t thr) {
     uint32_t ctr[4], key[2], o[4];
+    uint64_t g = (uint64_t)((ay >> 1) * Lx + ax);
     if (thr == 0) return 0;
-    ctr[0] = (uint32_t)site; ctr[1] = (uint32_t)(site >> 32);
+    ctr[0] = (uint32_t)g; ctr[1] = (uint32_t)(g >> 32);
     ctr[2] = (uint32_t)step; ctr[3] = (uint32_t)realization;
     key[0] = (uint32_t)seed; key[1] = (uint32_t)(seed >> 32);
     orc_philox(ctr, key, o);
-    return (uint64_t)o[pair] < thr;
+    return (uint64_t)o[2 * (ay & 1) + pair] < thr;
 }
 
 /* opposite-pair structure of a displacement table; returns the number of
@@ -424,12 +429,11 @@ int orc_evolve_rbl(int64_t Lx, int64_t Ly, int d, const int *disp, const double 
                      * member the link belongs to the start site, else to the
                      * site the move arrives at */
                     int64_t lx = positive[c] ? sx : x, ly = positive[c] ? sy : y;
-                    uint64_t owner = (uint64_t)(ly * Lx + lx);
                     /* walls: the links that close the lattice periodically are
                      * always broken (a finite segment / box, Sec. 3 and Fig. 3) */
                     int64_t rx = x - disp[2 * c], ry = y - disp[2 * c + 1];
                     int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);
-                    if (edge || link_broken(owner, pair[c], (uint64_t)(step0 + s), realization, seed, thr))
+                    if (edge || link_broken(lx, ly, Lx, pair[c], (uint64_t)(step0 + s), realization, seed, thr))
                         b[(y * Lx + x) * d + c] = phi[(y * Lx + x) * d + opp[c]];
                     else
                         b[(y * Lx + x) * d + c] = phi[(sy * Lx + sx) * d + c];

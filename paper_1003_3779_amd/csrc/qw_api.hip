@@ -426,7 +426,11 @@ int run_forward(qw_walk *w, int64_t n) {
         // the streaming kernel; rings and the remainder: one step per launch
         const int64_t t0 = w->t;
         int64_t left = n;
-        const int depth = w->opt.block_depth ? w->opt.block_depth : default_depth(w);
+        // K = 4 by default: the link draws make the blocked kernel bound by its
+        // integer arithmetic, and K = 4 keeps two or more waves per SIMD (K = 8
+        // and 16 drop to one; measured on the 4096^2 torus: c128 109 ms per walk at
+        // K = 4, 174 ms at K = 8; c64 69 ms at K = 4, 101 ms at K = 8)
+        const int depth = w->opt.block_depth ? w->opt.block_depth : 4;
         if (w->dim == 2 && depth > 1 && w->g.Lx >= 64 && stream2d_supported(w->prec, w->table, depth)) {
             Links L = w->rbl;
             while (left >= depth) {

@@ -216,24 +216,24 @@ __device__ __forceinline__ void ring_tile_steps_n(cv<R> (&a0)[M], cv<R> (&a1)[M]
     }
 }
 
-// Philox4x32-10 (Salmon et al., SC'11), output words 0 and 1: ten rounds of
+// Philox4x32-10 (Salmon et al., SC'11), all four output words: ten rounds of
 // two 32x32 -> 64-bit products of counter words 0 and 2 with the round
 // multipliers, the high halves mixed into the other words and the key, the
 // key advanced by the Weyl increments after every round.
-__device__ __forceinline__ uint2 philox_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                            uint32_t k1) {
+__device__ __forceinline__ uint4 philox4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t h0 = __umulhi(0xD2511F53u, c0), l0 = 0xD2511F53u * c0;
-        const uint32_t h1 = __umulhi(0xCD9E8D57u, c2), l1 = 0xCD9E8D57u * c2;
-        c0 = h1 ^ c1 ^ k0;
-        c1 = l1;
-        c2 = h0 ^ c3 ^ k1;
-        c3 = l0;
+        // one 32 x 32 -> 64-bit product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    return make_uint2(c0, c1);
+    return make_uint4(c0, c1, c2, c3);
 }
 
 

@@ -267,7 +267,7 @@ template <typename R, int K, int M> struct StreamRegs {
 // Broken links inside the stream (RB): level s advances a_{t0+s} and applies
 // first the shift pending in it, whose links are those of step t0 + s - 1
 // (none when t0 + s = 0).  Every lane draws, per level, the links its site
-// owns in the row entering the level (one generator call: word q = pair q);
+// owns in the row entering the level (one generator call per row pair);
 // a window of 2-bit codes per level keeps the rows above, and the
 // neighbouring columns' codes arrive by the same cross-lane moves as the
 // amplitudes.  A broken move takes the opposite component of the site itself.
@@ -308,21 +308,34 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
             for (int m = 0; m < M; ++m) st.v[s][NEW][c][m] = cur[c][m];
         // gather for the row in slot MID of level s
         cv<R> gth[4][M];
-        int code_new = 0;  // links owned by this lane's site in the entering row
-        int yn = 0;        // that row
+        int yn = 0;  // the row entering level s (broken links)
         if constexpr (RB) {
             static_assert(M == 1, "broken links in the stream: one column per lane");
             yn = SL.row_cons - s;
             yn = yn < 0 ? yn + g.Ly : yn;
             const int64_t step = SL.t0 + s - 1;
+            int code_new = 0, keep = 0;  // links owned by this lane's site in row yn; codes kept for row yn + 1
             if (step >= 0 && SL.L.thr != 0) {
-                const uint64_t site = (uint64_t)yn * (uint64_t)g.Lx + (uint64_t)xcol[0];
-                const uint2 w = philox_w01((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)step,
-                                           SL.L.realization, SL.L.key0, SL.L.key1);
-                code_new = ((uint64_t)w.x < SL.L.thr ? 1 : 0) | ((uint64_t)w.y < SL.L.thr ? 2 : 0);
+                // one generator call serves the rows 2j and 2j + 1 of a column: an odd
+                // row takes the codes kept when its even partner entered this level
+                // (the same for every lane, so the branch is uniform)
+                const bool odd = (yn & 1) != 0;
+                if (odd && (__builtin_amdgcn_readfirstlane(lw[s]) & 0x100)) {
+                    code_new = (lw[s] >> 6) & 3;
+                } else {
+                    const uint64_t grp = (uint64_t)(yn >> 1) * (uint64_t)g.Lx + (uint64_t)xcol[0];
+                    const uint4 w = philox4((uint32_t)grp, (uint32_t)(grp >> 32), (uint32_t)step,
+                                            SL.L.realization, SL.L.key0, SL.L.key1);
+                    const uint64_t thr = SL.L.thr;
+                    const int c01 = ((uint64_t)w.x < thr ? 1 : 0) | ((uint64_t)w.y < thr ? 2 : 0);
+                    const int c23 = ((uint64_t)w.z < thr ? 1 : 0) | ((uint64_t)w.w < thr ? 2 : 0);
+                    code_new = odd ? c23 : c01;
+                    keep = odd ? 0 : (0x100 | (c23 << 6));
+                }
             }
-            // window: bits 1:0 the entering row (y + 1), 3:2 row y, 5:4 row y - 1
-            lw[s] = ((lw[s] << 2) | code_new) & 0x3F;
+            // window: bits 1:0 the entering row (y + 1), 3:2 row y, 5:4 row y - 1;
+            // bits 7:6 the kept codes of row yn + 1, bit 8 set when they are kept
+            lw[s] = (((lw[s] << 2) | code_new) & 0x3F) | keep;
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -365,7 +378,9 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
                         const int rx = x - ex, ry = y - ey;
                         broken = broken || rx < 0 || rx >= g.Lx || ry < 0 || ry >= g.Ly;
                     }
-                    if (broken) gth[c][0] = st.v[s][MID][tab_opp(TABLE, c)][0];
+                    const cv<R> o = st.v[s][MID][tab_opp(TABLE, c)][0];
+                    gth[c][0].x = broken ? o.x : gth[c][0].x;
+                    gth[c][0].y = broken ? o.y : gth[c][0].y;
                 }
             }
         }
@@ -395,7 +410,9 @@ __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, 
     static_assert(PD == 1 || PD == 3, "the stream loop is unrolled by 3: read-ahead 1 or 3 rows");
     constexpr int TW = 64 * M - 2 * K;
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave index is the same in every lane: kept in scalar registers, so are
+    // the row indices derived from it
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int strip = wave % nstrips, seg = wave / nstrips;
     const int r0 = seg * seg_rows;  // first output row offset of this segment
     if (r0 >= b.wy) return;         // wave-uniform exit; no barriers in this kernel
@@ -602,12 +619,15 @@ __device__ __forceinline__ cv<R> shifted(const cv<R> *__restrict__ a, const Geom
         if (!broken && L.thr != 0) {
             // the link's owner: the start site of a move along the positive
             // member, the arrival site of one along the negative member; one
-            // generator call per (site, step) draws the links of both pairs
-            const uint64_t site = L.pos[c] ? (uint64_t)sy * (uint64_t)g.Lx + (uint64_t)sx
-                                           : (uint64_t)y * (uint64_t)g.Lx + (uint64_t)x;
-            const uint2 w = philox_w01((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)L.step, L.realization,
-                                       L.key0, L.key1);
-            broken = (uint64_t)(L.pair[c] == 0 ? w.x : w.y) < L.thr;
+            // generator call per (column, row pair, step) draws the links of
+            // both pairs of both rows, word 2 (row & 1) + pair
+            const int ox = L.pos[c] ? sx : x, oy = L.pos[c] ? sy : y;
+            const uint64_t grp = (uint64_t)(oy >> 1) * (uint64_t)g.Lx + (uint64_t)ox;
+            const uint4 w = philox4((uint32_t)grp, (uint32_t)(grp >> 32), (uint32_t)L.step, L.realization, L.key0,
+                                    L.key1);
+            const int q = 2 * (oy & 1) + L.pair[c];
+            const uint32_t wq = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
+            broken = (uint64_t)wq < L.thr;
         }
         if (broken) return a[(int64_t)L.opp[c] * g.ps + (int64_t)y * g.Lx + x];
     }

@@ -45,9 +45,11 @@ MUTANTS = {
     "philox_multiplier": ("const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;",
                           "const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D55u;"),
     "philox_key_schedule": ("if (r > 0) { k0 += W0; k1 += W1; }", "if (r > 1) { k0 += W0; k1 += W1; }"),
-    "rbl_step_counter": ("link_broken(owner, pair[c], (uint64_t)(step0 + s), realization, seed, thr)",
-                         "link_broken(owner, pair[c], (uint64_t)step0, realization, seed, thr)"),
-    "rbl_pair_word": ("return (uint64_t)o[pair] < thr;", "return (uint64_t)o[0] < thr;"),
+    "rbl_step_counter": ("link_broken(lx, ly, Lx, pair[c], (uint64_t)(step0 + s), realization, seed, thr)",
+                         "link_broken(lx, ly, Lx, pair[c], (uint64_t)step0, realization, seed, thr)"),
+    "rbl_pair_word": ("return (uint64_t)o[2 * (ay & 1) + pair] < thr;", "return (uint64_t)o[2 * (ay & 1)] < thr;"),
+    "rbl_row_word": ("return (uint64_t)o[2 * (ay & 1) + pair] < thr;", "return (uint64_t)o[pair] < thr;"),
+    "rbl_group_column": ("uint64_t g = (uint64_t)((ay >> 1) * Lx + ax);", "uint64_t g = (uint64_t)((ay >> 1) * Lx);"),
     "wall_edge_test": ("int edge = walls && (rx < 0 || rx >= Lx || ry < 0 || ry >= Ly);",
                        "int edge = walls && (rx < 0 || rx > Lx || ry < 0 || ry >= Ly);"),
     "graph_no_shift": ("b[rev[k0 + i]] = acc;   /* the shift: to the other end of the edge */",
@@ -89,6 +91,7 @@ BATTERY = [
     lambda: RB.test_reflection_frequency_matches_p(),
     lambda: RB.test_steps_compose("PAIR"),
     lambda: RB.test_links_of_one_site_are_independent(),
+    lambda: RB.test_links_of_neighbouring_sites_are_independent(),
     lambda: RB.test_walls_two_site_segment_by_hand(),
     lambda: RB.test_walls_segment_never_wraps(),
     lambda: RB.test_walls_reflect_exactly_at_the_edge("PAIR"),

@@ -195,6 +195,25 @@ def test_links_of_one_site_are_independent():
     assert abs(frac - q) <= 5 * np.sqrt(q * (1 - q) / n)
 
 
+def test_links_of_neighbouring_sites_are_independent():
+    """Neighbouring sites draw different links: the x-links owned by (x, y) and
+    (x + 1, y), and by (x, 2j) and (x, 2j + 1) (one generator call serves that row
+    pair), are both broken with frequency p^2 (within 5 sigma)."""
+    Lx, Ly, p, T = 64, 64, 0.3, 20
+    C = np.eye(4)
+    horiz = vert = 0
+    for step in range(T):
+        psi = np.zeros((Ly, Lx, 4), dtype=np.complex128)
+        psi[:, :, 0] = 1.0                               # +x component everywhere
+        out = oracle.evolve_rbl(psi, inputs.PAIR, C, 1, p=p, seed=29, realization=0, step0=step)
+        xb = np.abs(np.roll(out[:, :, 0], -1, axis=1)) < 0.5   # x-link owned by (x, y) broken
+        horiz += int(np.sum(xb & np.roll(xb, -1, axis=1)))
+        vert += int(np.sum(xb[0::2] & xb[1::2]))
+    q = p * p
+    for count, n in ((horiz, Lx * Ly * T), (vert, Lx * Ly * T // 2)):
+        assert abs(count / n - q) <= 5 * np.sqrt(q * (1 - q) / n)
+
+
 def test_norm_kept_and_spreading_slowed():
     """Broken links keep the walk unitary; averaged over realizations the
     spreading is slower than the ballistic (1 - 1/sqrt 2) t^2 of the Hadamard walk."""
