@@ -434,7 +434,12 @@ class Batch:
         _bcheck(self._lib.walk_batch_binned(self.h, b.ctypes.data, 0))
         return b
 
-    def probabilities(self) -> list:
+    def probabilities(self, out=None) -> list | None:
+        """Every walk's P(x), walk after walk: a list of host arrays, or into
+        `out` (a device tensor of sum(N) float64)."""
+        if out is not None:
+            _bcheck(self._lib.walk_batch_probabilities(self.h, _ptr_of(out), 1))
+            return None
         flat = np.empty(int(self.N.sum()), dtype=np.float64)
         _bcheck(self._lib.walk_batch_probabilities(self.h, flat.ctypes.data, 0))
         return np.split(flat, np.cumsum(self.N)[:-1])

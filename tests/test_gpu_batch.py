@@ -171,3 +171,32 @@ def test_batch_renormalisation_c64():
     for i in range(N.size):
         ref = _oracle_P(N[i], T[i], p["angles"][i], p["psi0"][i], x0[i])
         assert np.max(np.abs(res[0][1][i] - ref)) <= 2e-5, i
+
+
+def test_batch_ragged_rings_full_size():
+    """The full ragged workload in the benchmark's launch (4096 rings, N odd in
+    [1001, 999999], T in [256, N/2], PCG64 seed 4, complex64, 512 bins): every
+    walk's norm and second moment; P and the bins of every walk with N < 1e4
+    against the oracle."""
+    import torch
+    p = inputs.ragged_ring_batch(4, 4096)
+    N, T = p["N"], p["T"]
+    b = qwalk.Batch(N, T, p["angles"], p["psi0"], prec=qwalk.QW_C64, nbins=512, keep_probabilities=True)
+    b.run()
+    mom = b.moments()
+    assert np.max(np.abs(mom[:, 0] - 1.0)) <= 1e-5
+    lim = 1.0 - np.abs(np.sin(p["angles"][:, 0]))
+    assert np.max(np.abs(mom[:, 2] / T.astype(np.float64) ** 2 - lim)) <= 2e-3
+    bins = b.binned()
+    flat = torch.empty(int(N.sum()), dtype=torch.float64, device="cuda")
+    b.probabilities(out=flat)
+    torch.cuda.synchronize()
+    b.destroy()
+    offs = np.concatenate([[0], np.cumsum(N)])
+    small = np.nonzero(N < 10000)[0]
+    assert small.size >= 10
+    for i in small:
+        Pi = flat[offs[i]:offs[i + 1]].cpu().numpy()
+        ref = _oracle_P(N[i], T[i], p["angles"][i], p["psi0"][i], N[i] // 2)
+        assert np.max(np.abs(Pi - ref)) <= 2e-5, i
+        assert np.max(np.abs(bins[i] - oracle.bin_ring(ref, int(N[i] // 2), 512))) <= 2e-5 + 1e-6, i

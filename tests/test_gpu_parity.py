@@ -342,6 +342,51 @@ def test_grover_4096_t2048_properties(prec):
     assert np.all(P[(xx + yy - cfg["T"]) % 2 != 0] == 0.0)
 
 
+def test_hh_16384_diagonal_factorises_full_size():
+    """The 16384^2, T = 4096, complex64 H(x)H configuration on the diagonal table:
+    there a product start a (x) b stays a product of two 1D Hadamard walks (c = 2j + k,
+    j moving x by (-1)^j and k moving y by (-1)^k), so every P(x, y) is P_a(x) P_b(y)
+    of two oracle ring walks; compared on all 2^28 sites."""
+    import torch
+    cfg = inputs.config("hh2d")
+    ext, T, x0 = cfg["extent"], cfg["T"], cfg["x0"]
+    rng = np.random.Generator(np.random.PCG64(33))
+    a, b = inputs.haar_state(rng, 2), inputs.haar_state(rng, 2)
+    w = qwalk.Walk(ext, inputs.DIAG, qwalk.HADAMARD2, np.kron(a, b), x0, prec=qwalk.QW_C64)
+    w.step(T)
+    P = torch.empty((ext[1], ext[0]), dtype=torch.float64, device="cuda")
+    w.probabilities(out=P)
+    n = w.norm()
+    w.destroy()
+    H = oracle.coin(oracle.HADAMARD, 2)
+    px = oracle.prob(oracle.walk(ext[0], 1, inputs.RING, H, (x0[0], 0), a, T))[0]
+    py = oracle.prob(oracle.walk(ext[1], 1, inputs.RING, H, (x0[1], 0), b, T))[0]
+    ref = torch.outer(torch.from_numpy(py).cuda(), torch.from_numpy(px).cuda())
+    assert torch.max(torch.abs(P - ref)).item() <= TOL32_P
+    assert abs(n - 1.0) <= 1e-5
+
+
+def test_hh_16384_properties():
+    """The benchmark's 16384^2 H(x)H walk (pair table, Haar start, complex64):
+    norm, nothing outside the light-cone box, and the site parity of a walk that
+    moves one coordinate by one every step."""
+    import torch
+    cfg = inputs.config("hh2d")
+    ext, T, x0 = cfg["extent"], cfg["T"], cfg["x0"]
+    w = qwalk.Walk(ext, cfg["disp"], qwalk.HADAMARD2, cfg["psi0"], x0, prec=qwalk.QW_C64)
+    w.step(T)
+    P = torch.empty((ext[1], ext[0]), dtype=torch.float64, device="cuda")
+    w.probabilities(out=P)
+    n = w.norm()
+    w.destroy()
+    assert abs(n - 1.0) <= 1e-5
+    yy = torch.arange(ext[1], device="cuda").view(-1, 1) - x0[1]
+    xx = torch.arange(ext[0], device="cuda").view(1, -1) - x0[0]
+    outside = (torch.abs(xx) + torch.abs(yy) > T) | ((xx + yy - T) % 2 != 0)
+    assert torch.count_nonzero(P[outside]).item() == 0
+    assert abs(torch.sum(P[~outside]).item() - 1.0) <= 1e-5
+
+
 @pytest.mark.parametrize("name", ["fourier2d_diag", "fourier2d_natural"])
 def test_fourier_workloads_full_size(name):
     """The paper's 2D workload shape (Fourier coin, diagonal and natural
