@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--depth", type=int, default=0, help="steps per launch (0 = library default)")
     ap.add_argument("--prefetch", type=int, default=0, help="torus kernel: rows requested ahead (0 = default)")
     ap.add_argument("--waves", type=int, default=0, help="torus kernel: waves per launch (0 = default)")
+    ap.add_argument("--block-order", type=int, default=0, choices=(0, 1, 2),
+                    help="torus kernel: block order 0 = library default, 1 = linear, 2 = XCD-aware")
     ap.add_argument("--broken-links", type=float, default=0.0, metavar="P",
                     help="random broken links: each link breaks with probability P at every step")
     ap.add_argument("--cpu-sample-steps", type=int, default=900)
@@ -470,8 +472,9 @@ def main():
     d = len(disp)
 
     w = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=prec)
-    if args.depth or args.prefetch or args.waves:
-        w.set_options(block_depth=args.depth, prefetch_rows=args.prefetch, stream_waves=args.waves)
+    if args.depth or args.prefetch or args.waves or args.block_order:
+        w.set_options(block_depth=args.depth, prefetch_rows=args.prefetch, stream_waves=args.waves,
+                      block_order=args.block_order)
     if args.broken_links > 0.0:
         w.set_broken_links(args.broken_links, seed=1, realization=0)
     P = torch.empty(V, dtype=torch.float64, device="cuda")

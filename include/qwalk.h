@@ -92,7 +92,7 @@ typedef struct {
 
 /* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
  * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
- * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3). */
+ * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3), stream_waves 0, block_order 0. */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
                               or 2, 4, 8, 16 (temporal blocking); auto with broken links
@@ -109,7 +109,11 @@ typedef struct {
     int32_t stream_waves;  /* torus streaming kernel: target waves per launch (rows are split
                               into segments of at least 4 K rows to reach it); 0 = default
                               (16384 for QW_C128, 4096 for QW_C64) */
-    int32_t reserved;
+    int32_t block_order;   /* torus streaming kernel: 1 = linear; 2 = XCD-aware (the blocks
+                              the hardware deals to one XCD take neighbouring strips, which
+                              share halo columns in that XCD's L2); 0 = auto: XCD-aware for
+                              QW_C128 (HBM-bound, 6 % faster on the 4096^2 torus), linear for
+                              QW_C64 (bound by its arithmetic at K = 16, 3 % faster) */
 } qw_options;
 
 /* Step kernels, as reported by walk_profile. */

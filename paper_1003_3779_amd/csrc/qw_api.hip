@@ -353,7 +353,8 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
                "ring tile kernel");
     else
     {
-        const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves};
+        const int linear = w->opt.block_order == 1 || (w->opt.block_order == 0 && w->prec == C64);
+        const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
         QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
                                w->stream, &li, links, w->t),
                "2D streaming kernel");
@@ -597,6 +598,7 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     w->opt.profile = 0;
     w->opt.prefetch_rows = 0;
     w->opt.stream_waves = 0;
+    w->opt.block_order = 0;
     for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
     set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
@@ -870,6 +872,8 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
     }
     if (o->stream_waves < 0 || o->stream_waves > (1 << 20))
         return fail(QW_EINVAL, "stream_waves must be in [0, 2^20] (got %d)", o->stream_waves);
+    if (o->block_order < 0 || o->block_order > 2)
+        return fail(QW_EINVAL, "block_order must be 0, 1 or 2 (got %d)", o->block_order);
     w->opt = *o;
     w->since_check = 0;
     return QW_OK;

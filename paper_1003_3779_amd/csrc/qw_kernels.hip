@@ -406,13 +406,23 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
 template <typename R, int K, int M, int TABLE, int COIN, int PD, bool RB = false>
 __global__ __launch_bounds__(256) void k_stream2d(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
                                                   Geom g, Box b, int seg_rows, int nstrips, CoinR<R> C,
-                                                  StreamLinks SL) {
+                                                  StreamLinks SL, int xcd_order) {
     static_assert(PD == 1 || PD == 3, "the stream loop is unrolled by 3: read-ahead 1 or 3 rows");
     constexpr int TW = 64 * M - 2 * K;
     const int lane = threadIdx.x & 63;
+    // XCD-aware order: the hardware deals blocks to the 8 XCDs in turn (block b to
+    // XCD b mod 8); block b takes the (b / 8)-th of a contiguous range of blocks
+    // owned by its XCD, so the strips that run side by side on one XCD are
+    // neighbours and read each other's halo columns from that XCD's L2 (a
+    // bijection on [0, gridDim.x) for any grid size)
+    int lb = blockIdx.x;
+    if (xcd_order) {
+        const int nb = gridDim.x, xcd = lb & 7, i = lb >> 3, per = nb >> 3, rem = nb & 7;
+        lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + i;
+    }
     // the wave index is the same in every lane: kept in scalar registers, so are
     // the row indices derived from it
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
     const int strip = wave % nstrips, seg = wave / nstrips;
     const int r0 = seg * seg_rows;  // first output row offset of this segment
     if (r0 >= b.wy) return;         // wave-uniform exit; no barriers in this kernel
@@ -894,11 +904,13 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
         // broken links: one read-ahead row (the generator's registers take the place of the others)
         if constexpr (PD == 1)
             hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, 1, true>), dim3((unsigned)blocks), dim3(256), 0, s,
-                               (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), *sl);
+                               (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), *sl,
+                               tu.linear ? 0 : 1);
         return;
     }
     hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), StreamLinks{});
+                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), StreamLinks{},
+                       tu.linear ? 0 : 1);
 }
 
 template <typename R, int K, int M, int TABLE, int PD>

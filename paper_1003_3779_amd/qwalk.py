@@ -68,7 +68,7 @@ class Options(ctypes.Structure):
     _fields_ = [("block_depth", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double),
                 ("profile", ctypes.c_int32), ("prefetch_rows", ctypes.c_int32),
-                ("stream_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("stream_waves", ctypes.c_int32), ("block_order", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -330,8 +330,10 @@ class Walk:
     def set_options(self, block_depth: int | None = None, window: int | None = None,
                     renorm_every: int | None = None, renorm_tol: float | None = None,
                     profile: int | None = None, prefetch_rows: int | None = None,
-                    stream_waves: int | None = None):
+                    stream_waves: int | None = None, block_order: int | None = None):
         o = self.get_options()
+        if block_order is not None:
+            o.block_order = int(block_order)
         if stream_waves is not None:
             o.stream_waves = int(stream_waves)
         if prefetch_rows is not None:

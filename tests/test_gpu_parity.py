@@ -209,9 +209,10 @@ def test_torus_blocked_equals_unblocked_bitwise():
 @pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
 @pytest.mark.parametrize("table", ["PAIR", "EQ8", "DIAG"])
 def test_torus_prefetch_depth_is_bitwise_neutral(prec, table):
-    """The torus kernel's read-ahead (1 or 3 rows) and its segment length
-    (waves per launch) change only when loads are issued and how rows are
-    split: every block depth gives the same amplitudes bit for bit."""
+    """The torus kernel's read-ahead (1 or 3 rows), its segment length (waves
+    per launch) and its block order (XCD-aware or linear) change only when loads
+    are issued and which wave takes which strip: every block depth gives the same
+    amplitudes bit for bit."""
     disp = getattr(inputs, table)
     rng = np.random.default_rng(len(table) * 10 + prec)
     U = inputs.haar_unitary(rng, 4)
@@ -220,9 +221,9 @@ def test_torus_prefetch_depth_is_bitwise_neutral(prec, table):
     depths = (4, 8) if prec == qwalk.QW_C128 else (4, 8, 16)
     for depth in depths:
         res = []
-        for pd, waves in ((1, 0), (3, 0), (3, 37), (1, 5000)):
+        for pd, waves, order in ((1, 0, 0), (3, 0, 2), (3, 37, 1), (1, 5000, 2), (3, 5000, 1), (3, 9, 2)):
             _, psi, _, _ = _run_gpu(ext, disp, qwalk.DENSE, psi0, x0, T, prec, dense=U, block_depth=depth,
-                                    prefetch_rows=pd, stream_waves=waves, renorm_every=0)
+                                    prefetch_rows=pd, stream_waves=waves, block_order=order, renorm_every=0)
             res.append(psi)
         for r in res[1:]:
             assert np.array_equal(res[0], r), depth
