@@ -95,8 +95,11 @@ typedef struct {
  * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3), stream_waves 0, block_order 0. */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
-                              or 2, 4, 8, 16 (temporal blocking); auto with broken links
-                              or walls on a torus: 4 */
+                              or 2, 4, 8, 12, 16 (temporal blocking; a depth a kernel lacks
+                              runs as the largest smaller one it has: rings 4, 8, 16; tori
+                              4, 8 in QW_C128 and 4, 8, 12, 16 in QW_C64); the steps left
+                              after the last full block run at the largest smaller depth;
+                              auto with broken links or walls on a torus: 4 */
     int32_t window;        /* 1: update only the light cone of the start site (exact, the
                               rest is zero); 0: sweep the whole lattice every step */
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
@@ -109,11 +112,10 @@ typedef struct {
     int32_t stream_waves;  /* torus streaming kernel: target waves per launch (rows are split
                               into segments of at least 4 K rows to reach it); 0 = default
                               (16384 for QW_C128, 4096 for QW_C64) */
-    int32_t block_order;   /* torus streaming kernel: 1 = linear; 2 = XCD-aware (the blocks
+    int32_t block_order;   /* torus streaming kernel: 0 (default) or 2 = XCD-aware (the blocks
                               the hardware deals to one XCD take neighbouring strips, which
-                              share halo columns in that XCD's L2); 0 = auto: XCD-aware for
-                              QW_C128 (HBM-bound, 6 % faster on the 4096^2 torus), linear for
-                              QW_C64 (bound by its arithmetic at K = 16, 3 % faster) */
+                              share halo columns in that XCD's L2; 6 % faster on the 4096^2
+                              QW_C128 torus); 1 = linear */
 } qw_options;
 
 /* Step kernels, as reported by walk_profile. */

@@ -278,11 +278,22 @@ int64_t box_sites(const Box &b) { return (int64_t)b.wx * (int64_t)b.wy; }
 void *cur_buf(qw_walk *w) { return w->buf[w->cur]; }
 void *oth_buf(qw_walk *w) { return w->buf[1 - w->cur]; }
 
+// the largest blocked depth <= k that the ring tile kernel (ring) or the torus
+// stream kernel takes for this walk; 1 when there is none
+int fit_depth(const qw_walk *w, int k, bool ring) {
+    static const int ks[] = {16, 12, 8, 4};
+    for (int kk : ks)
+        if (kk <= k && (ring ? kk != 12 : stream2d_supported(w->prec, w->table, kk))) return kk;
+    return 1;
+}
+
 int default_depth(const qw_walk *w) {
     if (w->dim == 1) return 16;
-    // torus: complex128 fits 8 levels in registers; complex64 16 (measured on
-    // the 4096^2 Grover walk: 16 is ~3% faster than 8 in complex64)
-    return w->prec == C64 ? 16 : 8;
+    // torus: complex128 fits 8 levels in registers; complex64 12, which keeps two
+    // waves per SIMD where 16 keeps one and halves the wasted halo lanes of 16
+    // (measured: 4096^2 Grover 27.3 ms per walk at K = 12, 31.5 at 16, 32.1 at 8;
+    // 16384^2 H(x)H 190 ms at 12, 241 at 16)
+    return w->prec == C64 ? 12 : 8;
 }
 
 hipEvent_t take_event(qw_walk *w) {
@@ -353,7 +364,7 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
                "ring tile kernel");
     else
     {
-        const int linear = w->opt.block_order == 1 || (w->opt.block_order == 0 && w->prec == C64);
+        const int linear = w->opt.block_order == 1;
         const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
         QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
                                w->stream, &li, links, w->t),
@@ -432,17 +443,18 @@ int run_forward(qw_walk *w, int64_t n) {
         // and 16 drop to one; measured on the 4096^2 torus: c128 109 ms per walk at
         // K = 4, 174 ms at K = 8; c64 69 ms at K = 4, 101 ms at K = 8)
         const int depth = w->opt.block_depth ? w->opt.block_depth : 4;
-        if (w->dim == 2 && depth > 1 && w->g.Lx >= 64 && stream2d_supported(w->prec, w->table, depth)) {
+        if (w->dim == 2 && depth > 1 && w->g.Lx >= 64) {
             Links L = w->rbl;
-            while (left >= depth) {
-                int rc = stepK(w, depth, false, &L);
-                if (rc) {
-                    w->t = t0;
-                    return rc;
+            // full blocks, then the largest supported smaller depths for what is left
+            for (int k = fit_depth(w, depth, false); k > 1 && left > 0; k = fit_depth(w, k - 1, false))
+                for (; left >= k; left -= k) {
+                    int rc = stepK(w, k, false, &L);
+                    if (rc) {
+                        w->t = t0;
+                        return rc;
+                    }
+                    w->t += k;
                 }
-                w->t += depth;
-                left -= depth;
-            }
         }
         for (; left > 0; --left) {
             int rc = step1_rbl(w);
@@ -468,17 +480,18 @@ int run_forward(qw_walk *w, int64_t n) {
         w->updates += (int64_t)w->g.Lx * w->d * n;
         return QW_OK;
     }
-    const bool ring_blocked = w->dim == 1 && w->ring_std && depth > 1 && w->g.Lx >= 512 &&
-                              (depth == 4 || depth == 8 || depth == 16);
-    const bool torus_blocked = w->dim == 2 && depth > 1 && w->g.Lx >= 64 &&
-                               stream2d_supported(w->prec, w->table, depth);
+    const bool ring_blocked = w->dim == 1 && w->ring_std && w->g.Lx >= 512;
+    const bool torus_blocked = w->dim == 2 && w->g.Lx >= 64;
     int64_t left = n;
-    if (ring_blocked || torus_blocked) {
-        while (left >= depth) {
-            int rc = stepK(w, depth, ring_blocked);
-            if (rc) return rc;
-            left -= depth;
-        }
+    if ((ring_blocked || torus_blocked) && depth > 1) {
+        // full blocks of the chosen depth, then the largest supported smaller
+        // depths for what is left (e.g. 64 steps between norm checks at K = 12:
+        // five blocks of 12 and one of 4)
+        for (int k = fit_depth(w, depth, ring_blocked); k > 1 && left > 0; k = fit_depth(w, k - 1, ring_blocked))
+            for (; left >= k; left -= k) {
+                int rc = stepK(w, k, ring_blocked);
+                if (rc) return rc;
+            }
     }
     while (left > 0) {
         int rc = step1(w);
@@ -859,8 +872,8 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
     if (!w) return fail(QW_EINVAL, "walk handle is NULL");
     if (!o) return fail(QW_EINVAL, "options pointer is NULL");
     const int k = o->block_depth;
-    if (!(k == 0 || k == 1 || k == 2 || k == 4 || k == 8 || k == 16))
-        return fail(QW_EINVAL, "block_depth must be 0, 1, 2, 4, 8 or 16 (got %d)", k);
+    if (!(k == 0 || k == 1 || k == 2 || k == 4 || k == 8 || k == 12 || k == 16))
+        return fail(QW_EINVAL, "block_depth must be 0, 1, 2, 4, 8, 12 or 16 (got %d)", k);
     if (o->window != 0 && o->window != 1) return fail(QW_EINVAL, "window must be 0 or 1");
     if (o->renorm_every < 0) return fail(QW_EINVAL, "renorm_every must be >= 0");
     if (!(o->renorm_tol >= 0.0)) return fail(QW_EINVAL, "renorm_tol must be >= 0");

@@ -944,7 +944,7 @@ static bool stream_pd(int table, int coin_impl, const void *in, void *out, const
 bool stream2d_supported(int prec, int table, int K) {
     if (table == TABLE_OTHER) return false;
     if (prec == C128) return K == 4 || K == 8;
-    return K == 4 || K == 8 || K == 16;
+    return K == 4 || K == 8 || K == 12 || K == 16;
 }
 
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
@@ -968,6 +968,7 @@ hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, v
     } else {
         if (K == 4) ok = stream_pd<float, 4, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
         else if (K == 8) ok = stream_pd<float, 8, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
+        else if (K == 12) ok = stream_pd<float, 12, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
         else ok = stream_pd<float, 16, 1>(table, coin_impl, in, out, g, b, C, tu, s, info, slp);
     }
     if (!ok) return hipErrorInvalidValue;

@@ -165,7 +165,7 @@ def test_torus_c128(table, coin_name, kind, okind, depth):
     assert abs(n - 1.0) <= TOL64
 
 
-@pytest.mark.parametrize("depth", [1, 4, 8, 16])
+@pytest.mark.parametrize("depth", [1, 4, 8, 12, 16])
 @pytest.mark.parametrize("coin_name,kind,okind", TORUS_COINS)
 def test_torus_c64(coin_name, kind, okind, depth):
     rng = np.random.default_rng(depth * 31 + kind)
@@ -194,16 +194,21 @@ def test_torus_small_and_degenerate():
 
 
 def test_torus_blocked_equals_unblocked_bitwise():
+    """Every block depth (with remainders run at the largest smaller depth) and
+    both window modes give the same amplitudes bit for bit."""
     rng = np.random.default_rng(77)
     psi0 = inputs.haar_state(rng, 4)
-    for kind in (qwalk.GROVER, qwalk.HADAMARD2):
-        res = []
-        for depth, window in ((1, 1), (1, 0), (4, 1), (8, 1), (8, 0)):
-            _, psi, _, _ = _run_gpu((200, 150), inputs.PAIR, kind, psi0, (10, 140), 83, qwalk.QW_C128,
-                                    block_depth=depth, window=window)
-            res.append(psi)
-        for r in res[1:]:
-            assert np.array_equal(r, res[0])
+    for prec, depths in ((qwalk.QW_C128, (4, 8)), (qwalk.QW_C64, (4, 8, 12, 16))):
+        for kind in (qwalk.GROVER, qwalk.HADAMARD2):
+            res = []
+            for depth, window in ((1, 1), (1, 0)) + tuple((k, 1) for k in depths) + ((depths[-1], 0),):
+                # 83 steps: at K = 12 six blocks, one of 8 and three single steps; the c64
+                # norm check every 64 steps splits them further
+                _, psi, _, _ = _run_gpu((200, 150), inputs.PAIR, kind, psi0, (10, 140), 83, prec,
+                                        block_depth=depth, window=window)
+                res.append(psi)
+            for r in res[1:]:
+                assert np.array_equal(r, res[0])
 
 
 @pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
@@ -218,7 +223,7 @@ def test_torus_prefetch_depth_is_bitwise_neutral(prec, table):
     U = inputs.haar_unitary(rng, 4)
     psi0 = inputs.haar_state(rng, 4)
     ext, x0, T = (211, 90), (100, 7), 97          # ragged strips and segments, wraps in y
-    depths = (4, 8) if prec == qwalk.QW_C128 else (4, 8, 16)
+    depths = (4, 8) if prec == qwalk.QW_C128 else (4, 8, 12, 16)
     for depth in depths:
         res = []
         for pd, waves, order in ((1, 0, 0), (3, 0, 2), (3, 37, 1), (1, 5000, 2), (3, 5000, 1), (3, 9, 2)):
