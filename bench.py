@@ -123,6 +123,19 @@ def copy_reference(nbytes: int):
           flush=True)
 
 
+FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.6
+FP32_PUBLISHED_PEAK_TFLOPS = 157.3
+
+
+def alu_roofline(flops_per_launch: float, launch_ms: float) -> dict:
+    achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "batch", "achieved": round(achieved, 2),
+            "peak": round(FP32_UNPACKED_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(launch_ms, 3), "flops_per_launch": flops_per_launch,
+            "frac_of_published_fp32_peak": round(achieved / FP32_PUBLISHED_PEAK_TFLOPS, 4)}
+
+
 def ragged_rings(args):
     """Independent rings, N odd uniform in [1001, nmax], T uniform in [256, N/2],
     SU(2) coins with theta ~ U(0, pi), phi, chi ~ U(0, 2 pi), Haar start coin
@@ -162,6 +175,11 @@ def ragged_rings(args):
         "kernel_ms": ms, "grid": info.grid, "whole_ring_walks": info.whole_ring_walks,
         "tiled_variant_per_bucket": [[info.bucket_tile_sites[k], info.bucket_depth[k]] for k in range(3)],
         "est_updates_per_run": info.est_updates,
+        # the batch kernel is bound by its fp32 arithmetic: per site and step the
+        # rotation coin, factored as f [[1, t], [-t, 1]], costs 4 FMAs (8 flops),
+        # 4 per site*coin update; peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
+        # 2.4 GHz for unpacked fp32 FMAs (packed fp32 is off in this build)
+        "roofline": alu_roofline(info.est_updates * 4.0, float(np.median(ms))),
         "norm_error_max": float(np.max(np.abs(mom[:, 0] - 1.0))),
         "second_moment_vs_limit_max": float(np.max(np.abs(m2 - lim))),
     }

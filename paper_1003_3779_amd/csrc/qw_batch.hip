@@ -47,6 +47,8 @@ struct WalkDesc {
     int32_t m, rot;         // rot = 1: the walk runs in the rotation frame (see walk_batch_create)
     int64_t p_off;          // offset of this walk's P in the full-distribution output
     double rc, rs;          // rotation coin [[rc, rs], [-rs, rc]] (rot = 1)
+    double rt, rf;          // the same as rf [[1, rt], [-rt, 1]] (rswap = 0) or rf [[rt, 1], [-1, rt]]
+    int32_t rswap, pad;     //   (rswap = 1), |rt| <= 1: the tiled path's coin
     double cre[4], cim[4];  // SU(2) coin, row-major (rot = 0)
     double pre[2], pim[2];  // start coin state (in the rotation frame when rot = 1)
 };
@@ -80,6 +82,10 @@ __device__ __forceinline__ double sum_waves(const double *part) {
 template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, CoinRot<R> &cn) {
     cn.c = (R)w.rc;
     cn.s = (R)w.rs;
+}
+template <typename R, bool SWAP> __device__ __forceinline__ void load_coin(const WalkDesc &w, CoinRotS<R, SWAP> &cn) {
+    cn.t = (R)w.rt;
+    cn.f = w.rf;
 }
 template <typename R> __device__ __forceinline__ void load_coin(const WalkDesc &w, Coin2<R> &cn) {
     cn.c00r = (R)w.cre[0]; cn.c00i = (R)w.cim[0];
@@ -265,6 +271,26 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
     }
 }
 
+// the factor by which k steps of the coin leave the state below the true one
+template <typename CN> struct Factored { static constexpr bool value = false; };
+template <typename R, bool SWAP> struct Factored<CoinRotS<R, SWAP>> { static constexpr bool value = true; };
+template <typename CN> __device__ __forceinline__ double block_factor(const CN &, int) { return 1.0; }
+template <typename R, bool SWAP>
+__device__ __forceinline__ double block_factor(const CoinRotS<R, SWAP> &cn, int k) {
+    double f = 1.0;
+    for (int i = 0; i < k; ++i) f *= cn.f;
+    return f;
+}
+
+// The factored coin's state is multiplied back by f^16 after every 16 steps of
+// the walk (global steps 16, 32, ...: every block depth is a multiple of 16, so
+// all tile variants round alike); a last block of k steps leaves f^(k mod 16)
+// pending, applied by the next reads.
+constexpr int kFactorEvery = 16;
+static_assert(kCfgK[0] % kFactorEvery == 0 && kCfgK[1] % kFactorEvery == 0 && kCfgK[2] % kFactorEvery == 0 &&
+                  kCfgK[3] % kFactorEvery == 0,
+              "every tiled block depth is a multiple of the factor period");
+
 // ---------------------------------------------------------------- tiled ring
 template <typename R, int MT, typename CN>
 __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, const int K, double *s_bins,
@@ -274,6 +300,7 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     cv<R> *const base = (cv<R> *)A.slots + (int64_t)blockIdx.x * 4 * se;  // [buffer][plane][site]
     CN cn;
     load_coin<R>(w, cn);
+    const R f16 = (R)block_factor(cn, kFactorEvery);
     // zero both buffers over the region the walk can reach (cone plus halo)
     const int64_t reach = (int64_t)w.T + K + 2;
     const int zw = (int)std::min<int64_t>(N, 2 * reach + 1);
@@ -302,7 +329,7 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int t = 0;
     int npar = 0;
-    R sc = (R)1;  // pending renormalisation of the current buffer, applied as it is read
+    R sc = (R)1;  // pending scale of the current buffer (coin factor, renormalisation), applied as it is read
     double nacc = 0.0;
     while (t < w.T) {
         const int k = (w.T - t) >= K ? K : w.T - t;  // the last block may be shorter
@@ -324,7 +351,20 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                     a0[m] = cscale<R>(i0[x], sc);
                     a1[m] = cscale<R>(i1[x], sc);
                 }
-                ring_tile_steps_n<R, MT, CN>(a0, a1, cn, k);
+                if constexpr (Factored<CN>::value) {
+                    int left = k;
+                    for (; left >= kFactorEvery; left -= kFactorEvery) {
+                        ring_tile_steps_n<R, MT, CN>(a0, a1, cn, kFactorEvery);
+#pragma unroll
+                        for (int m = 0; m < MT; ++m) {
+                            a0[m] = cscale<R>(a0[m], f16);
+                            a1[m] = cscale<R>(a1[m], f16);
+                        }
+                    }
+                    if (left > 0) ring_tile_steps_n<R, MT, CN>(a0, a1, cn, left);
+                } else {
+                    ring_tile_steps_n<R, MT, CN>(a0, a1, cn, k);
+                }
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
                     const int q = lane * MT + m;
@@ -338,17 +378,20 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                 }
             }
         }
+        // the block's output is the state divided by fk (factored coin)
+        const double fk = block_factor(cn, k % kFactorEvery);
         if (A.renorm_every > 0) {
             // fp64 norm of the block's output, in fixed wave order; the rescale
             // (if any) is applied by the next reads of this buffer
             const double part = wave_sum64(nacc);
             if (lane == 0) s_norm[npar][wave] = part;
             __syncthreads();
-            const double nrm = sum_waves(s_norm[npar]);
+            const double nrm = sum_waves(s_norm[npar]) * fk * fk;
             npar ^= 1;
-            sc = fabs(nrm - 1.0) > A.renorm_tol ? (R)(1.0 / sqrt(nrm)) : (R)1;
+            sc = (R)(fabs(nrm - 1.0) > A.renorm_tol ? fk / sqrt(nrm) : fk);
         } else {
             __syncthreads();
+            sc = (R)fk;
         }
         nacc = 0.0;
         cur ^= 1;
@@ -417,10 +460,13 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
             // a walk whose light cone wraps the ring: full SU(2) coin, one variant
             walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
         } else if (kCfgMT[w.cfg] == 8) {
-            walk_tiled<R, 8, CoinRot<R>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            if (w.rswap) walk_tiled<R, 8, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else walk_tiled<R, 8, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         } else {
             // 16 sites per lane in complex64; complex128 keeps 8 (register budget)
-            walk_tiled<R, (sizeof(R) == 8 ? 8 : 16), CoinRot<R>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            constexpr int MT = sizeof(R) == 8 ? 8 : 16;
+            if (w.rswap) walk_tiled<R, MT, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else walk_tiled<R, MT, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         }
         finish_walk<R>(A, wi, acc, s_bins, s_red);
     }
@@ -732,6 +778,10 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         w.cre[3] = cos(ph) * ct;  w.cim[3] = -sin(ph) * ct;
         w.rc = ct;
         w.rs = st;
+        w.rswap = fabs(st) > fabs(ct) ? 1 : 0;
+        w.rf = w.rswap ? st : ct;
+        w.rt = w.rswap ? ct / st : st / ct;
+        w.pad = 0;
         w.rot = 2 * T[i] < N[i] ? 1 : 0;
         const double dphi = w.rot ? ch - ph : 0.0, cd = cos(dphi), sd = sin(dphi);
         w.pre[0] = psi0[4 * i];

@@ -176,6 +176,29 @@ template <typename R> struct CoinRot {
     }
 };
 
+// The same rotation with its larger entry f = c (SWAP = false) or f = s
+// (SWAP = true) factored out, |t| <= 1: [[c, s], [-s, c]] = f [[1, t], [-t, 1]]
+// with t = s / c, or f [[t, 1], [-1, t]] with t = c / s.  One FMA per real
+// output; the result of each step is the true one divided by f, and the caller
+// multiplies by f^k after k steps (the factor grows by at most sqrt(2) per step).
+template <typename R, bool SWAP> struct CoinRotS {
+    R t;
+    double f;
+    __device__ __forceinline__ void apply(cv<R> g0, cv<R> g1, cv<R> &o0, cv<R> &o1) const {
+        if constexpr (!SWAP) {
+            o0.x = fmaR(t, g1.x, g0.x);
+            o0.y = fmaR(t, g1.y, g0.y);
+            o1.x = fmaR(-t, g0.x, g1.x);
+            o1.y = fmaR(-t, g0.y, g1.y);
+        } else {
+            o0.x = fmaR(t, g0.x, g1.x);
+            o0.y = fmaR(t, g0.y, g1.y);
+            o1.x = fmaR(t, g1.x, -g0.x);
+            o1.y = fmaR(t, g1.y, -g0.y);
+        }
+    }
+};
+
 // K steps of a ring tile held by one wave: lane l holds sites l*M .. l*M+M-1
 // of both planes; the value a lane needs from its neighbour moves one lane per
 // step.  After K steps the sites K .. 64M-K-1 are exact.  CN: Coin2 or CoinRot.
