@@ -354,16 +354,16 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                 if constexpr (Factored<CN>::value) {
                     int left = k;
                     for (; left >= kFactorEvery; left -= kFactorEvery) {
-                        ring_tile_steps_n<R, MT, CN>(a0, a1, cn, kFactorEvery);
+                        ring_tile_steps_pp<R, MT, CN>(a0, a1, cn, kFactorEvery);
 #pragma unroll
                         for (int m = 0; m < MT; ++m) {
                             a0[m] = cscale<R>(a0[m], f16);
                             a1[m] = cscale<R>(a1[m], f16);
                         }
                     }
-                    if (left > 0) ring_tile_steps_n<R, MT, CN>(a0, a1, cn, left);
+                    if (left > 0) ring_tile_steps_pp<R, MT, CN>(a0, a1, cn, left);
                 } else {
-                    ring_tile_steps_n<R, MT, CN>(a0, a1, cn, k);
+                    ring_tile_steps_pp<R, MT, CN>(a0, a1, cn, k);
                 }
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {

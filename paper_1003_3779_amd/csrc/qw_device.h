@@ -220,6 +220,41 @@ __device__ __forceinline__ void ring_tile_steps(cv<R> (&a0)[M], cv<R> (&a1)[M], 
     }
 }
 
+// One step of a ring tile from (a0, a1) into (b0, b1) (distinct registers: no
+// copies of the old values are needed).
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void ring_tile_step_to(const cv<R> (&a0)[M], const cv<R> (&a1)[M], cv<R> (&b0)[M],
+                                                  cv<R> (&b1)[M], const CN &cn) {
+    const cv<R> left = from_left<R>(a0[M - 1]);
+    const cv<R> right = from_right<R>(a1[0]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+        const cv<R> g1 = m == M - 1 ? right : a1[m == M - 1 ? m : m + 1];
+        cn.apply(g0, g1, b0[m], b1[m]);
+    }
+}
+
+// k steps of a ring tile, alternating between (a0, a1) and a second register
+// set; the result ends in (a0, a1).  The same arithmetic as ring_tile_steps_n.
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void ring_tile_steps_pp(cv<R> (&a0)[M], cv<R> (&a1)[M], const CN &cn, int k) {
+    cv<R> b0[M], b1[M];
+    int s = 0;
+    for (; s + 2 <= k; s += 2) {
+        ring_tile_step_to<R, M, CN>(a0, a1, b0, b1, cn);
+        ring_tile_step_to<R, M, CN>(b0, b1, a0, a1, cn);
+    }
+    if (s < k) {
+        ring_tile_step_to<R, M, CN>(a0, a1, b0, b1, cn);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            a0[m] = b0[m];
+            a1[m] = b1[m];
+        }
+    }
+}
+
 // As ring_tile_steps with a run-time step count k (the step loop is not
 // unrolled, so deep blocks cost no code size); sites k .. 64M-k-1 are exact.
 template <typename R, int M, typename CN>
