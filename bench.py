@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--workload", default="grover2d",
                     choices=["grover2d", "grover2d_uniform", "hh2d", "fourier2d_diag", "fourier2d_natural",
                              "fourier2d_diag_4096", "ring1d", "ragged_rings", "surrogate", "graph_torus",
-                             "graph_random"])
+                             "graph_random", "rbl_segment"])
+    ap.add_argument("--realizations", type=int, default=1024,
+                    help="rbl_segment: realizations of the broken-link walk averaged in one launch")
     ap.add_argument("--train-walks", type=int, default=1 << 18, help="surrogate: training walks")
     ap.add_argument("--eval-walks", type=int, default=65536, help="surrogate: held-out walks")
     ap.add_argument("--epochs", type=int, default=30, help="surrogate: training epochs")
@@ -134,6 +136,71 @@ def alu_roofline(flops_per_launch: float, launch_ms: float) -> dict:
             "frac": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4), "traffic": None,
             "avg_launch_ms": round(launch_ms, 3), "flops_per_launch": flops_per_launch,
             "frac_of_published_fp32_peak": round(achieved / FP32_PUBLISHED_PEAK_TFLOPS, 4)}
+
+
+def rbl_segment(args):
+    """The segment walk with random broken links (Sec. 3, Fig. 3): a Hadamard walk
+    (SU(2) with theta = pi/4, phi = chi = -pi/2, equal to H up to a global phase)
+    on a segment of 2001 sites with reflecting ends, from (|L> + i|R>)/sqrt 2 at
+    the centre, T = 1000, p = 0.1; P averaged over R realizations, all in one
+    persistent launch (one workgroup per walk), against one realization at a
+    time through the single-walk path (one step per launch)."""
+    import numpy as np
+    import torch
+
+    from paper_1003_3779_amd import inputs, qwalk
+    R, N, T, p, seed = args.realizations, 2001, 1000, 0.1, 1
+    ang = np.tile([[math.pi / 4, -math.pi / 2, -math.pi / 2]], (R, 1))
+    psi0 = np.tile(inputs.PSI0_LR, (R, 1))
+    b = qwalk.Batch([N] * R, [T] * R, ang, psi0, [N // 2] * R, prec=qwalk.QW_C128, keep_probabilities=True,
+                    walls=True, link_p=p, link_seed=seed)
+    print(f"# rbl_segment: {R} realizations of N={N}, T={T}, p={p}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        b.run()
+        b.info()
+    ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+        ms.append(b.info().last_run_ms)
+    t1 = time.perf_counter()
+    info = b.info()
+    Pavg = np.mean(np.stack(b.probabilities()), axis=0)
+    mom = b.moments()
+    b.destroy()
+    # the same walk one realization at a time through walk_step (rings run one
+    # step per launch with broken links)
+    w = qwalk.Walk((N,), inputs.RING, qwalk.SU2, inputs.PSI0_LR, (N // 2,), prec=qwalk.QW_C128,
+                   theta=math.pi / 4, phi=-math.pi / 2, chi=-math.pi / 2)
+    w.set_reflecting_walls(True)
+    single = []
+    for r in range(4):
+        w.reset(inputs.PSI0_LR, (N // 2,))
+        w.set_broken_links(p, seed, r)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        w.step(T)
+        w.norm()
+        single.append(time.perf_counter() - ts)
+    w.destroy()
+    batch_s = (t1 - t0) / args.steps
+    out = {
+        "metric": METRIC, "value": info.est_updates / batch_s, "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * batch_s, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"rbl_segment: {R} realizations, segment N={N}, T={T}, p={p}, Hadamard, c128",
+                   "parallelism": "single GPU"},
+        "realizations_per_s": R / batch_s,
+        "kernel_ms": ms,
+        "single_walk_ms_per_realization": round(1e3 * float(np.median(single[1:])), 3),
+        "speedup_vs_single_walks": round(float(np.median(single[1:])) * R / batch_s, 1),
+        "norm_error_max": float(np.max(np.abs(mom[:, 0] - 1.0))),
+        "P_avg_at_centre": float(Pavg[N // 2]),
+        "P_avg_sum": float(Pavg.sum()),
+    }
+    print(json.dumps(out), flush=True)
 
 
 def ragged_rings(args):
@@ -476,6 +543,9 @@ def main():
         return
     if args.workload == "surrogate":
         surrogate(args)
+        return
+    if args.workload == "rbl_segment":
+        rbl_segment(args)
         return
     if args.workload in ("graph_torus", "graph_random"):
         graph_bench(args)

@@ -285,6 +285,20 @@ typedef struct {
                                     cone.  0 = default: rings shorter than 2048 sites, and
                                     rings whose cone wraps (2T >= N); > 0: rings of at most
                                     max(this, 2047) sites */
+    int32_t walls;               /* 1: reflecting ends, a segment of N sites (the segment walk
+                                    of Sec. 3 and Fig. 3): the link between sites N-1 and 0 is
+                                    broken at every step */
+    int32_t reserved;
+    double link_p;               /* random broken links (Sec. 3, Eqs. (9)-(10)): each link
+                                    breaks with this probability at every step; 0 = none */
+    uint64_t link_seed;          /* generator key of the links */
+    uint64_t realization0;       /* walk i draws realization realization0 + i: a batch of R
+                                    equal walks is R realizations, to average P over.  The
+                                    draws are those of walk_set_broken_links on a ring (one
+                                    Philox4x32-10 call per site and step, word 0).  With links
+                                    or walls every walk is held whole (N <= 4608 in QW_C64,
+                                    2048 in QW_C128, else QW_EINVAL) and runs the full SU(2)
+                                    coin */
 } qw_batch_opts;
 
 typedef struct {

@@ -51,6 +51,8 @@ struct WalkDesc {
     int32_t rswap, pad;     //   (rswap = 1), |rt| <= 1: the tiled path's coin
     double cre[4], cim[4];  // SU(2) coin, row-major (rot = 0)
     double pre[2], pim[2];  // start coin state (in the rotation frame when rot = 1)
+    uint32_t realization;   // broken links: the realization this walk draws
+    int32_t pad2;
 };
 
 struct BatchArgs {
@@ -68,6 +70,10 @@ struct BatchArgs {
     int32_t renorm_every;   // whole rings: steps between fp64 norm checks (0 = never); tiled rings
                             // check after every K-step block when non-zero
     double renorm_tol;      // rescale by 1/sqrt(n) when |n - 1| > renorm_tol
+    int32_t links;          // 1: broken links and / or walls (every walk held whole, full coin)
+    int32_t walls;          // 1: the link (N-1, 0) is broken at every step
+    uint64_t link_thr;      // a link is broken when its Philox word < link_thr (0: none at random)
+    uint32_t key0, key1;    // generator key (seed)
 };
 
 // fp64 norm of per-wave partial sums: lane 0 of each wave has written its sum
@@ -171,7 +177,30 @@ template <typename R> __device__ __forceinline__ double abs2d(cv<R> v) {
 }
 
 // ---------------------------------------------------------------- whole ring
-template <typename R, int M, typename CN>
+// Broken links of a ring held whole (RB): bit i tells whether the link from site
+// j*M + i - 1 to the next site (owned by the former, the start site of a move
+// along +1) is broken in the shift pending at step s, i.e. at step s - 1
+// (none at s = 0).  One Philox4x32-10 call per owner site and step (counter:
+// site, 0, step, realization; word 0), as for a single walk on a ring.
+template <int M>
+__device__ __forceinline__ uint32_t whole_links(const WalkDesc &w, const BatchArgs &A, int j, int cnt, int s) {
+    uint32_t lk = 0;  // bit i: lk[i]
+    if (s < 1) return lk;
+#pragma unroll 1
+    for (int i = 0; i <= cnt; ++i) {
+        int owner = j * M + i - 1;
+        owner = owner < 0 ? owner + w.N : owner;
+        bool b = A.walls && owner == w.N - 1;
+        if (!b && A.link_thr != 0) {
+            const uint4 o = philox4((uint32_t)owner, 0u, (uint32_t)(s - 1), w.realization, A.key0, A.key1);
+            b = (uint64_t)o.x < A.link_thr;
+        }
+        lk |= (b ? 1u : 0u) << i;
+    }
+    return lk;
+}
+
+template <typename R, int M, typename CN, bool RB = false>
 __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A, cv<R> (*L0)[kBT], cv<R> (*L1)[kBT],
                            double *s_bins, double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
@@ -244,13 +273,20 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
         __syncthreads();
         if (active && (s == w.T || dmin <= s + 2)) {
             const cv<R> left = L0[p][jl], right = L1[p][jr];
+            uint32_t lk = 0;
+            if constexpr (RB) lk = whole_links<M>(w, A, j, cnt, s);
             if (s < w.T) {
                 // in place, ascending m: a0[m-1] is carried, a1[m+1] is still old
                 cv<R> prev = left;
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
-                    const cv<R> g0 = prev;
-                    const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                    cv<R> g0 = prev;
+                    cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                    if constexpr (RB) {
+                        // a broken link reflects: the opposite component of the site itself
+                        if ((lk >> m) & 1u) g0 = a1[m];
+                        if ((lk >> (m + 1)) & 1u) g1 = a0[m];
+                    }
                     prev = a0[m];
                     cn.apply(g0, g1, a0[m], a1[m]);
                 }
@@ -258,8 +294,12 @@ __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     if (m < cnt) {
-                        const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
-                        const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                        cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+                        cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                        if constexpr (RB) {
+                            if ((lk >> m) & 1u) g0 = a1[m];
+                            if ((lk >> (m + 1)) & 1u) g1 = a0[m];
+                        }
                         const double pr = abs2d<R>(g0) + abs2d<R>(g1);
                         const int x = j * M + m;
                         acc.add(pr, ring_offset(x, w.x0, N), N, A.nbins, s_bins);
@@ -483,7 +523,8 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
 #define QW_WHOLE_CASE(MM)                                                                                  \
         case MM:                                                                                           \
             if (MM <= MMAX) {                                                                              \
-                if (w.rot) walk_whole<R, (MM <= MMAX ? MM : 1), CoinRot<R>>(w, A, L0, L1, s_bins, s_norm, acc); \
+                if (A.links) walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>, true>(w, A, L0, L1, s_bins, s_norm, acc); \
+                else if (w.rot) walk_whole<R, (MM <= MMAX ? MM : 1), CoinRot<R>>(w, A, L0, L1, s_bins, s_norm, acc); \
                 else walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>>(w, A, L0, L1, s_bins, s_norm, acc);         \
             }                                                                                              \
             break;
@@ -607,6 +648,9 @@ struct qw_batch {
     int64_t n_tiled = 0;
     int32_t renorm_every = 0;
     double renorm_tol = 1e-7;
+    int32_t links = 0, walls = 0;  // broken links / reflecting ends
+    uint64_t link_thr = 0;
+    uint32_t key0 = 0, key1 = 0;
     WalkDesc *d_walks = nullptr;
     int32_t *d_order = nullptr;
     unsigned int *d_queue = nullptr;
@@ -661,6 +705,11 @@ BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, in
     A.P = b->keep ? b->d_P : nullptr;
     A.renorm_every = b->renorm_every;
     A.renorm_tol = b->renorm_tol;
+    A.links = b->links;
+    A.walls = b->walls;
+    A.link_thr = b->link_thr;
+    A.key0 = b->key0;
+    A.key1 = b->key1;
     return A;
 }
 
@@ -722,6 +771,12 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
     if (o.tiled_variant < 0 || o.tiled_variant > kNumCfg)
         return bfail(QW_EINVAL, "tiled_variant must be 0 (tuned) or 1..%d", kNumCfg);
     if (o.whole_max_sites < 0) return bfail(QW_EINVAL, "whole_max_sites must be >= 0");
+    if (o.walls != 0 && o.walls != 1) return bfail(QW_EINVAL, "walls must be 0 or 1 (got %d)", o.walls);
+    if (!(o.link_p >= 0.0 && o.link_p <= 1.0))
+        return bfail(QW_EINVAL, "link_p must be in [0, 1] (got %g)", o.link_p);
+    if (o.realization0 > 0xFFFFFFFFull || (uint64_t)(n - 1) > 0xFFFFFFFFull - o.realization0)
+        return bfail(QW_ERANGE, "realization0 + n - 1 must be below 2^32");
+    const bool links = o.link_p > 0.0 || o.walls != 0;
     qw_batch *b = new (std::nothrow) qw_batch();
     if (!b) return bfail(QW_ENOMEM, "host allocation failed");
     b->prec = prec;
@@ -731,6 +786,12 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
     b->use_graph = o.no_graph == 0;
     b->stream = (hipStream_t)stream;
     b->renorm_every = o.renorm_every > 0 ? o.renorm_every : (o.renorm_every < 0 ? 0 : (prec == QW_C64 ? 64 : 0));
+    b->links = links ? 1 : 0;
+    b->walls = o.walls;
+    // a link breaks when its 32-bit draw is below floor(p 2^32) (p = 1: always)
+    b->link_thr = o.link_p >= 1.0 ? (1ull << 32) : (uint64_t)floor(o.link_p * 4294967296.0);
+    b->key0 = (uint32_t)o.link_seed;
+    b->key1 = (uint32_t)(o.link_seed >> 32);
     const int mmax = prec == QW_C128 ? kMaxMC128 : kMaxMC64;
     b->walks.resize(n);
     b->p_off.resize(n);
@@ -782,7 +843,9 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         w.rf = w.rswap ? st : ct;
         w.rt = w.rswap ? ct / st : st / ct;
         w.pad = 0;
-        w.rot = 2 * T[i] < N[i] ? 1 : 0;
+        // (the rotation frame needs every component to move: not with broken links)
+        w.rot = (2 * T[i] < N[i] && !links) ? 1 : 0;
+        w.realization = (uint32_t)(o.realization0 + (uint64_t)i);
         const double dphi = w.rot ? ch - ph : 0.0, cd = cos(dphi), sd = sin(dphi);
         w.pre[0] = psi0[4 * i];
         w.pim[0] = psi0[4 * i + 1];
@@ -796,7 +859,14 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         // the ring is short or the cone wraps it (2T >= N: no cone to save).
         const int64_t m = (N[i] + kBT - 1) / kBT;
         bool whole = m <= mmax;
-        if (o.whole_max_sites > 0)
+        if (links && !whole) {
+            free_batch(b);
+            return bfail(QW_EINVAL, "walk %lld: with broken links or walls a ring must fit one workgroup "
+                         "(N <= %d; got %lld)", (long long)i, kBT * mmax, (long long)N[i]);
+        }
+        if (links) {
+            // held whole: the link draws run inside the whole-ring loop
+        } else if (o.whole_max_sites > 0)
             whole = whole && N[i] <= std::max<int64_t>(o.whole_max_sites, kMinTiledSites - 1);
         else
             whole = whole && (N[i] < kMinTiledSites || 2 * T[i] >= N[i]);

@@ -183,12 +183,12 @@ def test_ext_buffers_checked(lib):
                                ctypes.c_void_p(4096 + 8), ctypes.c_void_p(8192), ctypes.byref(h)) == qwalk.QW_EINVAL
 
 
-def _batch_create(lib, N, T, angles, psi0, nbins=0, prec=qwalk.QW_C64):
+def _batch_create(lib, N, T, angles, psi0, nbins=0, prec=qwalk.QW_C64, walls=0, link_p=0.0, realization0=0):
     N = np.ascontiguousarray(N, dtype=np.int64)
     T = np.ascontiguousarray(T, dtype=np.int64)
     a = np.ascontiguousarray(angles, dtype=np.float64)
     p = np.ascontiguousarray(psi0, dtype=np.complex128)
-    o = qwalk.BatchOpts(nbins, 0, 0, 0, 0, 0)
+    o = qwalk.BatchOpts(nbins, 0, 0, 0, 0, 0, walls, 0, link_p, 0, realization0)
     h = ctypes.c_void_p()
     rc = lib.walk_batch_create(N.size, N.ctypes.data, T.ctypes.data, a.ctypes.data, p.ctypes.data, None, prec,
                                ctypes.byref(o), None, ctypes.byref(h))
@@ -205,5 +205,15 @@ def test_batch_validation(lib):
     assert _batch_create(lib, [11], [5], ok_a, ok_p, nbins=3)[0] == qwalk.QW_EINVAL  # odd bins
     assert _batch_create(lib, [11], [5], ok_a, ok_p, nbins=4096)[0] == qwalk.QW_EINVAL
     assert _batch_create(lib, [11], [5], ok_a, ok_p, prec=9)[0] == qwalk.QW_EINVAL
+    # broken links and walls: probability in [0, 1], walls 0 / 1, rings that fit one
+    # workgroup, realizations below 2^32
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, link_p=1.5)[0] == qwalk.QW_EINVAL
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, link_p=float("nan"))[0] == qwalk.QW_EINVAL
+    assert _batch_create(lib, [11], [5], ok_a, ok_p, walls=2)[0] == qwalk.QW_EINVAL
+    rc, msg = _batch_create(lib, [4609], [5], ok_a, ok_p, link_p=0.1)
+    assert rc == qwalk.QW_EINVAL and "workgroup" in msg
+    assert _batch_create(lib, [2049], [5], ok_a, ok_p, prec=qwalk.QW_C128, walls=1)[0] == qwalk.QW_EINVAL
+    assert _batch_create(lib, [11, 11], [5, 5], ok_a * 2, ok_p * 2, link_p=0.1,
+                         realization0=2 ** 32 - 1)[0] == qwalk.QW_ERANGE
     assert lib.walk_batch_run(None) == qwalk.QW_EINVAL
     assert lib.walk_batch_destroy(None) == qwalk.QW_OK

@@ -200,3 +200,56 @@ def test_batch_ragged_rings_full_size():
         ref = _oracle_P(N[i], T[i], p["angles"][i], p["psi0"][i], N[i] // 2)
         assert np.max(np.abs(Pi - ref)) <= 2e-5, i
         assert np.max(np.abs(bins[i] - oracle.bin_ring(ref, int(N[i] // 2), 512))) <= 2e-5 + 1e-6, i
+
+
+def _oracle_rbl_P(N, T, ang, psi0, x0, p, seed, real, walls):
+    C = oracle.coin(oracle.SU2, 2, *ang)
+    psi = oracle.initial_state(int(N), 1, 2, (int(x0), 0), psi0)
+    out = oracle.evolve_rbl(psi, inputs.RING, C, int(T), p=p, seed=seed, realization=real, walls=walls)
+    return oracle.prob(out)[0]
+
+
+@pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
+@pytest.mark.parametrize("p,walls", [(0.15, False), (0.0, True), (0.3, True), (1.0, False)])
+def test_batch_broken_links_and_walls(prec, tol, p, walls):
+    """Rings held whole with random broken links and / or reflecting ends (Sec. 3,
+    Eqs. (9)-(10), Fig. 3): walk i draws realization realization0 + i; every walk's
+    P and moments against the oracle, across the whole-ring sizes (one site per
+    thread up to the register limit) and cones that reach the ends."""
+    rng = np.random.default_rng(int(p * 100) + 7 * walls + prec)
+    nmax = 2048 if prec == qwalk.QW_C128 else 4608
+    N = np.array([1, 2, 3, 7, 64, 511, 512, 513, 1001, 2047, nmax], dtype=np.int64)
+    T = np.array([3, 5, 9, 40, 100, 700, 300, 1100, 600, 900, 450], dtype=np.int64)
+    x0 = np.array([int(rng.integers(0, n)) for n in N], dtype=np.int64)
+    ang = inputs.su2_angles(rng, N.size)
+    psi0 = np.stack([inputs.haar_state(rng, 2) for _ in N])
+    seed, r0 = 2 ** 33 + 17, 5
+    b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=0, keep_probabilities=True, walls=walls,
+                    link_p=p, link_seed=seed, realization0=r0)
+    b.run()
+    Ps = b.probabilities()
+    mom = b.moments()
+    b.destroy()
+    for i in range(N.size):
+        ref = _oracle_rbl_P(N[i], T[i], ang[i], psi0[i], x0[i], p, seed, r0 + i, walls)
+        assert np.max(np.abs(Ps[i] - ref)) <= tol, (i, N[i], T[i])
+        assert abs(mom[i, 0] - 1.0) <= (1e-12 if prec == qwalk.QW_C128 else 1e-5), i
+
+
+def test_batch_realization_average():
+    """P averaged over 64 realizations in one launch equals the average of the
+    oracle's realizations; the links matter (a different seed moves P)."""
+    R, N, T, x0 = 64, 301, 150, 150
+    ang = np.tile([[0.7, 0.2, 1.1]], (R, 1))
+    psi0 = np.tile(inputs.PSI0_LR, (R, 1))
+    def avg(seed):
+        b = qwalk.Batch([N] * R, [T] * R, ang, psi0, [x0] * R, prec=qwalk.QW_C128, keep_probabilities=True,
+                        link_p=0.2, link_seed=seed, walls=True)
+        b.run()
+        P = np.mean(np.stack(b.probabilities()), axis=0)
+        b.destroy()
+        return P
+    P = avg(9)
+    ref = np.mean([_oracle_rbl_P(N, T, ang[0], psi0[0], x0, 0.2, 9, r, True) for r in range(R)], axis=0)
+    assert np.max(np.abs(P - ref)) <= 1e-12
+    assert np.max(np.abs(avg(10) - P)) > 1e-4
