@@ -215,8 +215,10 @@ int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device);
  * count from 0 at t = 0.
  * p = 0 switches the links back to intact.  Call at t = 0 (after walk_create or
  * walk_reset; walk_reset keeps the setting).  While links break, tori run K
- * steps per launch as without them, rings one step per launch;
- * walk_step_inverse is refused and walk_set_state works only at t = 0.
+ * steps per launch as without them, rings that one workgroup holds (4096 sites
+ * in QW_C128, 8192 in QW_C64) all steps in one launch, longer rings one step
+ * per launch; walk_step_inverse is refused and walk_set_state works only at
+ * t = 0.
  * QW_EINVAL: p outside [0, 1], t != 0, or a table without opposite pairs;
  * QW_ERANGE: realization >= 2^32. */
 int walk_set_broken_links(qw_walk_t w, double p, uint64_t seed, uint64_t realization);

@@ -434,8 +434,9 @@ int step1_rbl(qw_walk *w) {
 int run_forward(qw_walk *w, int64_t n) {
     if (n <= 0) return QW_OK;
     if (w->rbl_on) {
-        // tori: K steps per launch, each level drawing its step's links inside
-        // the streaming kernel; rings and the remainder: one step per launch
+        // rings held whole: all n steps in one launch; tori: K steps per launch,
+        // each level drawing its step's links inside the streaming kernel;
+        // longer rings and the remainder: one step per launch
         const int64_t t0 = w->t;
         int64_t left = n;
         // K = 4 by default: the link draws make the blocked kernel bound by its
@@ -443,6 +444,21 @@ int run_forward(qw_walk *w, int64_t n) {
         // and 16 drop to one; measured on the 4096^2 torus: c128 109 ms per walk at
         // K = 4, 174 ms at K = 8; c64 69 ms at K = 4, 101 ms at K = 8)
         const int depth = w->opt.block_depth ? w->opt.block_depth : 4;
+        if (w->dim == 1 && w->ring_std && depth > 1 && w->g.Lx <= ring_whole_max_sites(w->prec)) {
+            // the whole ring in one workgroup: all n steps in one launch, each
+            // drawing its links inside the step loop
+            const Links L = w->rbl;
+            grow_forward(w, n);
+            LaunchInfo li;
+            Timed tm(w);
+            QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li, &L, t0),
+                   "ring kernel");
+            tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n);
+            w->cur ^= 1;
+            w->launches++;
+            w->updates += (int64_t)w->g.Lx * w->d * n;
+            return QW_OK;
+        }
         if (w->dim == 2 && depth > 1 && w->g.Lx >= 64) {
             Links L = w->rbl;
             // full blocks, then the largest supported smaller depths for what is left

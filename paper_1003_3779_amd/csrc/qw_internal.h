@@ -57,9 +57,6 @@ hipError_t launch_step(int prec, int coin_impl, const void *in, void *out, const
 // one step of U^-1 over the output box; Cdag is C^dagger
 hipError_t launch_step_inverse(int prec, const void *in, void *out, const Geom &g,
                                const Box &out_box, const CoinF64 &Cdag, hipStream_t s);
-// K steps of a ring of N = g.Lx sites held whole by one workgroup
-hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
-                             const CoinF64 &C, int64_t K, hipStream_t s, LaunchInfo *info);
 int ring_whole_max_sites(int prec);
 // K steps of a ring, wave-sized register tiles over the output window box
 hipError_t launch_ring_tiles(int prec, const void *in, void *out, const Geom &g,
@@ -83,6 +80,13 @@ struct Links {
     int32_t opp[4], pos[4], pair[4];
     int32_t walls;
 };
+
+// K steps of a ring of N = g.Lx sites held whole by one workgroup; links:
+// broken links / walls (then t0 is the walk time at the launch: step s of the
+// launch applies the links of step t0 + s - 1, none at t0 + s = 0)
+hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
+                             const CoinF64 &C, int64_t K, hipStream_t s, LaunchInfo *info,
+                             const Links *links = nullptr, int64_t t0 = 0);
 
 // launch shape of the torus streaming kernel
 struct StreamTune {

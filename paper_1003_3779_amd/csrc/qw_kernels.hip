@@ -120,9 +120,16 @@ __global__ __launch_bounds__(256) void k_step_inv(const cv<R> *__restrict__ in, 
 // step each thread publishes its last component-0 value and first
 // component-1 value in LDS (double-buffered, so one barrier per step); the
 // ring closes through thread nl-1 <-> thread 0.
-template <typename R, int M>
+//
+// RB: broken links / walls.  Before the coin of step s each thread takes the
+// links its sites own at step t0 + s - 1 (bit i of lk: the link from site
+// j*M + i - 1 to the next one, owned by the former; one generator call per
+// owner site, word 0 -- the draws of k_step_rbl), and a move across a broken
+// link takes the opposite component of the site itself.
+template <typename R, int M, bool RB = false>
 __global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
-                                                     int N, int64_t ps, int64_t K, CoinR<R> C) {
+                                                     int N, int64_t ps, int64_t K, CoinR<R> C, Links L,
+                                                     int64_t t0) {
     __shared__ cv<R> L0[2][1024];
     __shared__ cv<R> L1[2][1024];
     const int j = threadIdx.x;
@@ -156,11 +163,32 @@ __global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ i
         __syncthreads();
         if (active) {
             const cv<R> left = L0[p][jl], right = L1[p][jr];
+            uint32_t lk = 0;
+            if constexpr (RB) {
+                const int64_t step = t0 + s - 1;
+                if (step >= 0) {
+#pragma unroll 1
+                    for (int i = 0; i <= cnt; ++i) {
+                        int owner = j * M + i - 1;
+                        owner = owner < 0 ? owner + N : owner;
+                        bool b = L.walls && owner == N - 1;
+                        if (!b && L.thr != 0) {
+                            const uint4 o = philox4((uint32_t)owner, 0u, (uint32_t)step, L.realization, L.key0, L.key1);
+                            b = (uint64_t)o.x < L.thr;
+                        }
+                        lk |= (b ? 1u : 0u) << i;
+                    }
+                }
+            }
             cv<R> n0[M], n1[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
-                const cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+                cv<R> g1 = (m + 1 < M && m + 1 < cnt) ? a1[m + 1 < M ? m + 1 : m] : right;
+                if constexpr (RB) {
+                    if ((lk >> m) & 1u) g0 = a1[m];
+                    if ((lk >> (m + 1)) & 1u) g1 = a0[m];
+                }
                 n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
                 n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
             }
@@ -807,15 +835,20 @@ static int ring_whole_m(int prec, int64_t N) {
 int ring_whole_max_sites(int prec) { return 1024 * (prec == C128 ? 4 : 8); }
 
 template <typename R, int M>
-static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K, hipStream_t s) {
+static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K, hipStream_t s,
+                         const Links *links, int64_t t0) {
     const int nl = (g.Lx + M - 1) / M;
     const int threads = ((nl + 63) / 64) * 64;
-    hipLaunchKernelGGL((k_ring_whole<R, M>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out, g.Lx,
-                       g.ps, K, to_coin<R>(C));
+    if (links)
+        hipLaunchKernelGGL((k_ring_whole<R, M, true>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out,
+                           g.Lx, g.ps, K, to_coin<R>(C), *links, t0);
+    else
+        hipLaunchKernelGGL((k_ring_whole<R, M>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out,
+                           g.Lx, g.ps, K, to_coin<R>(C), Links{}, (int64_t)0);
 }
 
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
-                             hipStream_t s, LaunchInfo *info) {
+                             hipStream_t s, LaunchInfo *info, const Links *links, int64_t t0) {
     const int m = ring_whole_m(prec, g.Lx);
     if (m == 0) return hipErrorInvalidValue;
     if (info) {
@@ -825,16 +858,16 @@ hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
     }
     if (prec == C128) {
         switch (m) {
-        case 1: ring_whole_t<double, 1>(in, out, g, C, K, s); break;
-        case 2: ring_whole_t<double, 2>(in, out, g, C, K, s); break;
-        default: ring_whole_t<double, 4>(in, out, g, C, K, s); break;
+        case 1: ring_whole_t<double, 1>(in, out, g, C, K, s, links, t0); break;
+        case 2: ring_whole_t<double, 2>(in, out, g, C, K, s, links, t0); break;
+        default: ring_whole_t<double, 4>(in, out, g, C, K, s, links, t0); break;
         }
     } else {
         switch (m) {
-        case 1: ring_whole_t<float, 1>(in, out, g, C, K, s); break;
-        case 2: ring_whole_t<float, 2>(in, out, g, C, K, s); break;
-        case 4: ring_whole_t<float, 4>(in, out, g, C, K, s); break;
-        default: ring_whole_t<float, 8>(in, out, g, C, K, s); break;
+        case 1: ring_whole_t<float, 1>(in, out, g, C, K, s, links, t0); break;
+        case 2: ring_whole_t<float, 2>(in, out, g, C, K, s, links, t0); break;
+        case 4: ring_whole_t<float, 4>(in, out, g, C, K, s, links, t0); break;
+        default: ring_whole_t<float, 8>(in, out, g, C, K, s, links, t0); break;
         }
     }
     return hipGetLastError();

@@ -281,3 +281,34 @@ def test_blocked_torus_c64_all_depths(kind):
     for depth in (4, 8, 16):
         P, _ = _walk_opts(ext, inputs.PAIR, kind, psi0, x0, T, qwalk.QW_C64, 0.1, 5, 0, False, depth)
         assert np.max(np.abs(P - ref)) <= TOL32_P, depth
+
+
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+@pytest.mark.parametrize("walls", [False, True])
+def test_ring_whole_matches_one_step(prec, walls):
+    """Rings held whole by one workgroup run all steps with broken links in one
+    launch (the links drawn inside the step loop): the amplitudes equal those of one
+    step per launch bit for bit, for walks stepped in pieces (t0 > 0 at a launch),
+    across the sizes of one to eight sites per thread; c128 also against the oracle."""
+    nmax = 4096 if prec == qwalk.QW_C128 else 8192
+    for N in (1, 2, 5, 1024, 1025, 3001, nmax):
+        rng = np.random.default_rng(N + 11 * walls + prec)
+        U = inputs.haar_unitary(rng, 2)
+        psi0 = inputs.haar_state(rng, 2)
+        x0 = (int(rng.integers(0, N)),)
+        res = []
+        for depth in (1, 0):
+            w = qwalk.Walk((N,), inputs.RING, qwalk.DENSE, psi0, x0, prec=prec, dense=U)
+            w.set_options(block_depth=depth, renorm_every=0)
+            if walls:
+                w.set_reflecting_walls(True)
+            w.set_broken_links(0.25, 41, 3)
+            for n in (7, 1, 150):
+                w.step(n)
+            res.append(w.get_state())
+            w.destroy()
+        assert np.array_equal(res[0], res[1]), N
+        if prec == qwalk.QW_C128:
+            o = oracle.initial_state(N, 1, 2, (x0[0], 0), psi0)
+            o = oracle.evolve_rbl(o, inputs.RING, U, 158, p=0.25, seed=41, realization=3, walls=walls)
+            assert np.max(np.abs(np.transpose(res[1], (1, 2, 0)) - o)) <= TOL64, N
