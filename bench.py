@@ -266,6 +266,16 @@ def _surrogate_walks(seed: int, n: int):
     return np.full(n, 4097, dtype=np.int64), T, ang, psi0
 
 
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def mfma_roofline(flops: float, ms: float) -> dict:
+    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"bound": "mfma", "kernel": "network pass (k_gemm_nt)", "achieved": round(achieved, 1),
+            "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / BF16_DENSE_PEAK_TFLOPS, 4),
+            "traffic": None, "flops": flops, "ms": round(ms, 4)}
+
+
 def surrogate(args):
     """Learned surrogate vs the plain batched walk on the same GPU: train on
     walks the batched simulator generates (seed 5), evaluate on held-out
@@ -379,6 +389,11 @@ def surrogate(args):
         "recheck_max_tvd": st.max_tvd_sampled,
         "network_ms": st.ms_network, "recheck_ms": st.ms_recheck, "fallback_ms": st.ms_fallback,
         "network_only_speedup": (plain_ms / st.ms_network) if st.ms_network > 0 else None,
+        # the network pass is four bf16 GEMMs (32 -> 512 -> 1024 -> 1024 -> 1024 per
+        # walk, rows padded to 128) plus the inputs and the conv head; timed whole
+        # (HIP events) against the dense bf16 MFMA peak
+        "roofline": mfma_roofline(2.0 * ((ne + 127) // 128 * 128) * (32 * 512 + 512 * 1024 + 2 * 1024 * 1024),
+                                  st.ms_network),
         "tvd_network": {"median": float(np.median(tvd)), "p90": float(np.quantile(tvd, 0.9)),
                         "p99": float(np.quantile(tvd, 0.99)), "max": float(tvd.max()),
                         "frac_le_1e-3": float(np.mean(tvd <= 1e-3)), "frac_le_1e-2": float(np.mean(tvd <= 1e-2))},

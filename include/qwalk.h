@@ -362,7 +362,7 @@ const char *walk_batch_last_error(void);
 typedef struct qw_surr *qw_surr_t;
 
 typedef struct {
-    int32_t batch;        /* samples per step: a multiple of 128 in [128, 4096] */
+    int32_t batch;        /* samples per step: a multiple of 128 in [128, 16384] */
     int32_t epochs;
     float lr;             /* peak Adam learning rate (cosine decay to lr * lr_floor) */
     float lr_floor;
@@ -409,7 +409,7 @@ int surr_features(qw_surr_t s, int64_t n, const int64_t *N, const int64_t *T, co
  * of T steps (n int32, host). */
 int surr_forward(qw_surr_t s, int64_t n, const float *X, const int32_t *T, float *out);
 /* Mean loss and the gradient of every parameter (host, surr_num_params()) for
- * n <= 4096 samples (X: n x 32, Y: n x 512 targets, T: n steps; host). */
+ * n <= 16384 samples (X: n x 32, Y: n x 512 targets, T: n steps; host). */
 int surr_loss_grad(qw_surr_t s, int64_t n, const float *X, const float *Y, const int32_t *T, double *loss,
                    float *grads);
 /* Train on n samples held on the device (X: n x 32, Y: n x 512 floats, T: n

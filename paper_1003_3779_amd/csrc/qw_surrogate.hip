@@ -49,7 +49,10 @@ __host__ __device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(floa
 // C[m][n] = alpha * sum_k A[m][k] B[n][k] (+ bias[n]); optional mask (keep where
 // mask[m][n] > 0) and relu; store fp32 and/or bf16.  A: M x K, B: N x K, both
 // bf16 row-major with K contiguous; K % 32 == 0.  Tile 128 x 128 x 32 per
-// 256-thread block, each wave a 64 x 64 quarter as 2 x 2 MFMA 32x32x8 tiles.
+// 256-thread block, each wave a 64 x 64 quarter as 2 x 2 MFMA 32x32x16 tiles
+// (gfx950's double-K bf16 MFMA).  The next K tile is fetched into registers
+// while the current one is multiplied, and the LDS tiles are double-buffered:
+// one barrier per K tile.
 struct GemmArgs {
     const bf16_t *A;
     int lda;
@@ -67,11 +70,12 @@ struct GemmArgs {
     int ldcb;
 };
 
-constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsRow = kBK + 4;  // +4 bf16 row padding (bank spread)
+constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsRow = kBK + 8;  // +8 bf16: 16-byte aligned, spread rows
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-    __shared__ bf16_t sA[kBM * kLdsRow];
-    __shared__ bf16_t sB[kBN * kLdsRow];
+    __shared__ bf16_t sA[2][kBM * kLdsRow];
+    __shared__ bf16_t sB[2][kBN * kLdsRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
@@ -82,10 +86,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    // staging: each thread moves 2 x 16 bytes of A and of B per K step
+    // staging: each thread moves 2 x 16 bytes of A and of B per K tile
     const int lrow = tid >> 2, lk = (tid & 3) * 8;
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        uint4 va[2], vb[2];
+    uint4 va[2], vb[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int r = lrow + 64 * h;
@@ -93,34 +97,43 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             va[h] = ma < g.M ? *(const uint4 *)(g.A + (int64_t)ma * g.lda + k0 + lk) : make_uint4(0, 0, 0, 0);
             vb[h] = nb < g.N ? *(const uint4 *)(g.B + (int64_t)nb * g.ldb + k0 + lk) : make_uint4(0, 0, 0, 0);
         }
-        __syncthreads();
+    };
+    auto stage = [&](int buf) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int r = lrow + 64 * h;
-            unsigned *pa = (unsigned *)(sA + r * kLdsRow + lk);
-            unsigned *pb = (unsigned *)(sB + r * kLdsRow + lk);
-            pa[0] = va[h].x; pa[1] = va[h].y; pa[2] = va[h].z; pa[3] = va[h].w;
-            pb[0] = vb[h].x; pb[1] = vb[h].y; pb[2] = vb[h].z; pb[3] = vb[h].w;
+            *(uint4 *)(sA[buf] + r * kLdsRow + lk) = va[h];
+            *(uint4 *)(sB[buf] + r * kLdsRow + lk) = vb[h];
         }
-        __syncthreads();
+    };
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        const bool more = k0 + kBK < g.K;
+        if (more) fetch(k0 + kBK);  // in flight while this tile is multiplied
 #pragma unroll
-        for (int kk = 0; kk < kBK; kk += 8) {
-            // lane l supplies row (l % 32) of the 32 x 8 operand, k = kk + 4 (l / 32) .. + 3
-            const int kof = kk + 4 * (lane >> 5);
-            short4_t a[2], b[2];
+        for (int kk = 0; kk < kBK; kk += 16) {
+            // lane l supplies row (l % 32) of the 32 x 16 operand, k = kk + 8 (l / 32) .. + 7
+            // (A and B alike, so each product pairs equal k)
+            const int kof = kk + 8 * (lane >> 5);
+            bf16x8_t a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const bf16_t *p = sA + (wm * 64 + i * 32 + (lane & 31)) * kLdsRow + kof;
-                a[i] = *(const short4_t *)p;
-                const bf16_t *q = sB + (wn * 64 + i * 32 + (lane & 31)) * kLdsRow + kof;
-                b[i] = *(const short4_t *)q;
+                a[i] = *(const bf16x8_t *)(sA[buf] + (wm * 64 + i * 32 + (lane & 31)) * kLdsRow + kof);
+                b[i] = *(const bf16x8_t *)(sB[buf] + (wn * 64 + i * 32 + (lane & 31)) * kLdsRow + kof);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        // the other buffer was last read before the previous barrier
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
     // result layout of a 32x32 tile: lane l holds column l % 32, rows
     // 8 (r / 4) + 4 (l / 32) + (r % 4) for r = 0 .. 15
@@ -592,7 +605,7 @@ double unif(uint64_t &s) { return (splitmix(s) >> 11) * (1.0 / 9007199254740992.
 struct qw_surr {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int bmax = 4096;
+    int bmax = 16384;  // rows per network pass (training batches, forward chunks)
     float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 params, Adam moments, grads
     bf16_t *pb = nullptr;                                          // bf16 mirror of p
     bf16_t *W2T = nullptr, *W3T = nullptr, *W4T = nullptr;
