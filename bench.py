@@ -166,9 +166,28 @@ def rbl_segment(args):
         ms.append(b.info().last_run_ms)
     t1 = time.perf_counter()
     info = b.info()
-    Pavg = np.mean(np.stack(b.probabilities()), axis=0)
+    Pall = b.probabilities()
+    Pavg = np.mean(np.stack(Pall), axis=0)
     mom = b.moments()
     b.destroy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        C = oracle.coin(oracle.SU2, 2, math.pi / 4, -math.pi / 2, -math.pi / 2)
+        worst = 0.0
+        tc0 = time.perf_counter()
+        refs = []
+        for r in range(4):
+            o = oracle.initial_state(N, 1, 2, (N // 2, 0), inputs.PSI0_LR)
+            o = oracle.evolve_rbl(o, inputs.RING, C, T, p=p, seed=seed, realization=r, walls=True)
+            refs.append(oracle.prob(o)[0])
+        tc1 = time.perf_counter()
+        for r, ref in enumerate(refs):
+            worst = max(worst, float(np.max(np.abs(Pall[r] - ref))))
+        cpu = {"value": 4 * N * 2 * T / (tc1 - tc0), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": f"oracle (plain C, fp64, 1 thread), realizations 0-3 of the same segment walk "
+                         f"({4 * N * 2 * T:.3e} site*coin updates, {tc1 - tc0:.2f} s)",
+               "max_abs_dP_vs_oracle": worst}
     # the same walk one realization at a time through walk_step (rings run one
     # step per launch with broken links)
     w = qwalk.Walk((N,), inputs.RING, qwalk.SU2, inputs.PSI0_LR, (N // 2,), prec=qwalk.QW_C128,
@@ -200,6 +219,8 @@ def rbl_segment(args):
         "P_avg_at_centre": float(Pavg[N // 2]),
         "P_avg_sum": float(Pavg.sum()),
     }
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
@@ -229,8 +250,31 @@ def ragged_rings(args):
     t1 = time.perf_counter()
     info = b.info()
     mom = b.moments()
+    bins = b.binned()
     lim = 1.0 - np.abs(np.sin(p["angles"][:, 0]))
     m2 = mom[:, 2] / p["T"].astype(np.float64) ** 2
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle (light-cone windowed, plain C, fp64, 1 thread) on the walks
+        # with N < 1e4, against the GPU's bins of the same walks
+        import oracle
+        Ns, Ts_, As, Ps = p["N"], p["T"], p["angles"], p["psi0"]
+        pick = [i for i in np.argsort(Ns) if Ns[i] < 10000][:64]
+        upd, worst = 0, 0.0
+        tc0 = time.perf_counter()
+        refs = []
+        for i in pick:
+            C = oracle.coin(oracle.SU2, 2, *As[i])
+            psi = oracle.walk(int(Ns[i]), 1, inputs.RING, C, (int(Ns[i] // 2), 0), Ps[i], int(Ts_[i]))
+            refs.append(oracle.prob(psi)[0])
+            upd += 2 * sum(min(2 * r + 1, int(Ns[i])) for r in range(1, int(Ts_[i]) + 1))
+        tc1 = time.perf_counter()
+        for i, ref in zip(pick, refs):
+            worst = max(worst, float(np.max(np.abs(bins[i] - oracle.bin_ring(ref, int(Ns[i] // 2), 512)))))
+        cpu = {"value": upd / (tc1 - tc0), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": f"light-cone windowed oracle (plain C, fp64, 1 thread) on the {len(pick)} walks "
+                         f"with N < 1e4 ({upd:.3e} site*coin updates, {tc1 - tc0:.1f} s)",
+               "max_abs_dbins_vs_oracle": worst}
     out = {
         "metric": METRIC, "value": info.est_updates * args.steps / (t1 - t0), "unit": UNIT,
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -250,6 +294,8 @@ def ragged_rings(args):
         "norm_error_max": float(np.max(np.abs(mom[:, 0] - 1.0))),
         "second_moment_vs_limit_max": float(np.max(np.abs(m2 - lim))),
     }
+    if cpu:
+        out["cpu_baseline"] = cpu
     b.destroy()
     print(json.dumps(out), flush=True)
 
