@@ -924,7 +924,20 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
     const long target_waves = tu.waves > 0 ? tu.waves : (sizeof(R) == 8 ? 16384 : 4096);
     long segs = (target_waves + nstrips - 1) / nstrips;
     int seg_rows = (int)((b.wy + segs - 1) / segs);
-    if (seg_rows < 4 * K) seg_rows = 4 * K;
+    if (seg_rows < 4 * K) {
+        // below 4K rows the 2K halo rows of a segment cost more traffic than
+        // shorter segments save -- unless the launch would not fill the chip
+        // (small boxes): then each wave's serial time (rows + 2K iterations of
+        // K levels) is the launch time, and shorter segments cut it
+        constexpr long kFillWaves = 2048;  // two waves per SIMD of the 256 CUs
+        const long waves_at_4k = (long)nstrips * ((b.wy + 4 * K - 1) / (4 * K));
+        if (waves_at_4k >= kFillWaves) {
+            seg_rows = 4 * K;
+        } else {
+            const long segs_fill = (kFillWaves + nstrips - 1) / nstrips;
+            seg_rows = std::max(seg_rows, (int)((b.wy + segs_fill - 1) / segs_fill));
+        }
+    }
     const int nseg = (b.wy + seg_rows - 1) / seg_rows;
     const long waves = (long)nstrips * nseg;
     const long blocks = (waves + 3) / 4;
