@@ -475,22 +475,25 @@ def traffic_from_profile(kernel_sha: str):
 
 
 def kernel_source_sha():
-    """sha256 of the torus streaming kernel's source: the regions of
-    qw_kernels.hip between its begin / end markers (device code and launcher)."""
-    with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", "qw_kernels.hip"), "rb") as f:
-        src = f.read()
-    begin, end = b"// ---- torus streaming kernel: begin ----", b"// ---- torus streaming kernel: end ----"
+    """sha256 of what sets the torus walk's launches: the streaming kernel's
+    source (the regions of qw_kernels.hip between its begin / end markers,
+    device code and launcher) and the choice of launches (the marked regions
+    of qw_api.hip)."""
     h = hashlib.sha256()
-    pos = 0
-    while True:
-        i = src.find(begin, pos)
-        if i < 0:
-            break
-        j = src.find(end, i)
-        if j < 0:
-            break
-        h.update(src[i:j])
-        pos = j + len(end)
+    for fname, tag in (("qw_kernels.hip", b"torus streaming kernel"), ("qw_api.hip", b"torus launch choice")):
+        with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", fname), "rb") as f:
+            src = f.read()
+        begin, end = b"// ---- " + tag + b": begin ----", b"// ---- " + tag + b": end ----"
+        pos = 0
+        while True:
+            i = src.find(begin, pos)
+            if i < 0:
+                break
+            j = src.find(end, i)
+            if j < 0:
+                break
+            h.update(src[i:j])
+            pos = j + len(end)
     return h.hexdigest()
 
 

@@ -99,7 +99,9 @@ typedef struct {
                               runs as the largest smaller one it has: rings 4, 8, 16; tori
                               4, 8 in QW_C128 and 4, 8, 12, 16 in QW_C64); the steps left
                               after the last full block run at the largest smaller depth;
-                              auto with broken links or walls on a torus: 4 */
+                              auto: rings 16, tori 8 (QW_C128) or 12 (QW_C64), small tori
+                              (state under 32 MiB) 4, with broken links or walls on a
+                              torus 4 */
     int32_t window;        /* 1: update only the light cone of the start site (exact, the
                               rest is zero); 0: sweep the whole lattice every step */
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and

@@ -278,6 +278,7 @@ int64_t box_sites(const Box &b) { return (int64_t)b.wx * (int64_t)b.wy; }
 void *cur_buf(qw_walk *w) { return w->buf[w->cur]; }
 void *oth_buf(qw_walk *w) { return w->buf[1 - w->cur]; }
 
+// ---- torus launch choice: begin ----
 // the largest blocked depth <= k that the ring tile kernel (ring) or the torus
 // stream kernel takes for this walk; 1 when there is none
 int fit_depth(const qw_walk *w, int k, bool ring) {
@@ -289,12 +290,19 @@ int fit_depth(const qw_walk *w, int k, bool ring) {
 
 int default_depth(const qw_walk *w) {
     if (w->dim == 1) return 16;
+    // a small torus (its state moved twice under 64 MiB, e.g. 500^2 in c128):
+    // every launch lasts one wave's serial time, (rows + 2K) x K level steps,
+    // not its traffic, so K = 4 beats 8 (measured on the 500^2 Fourier walk:
+    // 1.35 ms per walk against 1.55); on large tori the same switch for the
+    // small early boxes was slower (4096^2: 49.5 ms against 49.0)
+    if (2 * (int64_t)w->state_bytes < ((int64_t)64 << 20)) return 4;
     // torus: complex128 fits 8 levels in registers; complex64 12, which keeps two
     // waves per SIMD where 16 keeps one and halves the wasted halo lanes of 16
     // (measured: 4096^2 Grover 27.3 ms per walk at K = 12, 31.5 at 16, 32.1 at 8;
     // 16384^2 H(x)H 190 ms at 12, 241 at 16)
     return w->prec == C64 ? 12 : 8;
 }
+// ---- torus launch choice: end ----
 
 hipEvent_t take_event(qw_walk *w) {
     if (!w->spare.empty()) {
@@ -496,6 +504,7 @@ int run_forward(qw_walk *w, int64_t n) {
         w->updates += (int64_t)w->g.Lx * w->d * n;
         return QW_OK;
     }
+    // ---- torus launch choice: begin ----
     const bool ring_blocked = w->dim == 1 && w->ring_std && w->g.Lx >= 512;
     const bool torus_blocked = w->dim == 2 && w->g.Lx >= 64;
     int64_t left = n;
@@ -504,11 +513,13 @@ int run_forward(qw_walk *w, int64_t n) {
         // depths for what is left (e.g. 64 steps between norm checks at K = 12:
         // five blocks of 12 and one of 4)
         for (int k = fit_depth(w, depth, ring_blocked); k > 1 && left > 0; k = fit_depth(w, k - 1, ring_blocked))
-            for (; left >= k; left -= k) {
+            while (left >= k) {
                 int rc = stepK(w, k, ring_blocked);
                 if (rc) return rc;
+                left -= k;
             }
     }
+    // ---- torus launch choice: end ----
     while (left > 0) {
         int rc = step1(w);
         if (rc) return rc;
