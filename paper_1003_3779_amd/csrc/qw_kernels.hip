@@ -126,7 +126,11 @@ __global__ __launch_bounds__(256) void k_step_inv(const cv<R> *__restrict__ in, 
 // j*M + i - 1 to the next one, owned by the former; one generator call per
 // owner site, word 0 -- the draws of k_step_rbl), and a move across a broken
 // link takes the opposite component of the site itself.
-template <typename R, int M, bool RB = false>
+//
+// REALC: the coin is real (Hadamard, real rotations): each output is one
+// product and one FMA per real part, the same roundings as the complex form
+// with zero imaginary parts (whose extra terms add exact zeros).
+template <typename R, int M, bool RB = false, bool REALC = false>
 __global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
                                                      int N, int64_t ps, int64_t K, CoinR<R> C, Links L,
                                                      int64_t t0) {
@@ -189,8 +193,15 @@ __global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ i
                     if ((lk >> m) & 1u) g0 = a1[m];
                     if ((lk >> (m + 1)) & 1u) g1 = a0[m];
                 }
-                n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
-                n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+                if constexpr (REALC) {
+                    n0[m].x = fmaR(c01r, g1.x, c00r * g0.x);
+                    n0[m].y = fmaR(c01r, g1.y, c00r * g0.y);
+                    n1[m].x = fmaR(c11r, g1.x, c10r * g0.x);
+                    n1[m].y = fmaR(c11r, g1.y, c10r * g0.y);
+                } else {
+                    n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
+                    n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+                }
             }
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -839,12 +850,20 @@ static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64
                          const Links *links, int64_t t0) {
     const int nl = (g.Lx + M - 1) / M;
     const int threads = ((nl + 63) / 64) * 64;
-    if (links)
-        hipLaunchKernelGGL((k_ring_whole<R, M, true>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out,
-                           g.Lx, g.ps, K, to_coin<R>(C), *links, t0);
-    else
-        hipLaunchKernelGGL((k_ring_whole<R, M>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in, (cv<R> *)out,
-                           g.Lx, g.ps, K, to_coin<R>(C), Links{}, (int64_t)0);
+    const bool real = C.im[0] == 0.0 && C.im[1] == 0.0 && C.im[2] == 0.0 && C.im[3] == 0.0;
+    const Links L = links ? *links : Links{};
+    const int64_t tl = links ? t0 : 0;
+#define QW_RING_WHOLE(RBV, RC)                                                                            \
+    hipLaunchKernelGGL((k_ring_whole<R, M, RBV, RC>), dim3(1), dim3(threads), 0, s, (const cv<R> *)in,     \
+                       (cv<R> *)out, g.Lx, g.ps, K, to_coin<R>(C), L, tl)
+    if (links) {
+        if (real) QW_RING_WHOLE(true, true);
+        else QW_RING_WHOLE(true, false);
+    } else {
+        if (real) QW_RING_WHOLE(false, true);
+        else QW_RING_WHOLE(false, false);
+    }
+#undef QW_RING_WHOLE
 }
 
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,

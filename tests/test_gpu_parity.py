@@ -408,3 +408,25 @@ def test_fourier_workloads_full_size(name):
     if cfg["disp"] == inputs.DIAG:
         yy, xx = np.indices(P.shape)
         assert np.all(P[((xx - x0[0]) + (yy - x0[1])) % 2 == 1] == 0.0)
+
+
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+def test_ring_real_coin_bitwise(prec):
+    """Real coins (Hadamard, real rotations) take a real-arithmetic path in the
+    whole-ring kernel: the same amplitudes as one step per launch (complex
+    arithmetic with zero imaginary parts), and the oracle's in c128."""
+    th = 0.83
+    Rot = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]], dtype=np.complex128)
+    rng = np.random.default_rng(12)
+    psi0 = inputs.haar_state(rng, 2)
+    for kind, dense, oc in ((qwalk.HADAMARD, None, oracle.coin(oracle.HADAMARD, 2)), (qwalk.DENSE, Rot, Rot)):
+        N, T, x0 = 3001, 700, (1500, 0)
+        res = []
+        for depth in (1, 0):
+            _, psi, _, _ = _run_gpu((N,), inputs.RING, kind, psi0, x0, T, prec, dense=dense, block_depth=depth,
+                                    renorm_every=0)
+            res.append(psi)
+        assert np.array_equal(res[0], res[1])
+        if prec == qwalk.QW_C128:
+            Pr, psir = _oracle_run((N,), inputs.RING, oc, psi0, x0, T)
+            assert np.max(np.abs(_as_oracle_layout(res[1]) - psir)) <= TOL64
