@@ -253,3 +253,10 @@ def test_batch_realization_average():
     ref = np.mean([_oracle_rbl_P(N, T, ang[0], psi0[0], x0, 0.2, 9, r, True) for r in range(R)], axis=0)
     assert np.max(np.abs(P - ref)) <= 1e-12
     assert np.max(np.abs(avg(10) - P)) > 1e-4
+    # every ring is held whole with links: the tuner has no tiled walk to time
+    b = qwalk.Batch([N] * 4, [T] * 4, ang[:4], psi0[:4], [x0] * 4, prec=qwalk.QW_C64, link_p=0.2, link_seed=9)
+    b.tune(samples=2, save=False)
+    b.run()
+    assert np.max(np.abs(b.moments()[:, 0] - 1.0)) <= 1e-5
+    assert b.info().whole_ring_walks == 4
+    b.destroy()
