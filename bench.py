@@ -289,7 +289,7 @@ def ragged_rings(args):
         # the batch kernel is bound by its fp32 arithmetic: per site and step the
         # rotation coin, factored as f [[1, t], [-t, 1]], costs 4 FMAs (8 flops),
         # 4 per site*coin update; peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
-        # 2.4 GHz for unpacked fp32 FMAs (packed fp32 is off in this build)
+        # 2.4 GHz for unpacked fp32 FMAs (the library is compiled without packed fp32)
         "roofline": alu_roofline(info.est_updates * 4.0, float(np.median(ms))),
         "norm_error_max": float(np.max(np.abs(mom[:, 0] - 1.0))),
         "second_moment_vs_limit_max": float(np.max(np.abs(m2 - lim))),
@@ -586,7 +586,7 @@ def graph_bench(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

@@ -359,7 +359,7 @@ const char *walk_batch_last_error(void);
  * softmax, KL(y || q) loss and its gradient in fp32; Adam keeps fp32 master
  * weights.  Parameters are one fp32 vector in the order W1, b1, W2, b2, W3,
  * b3, W4, b4, cw (2 x 9), cb (surr_num_params() values).  The plain walk is
- * the surrogate's fallback and its judge (surr_predict).
+ * the surrogate's fallback and its arbiter (surr_predict).
  * ------------------------------------------------------------------------ */
 typedef struct qw_surr *qw_surr_t;
 

@@ -1,7 +1,7 @@
 // qw_surrogate.hip -- a learned surrogate of the ring walk: a small network
 // (MLP + 1D convolution head) that maps the parameters of a walk to its
 // position distribution in 512 symmetric bins, trained on walks produced by
-// the batched simulator, with the plain walk as its fallback and its judge.
+// the batched simulator, with the plain walk as its fallback and its arbiter.
 //
 // Network (x: 32 features, 12 used, the rest zero; T the walk's steps):
 //   h1 = relu(x W1^T + b1)      512 x 32        (GEMMs: bf16 operands on

@@ -495,7 +495,7 @@ def _walk_arrays(N, T, angles, psi0):
 
 class Surrogate:
     """The learned surrogate (surr_*): features -> network -> 512 bins, with
-    the plain walk as fallback and judge."""
+    the plain walk as fallback and arbiter."""
 
     NBINS = 512
     NFEAT = 32
