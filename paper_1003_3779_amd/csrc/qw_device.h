@@ -92,6 +92,16 @@ template <typename R> struct Coin<R, 4, COIN_GROVER4> {
 #pragma unroll
         for (int c = 0; c < 4; ++c) o[c] = csub<R>(s, g[c]);
     }
+    // twice the result: (sum) - 2 g_c, one FMA per real part; the same rounding
+    // as apply, scaled by 2 (exact outside the subnormal range)
+    __device__ __forceinline__ static void apply_x2(const cv<R> *g, cv<R> *o) {
+        const cv<R> s = cadd<R>(cadd<R>(g[0], g[1]), cadd<R>(g[2], g[3]));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            o[c].x = fmaR((R)-2, g[c].x, s.x);
+            o[c].y = fmaR((R)-2, g[c].y, s.y);
+        }
+    }
 };
 // H (x) H, d = 4, c = 2j + k: two butterfly levels and a factor 1/2.
 template <typename R> struct Coin<R, 4, COIN_HH4> {
@@ -102,6 +112,15 @@ template <typename R> struct Coin<R, 4, COIN_HH4> {
         o[1] = cscale<R>(cadd<R>(u1, u3), (R)0.5);
         o[2] = cscale<R>(csub<R>(u0, u2), (R)0.5);
         o[3] = cscale<R>(csub<R>(u1, u3), (R)0.5);
+    }
+    // twice the result (no factor 1/2): the same roundings as apply, scaled by 2
+    __device__ __forceinline__ static void apply_x2(const cv<R> *g, cv<R> *o) {
+        cv<R> u0 = cadd<R>(g[0], g[1]), u1 = csub<R>(g[0], g[1]);
+        cv<R> u2 = cadd<R>(g[2], g[3]), u3 = csub<R>(g[2], g[3]);
+        o[0] = cadd<R>(u0, u2);
+        o[1] = cadd<R>(u1, u3);
+        o[2] = csub<R>(u0, u2);
+        o[3] = csub<R>(u1, u3);
     }
 };
 

@@ -428,17 +428,25 @@ __device__ __forceinline__ void stream_iter(StreamRegs<R, K, M> &st, cv<R> (&pf)
             cv<R> gi[4], go[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) gi[c] = gth[c][m];
-            Coin<R, 4, COIN>::apply(gi, go, C);
+            // Grover and H (x) H carry a factor 1/2 per step: inside the launch the
+            // levels keep it out (values 2^s times the true ones at level s, the
+            // same roundings) and the store applies 2^-K once
+            if constexpr (COIN == COIN_GROVER4 || COIN == COIN_HH4) Coin<R, 4, COIN>::apply_x2(gi, go);
+            else Coin<R, 4, COIN>::apply(gi, go, C);
 #pragma unroll
             for (int c = 0; c < 4; ++c) cur[c][m] = go[c];
         }
     }
     if (do_store) {
+        constexpr bool kScaled = COIN == COIN_GROVER4 || COIN == COIN_HH4;
+        const R unscale = (R)1 / (R)(1u << K);  // 2^-K, exact
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                if (store_col[m]) out[(int64_t)c * g.ps + (int64_t)row_out * g.Lx + xcol[m]] = cur[c][m];
+                if (store_col[m])
+                    out[(int64_t)c * g.ps + (int64_t)row_out * g.Lx + xcol[m]] =
+                        kScaled ? cscale<R>(cur[c][m], unscale) : cur[c][m];
     }
 }
 
