@@ -756,11 +756,12 @@ def main():
         okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2,
                  qwalk.FOURIER: oracle.FOURIER}[cfg["coin"]]
         C = oracle.coin(okind, 4)
-        psi_init = oracle.initial_state(Lx, Ly, 4, x0, psi0)
+        psi_o = oracle.initial_state(Lx, Ly, 4, x0, psi0)
         tc0 = time.perf_counter()
-        psi_o = oracle.evolve(psi_init, disp, C, Ts, windowed=True, x0=x0, t0=0)
+        for t0 in range(0, Ts, 256):           # in chunks, with a progress line each
+            psi_o = oracle.evolve(psi_o, disp, C, min(256, Ts - t0), windowed=True, x0=x0, t0=t0)
+            print(f"# cpu baseline: oracle at step {min(t0 + 256, Ts)} of {Ts}", file=sys.stderr, flush=True)
         tc1 = time.perf_counter()
-        del psi_init
         # the oracle's window at step s (s = 1..Ts) is the box of radius s about x0
         upd = sum(min(2 * r + 1, Lx) * min(2 * r + 1, Ly) for r in range(1, Ts + 1)) * 4
         Po = oracle.prob(psi_o)
