@@ -38,9 +38,9 @@ namespace {
 constexpr int kBT = 512;          // threads per batch workgroup
 constexpr int kWaves = kBT / 64;
 constexpr int kMaxBins = 1024;
-constexpr int kNumCfg = 4;        // tiled-path variants (sites per lane MT, steps per block K)
-constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16};
-constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64};
+constexpr int kNumCfg = 6;        // tiled-path variants (sites per lane MT, steps per block K)
+constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16, 4, 4};
+constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64, 16, 32};
 
 struct WalkDesc {
     int32_t N, T, x0, cfg;  // cfg < 0: whole-ring path with m sites per thread; else tiled variant
@@ -328,7 +328,7 @@ __device__ __forceinline__ double block_factor(const CoinRotS<R, SWAP> &cn, int 
 // pending, applied by the next reads.
 constexpr int kFactorEvery = 16;
 static_assert(kCfgK[0] % kFactorEvery == 0 && kCfgK[1] % kFactorEvery == 0 && kCfgK[2] % kFactorEvery == 0 &&
-                  kCfgK[3] % kFactorEvery == 0,
+                  kCfgK[3] % kFactorEvery == 0 && kCfgK[4] % kFactorEvery == 0 && kCfgK[5] % kFactorEvery == 0,
               "every tiled block depth is a multiple of the factor period");
 
 // ---------------------------------------------------------------- tiled ring
@@ -499,6 +499,10 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         if (!w.rot) {
             // a walk whose light cone wraps the ring: full SU(2) coin, one variant
             walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
+        } else if (kCfgMT[w.cfg] == 4) {
+            // short cones: small tiles keep more of the workgroup's waves busy
+            if (w.rswap) walk_tiled<R, 4, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else walk_tiled<R, 4, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         } else if (kCfgMT[w.cfg] == 8) {
             if (w.rswap) walk_tiled<R, 8, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
             else walk_tiled<R, 8, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
@@ -662,10 +666,10 @@ struct qw_batch {
     int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (512 sites, 32
-    // steps) for the short rings, (1024, 64) for the long ones -- what the tuner
-    // picks on the 4096-ring workload
-    int bucket_cfg[3] = {1, 3, 3};
+    // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (256 sites, 32
+    // steps) for the short rings, whose cones span few tiles, (1024, 64) for the
+    // long ones
+    int bucket_cfg[3] = {5, 3, 3};
     double last_ms = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool own_stream = false;
@@ -1041,7 +1045,8 @@ int walk_batch_info(qw_batch_t b, qw_batch_info *out) {
     out->last_run_ms = ms;
     for (int k = 0; k < 3; ++k) {
         out->bucket_cfg[k] = b->bucket_cfg[k];
-        out->bucket_tile_sites[k] = 64 * (b->prec == QW_C128 ? 8 : kCfgMT[b->bucket_cfg[k]]);
+        out->bucket_tile_sites[k] = 64 * (b->prec == QW_C128 ? std::min(8, kCfgMT[b->bucket_cfg[k]])
+                                                              : kCfgMT[b->bucket_cfg[k]]);
         out->bucket_depth[k] = kCfgK[b->bucket_cfg[k]];
     }
     return QW_OK;

@@ -56,7 +56,7 @@ def _check_walks(b, N, T, ang, psi0, x0, tolP, nbins):
 
 
 @pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_batch_mixed_sizes(prec, tol, variant):
     N, T, ang, psi0, x0 = _mixed(11 + variant)
     b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True, tiled_variant=variant)
@@ -68,7 +68,7 @@ def test_batch_mixed_sizes(prec, tol, variant):
 
 
 @pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
-@pytest.mark.parametrize("variant", [1, 4])
+@pytest.mark.parametrize("variant", [1, 4, 5])
 def test_batch_short_rings_tiled(prec, tol, variant):
     """whole_max_sites = 1: every ring of 2048 sites or more runs tiled over its
     light cone (rings 2048..4608 are otherwise held whole), shorter ones whole."""
@@ -93,7 +93,7 @@ def test_batch_short_rings_tiled(prec, tol, variant):
 def test_batch_variants_and_graph_replay_bitwise():
     N, T, ang, psi0, x0 = _mixed(5, n_extra=20)
     ref = None
-    for variant, no_graph in ((1, True), (2, False), (3, False), (4, False), (0, False)):
+    for variant, no_graph in ((1, True), (2, False), (3, False), (4, False), (5, False), (6, False), (0, False)):
         b = qwalk.Batch(N, T, ang, psi0, x0, prec=qwalk.QW_C64, nbins=32, keep_probabilities=True,
                         tiled_variant=variant, no_graph=no_graph, renorm_every=-1)
         for rep in range(3):
@@ -117,8 +117,8 @@ def test_batch_autotuner(tmp_path, monkeypatch):
     b.tune(samples=4, save=True)
     info = b.info()
     for k in range(3):
-        assert 0 <= info.bucket_cfg[k] < 4
-        assert info.bucket_tile_sites[k] in (512, 1024) and info.bucket_depth[k] in (16, 32, 64)
+        assert 0 <= info.bucket_cfg[k] < 6
+        assert info.bucket_tile_sites[k] in (256, 512, 1024) and info.bucket_depth[k] in (16, 32, 64)
     b.run()
     assert np.array_equal(b.moments(), before)      # every variant is the same arithmetic
     assert (tmp_path / "tune.txt").exists()
