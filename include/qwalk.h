@@ -471,13 +471,14 @@ typedef struct qw_graph *qw_graph_t;
 typedef struct {
     int64_t nv, narcs;
     int32_t max_degree;
-    int32_t reserved;
+    int32_t layout;          /* device state: 0 = arcs in row order; 1 = slot-major (regular
+                                graphs of degree <= 8: arc j of vertex v at j * nv + v) */
     int64_t t;               /* steps taken */
     int64_t launches;        /* step kernel launches */
     double step_ms;          /* HIP-event time of all graph_walk_step calls */
     double bytes_per_step;   /* HBM bytes of one step by construction: every arc's
                                 amplitude read and written, its reverse index read,
-                                the row offsets read */
+                                the row offsets read (row layout) */
 } qw_graph_info;
 
 int graph_walk_create(int64_t nv, const int64_t *offsets, const int64_t *targets, int32_t coin_kind,

@@ -15,6 +15,13 @@
 // Coins by degree: Grover (2/d) J - I for any degree (as (2/d) s - psi_i with s
 // the row sum); the d-point Fourier matrix and caller-given dense matrices for
 // degrees up to kMaxTableDegree, held in a device table.
+//
+// Regular graphs of degree d <= kSlotMajorDegree are held slot-major instead:
+// arc j of vertex v at j * nv + v.  A wave then reads each slot of 64
+// consecutive vertices as one contiguous run, and on lattice-like graphs
+// (neighbours at nearby indices) the writes to the reverse arcs are contiguous
+// runs too, where the row layout scatters 16-byte pieces 16 d bytes apart.
+// The arithmetic per vertex is the same in both layouts (bitwise-equal results).
 #include "qwalk.h"
 #include "qw_device.h"
 #include "qw_internal.h"
@@ -32,6 +39,7 @@ namespace qw {
 namespace {
 
 constexpr int kMaxTableDegree = 16;  // Fourier and dense coins: degrees 1 .. 16
+constexpr int kSlotMajorDegree = 8;  // regular graphs up to this degree: slot-major state
 constexpr int kGraphRedBlocks = 1024;
 
 // ---------------------------------------------------------------- kernels
@@ -107,6 +115,59 @@ __global__ __launch_bounds__(256) void k_graph_table(const cv<R> *__restrict__ i
     }
 }
 
+// slot-major (regular graphs of degree d <= kSlotMajorDegree): arc j of v at
+// j * nv + v; rev holds slot-major indices.  Same arithmetic as k_graph_grover.
+template <typename R>
+__global__ __launch_bounds__(256) void k_graph_grover_sm(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                         const int32_t *__restrict__ rev, int64_t nv, int d) {
+    const R w = (R)2 / (R)d;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256) {
+        cv<R> a[kSlotMajorDegree];
+        int r[kSlotMajorDegree];
+#pragma unroll
+        for (int j = 0; j < kSlotMajorDegree; ++j) {
+            a[j] = j < d ? in[j * nv + v] : czero<R>();
+            r[j] = j < d ? rev[j * nv + v] : 0;
+        }
+        cv<R> s = czero<R>();
+#pragma unroll
+        for (int j = 0; j < kSlotMajorDegree; ++j)
+            if (j < d) s = cadd<R>(s, a[j]);
+#pragma unroll
+        for (int j = 0; j < kSlotMajorDegree; ++j)
+            if (j < d) {
+                cv<R> o;
+                o.x = fmaR(w, s.x, -a[j].x);
+                o.y = fmaR(w, s.y, -a[j].y);
+                out[r[j]] = o;
+            }
+    }
+}
+
+// slot-major table coins; same arithmetic as k_graph_table
+template <typename R>
+__global__ __launch_bounds__(256) void k_graph_table_sm(const cv<R> *__restrict__ in, cv<R> *__restrict__ out,
+                                                        const int32_t *__restrict__ rev, int64_t nv, int d,
+                                                        const cv<R> *__restrict__ table,
+                                                        const int32_t *__restrict__ toff) {
+    const cv<R> *C = table + toff[d];
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256) {
+        cv<R> a[kSlotMajorDegree];
+#pragma unroll
+        for (int j = 0; j < kSlotMajorDegree; ++j) a[j] = j < d ? in[j * nv + v] : czero<R>();
+        for (int i = 0; i < d; ++i) {
+            cv<R> acc = czero<R>();
+#pragma unroll
+            for (int j = 0; j < kSlotMajorDegree; ++j)
+                if (j < d) {
+                    const cv<R> c = C[i * d + j];
+                    acc = cmac<R>(acc, c.x, c.y, a[j]);
+                }
+            out[rev[i * nv + v]] = acc;
+        }
+    }
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -114,17 +175,26 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // P(v) = sum of |psi|^2 over v's row (fp64, row order); block partial sums of P
+// sm_d > 0: slot-major state of degree sm_d (off unused); the same row order
 template <typename R>
 __global__ __launch_bounds__(256) void k_graph_prob(const cv<R> *__restrict__ psi, const int32_t *__restrict__ off,
                                                     int64_t nv, double *__restrict__ P,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ partial, int sm_d) {
     __shared__ double ws[4];
     double acc = 0.0;
     for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256) {
         double p = 0.0;
-        for (int k = off[v]; k < off[v + 1]; ++k) {
-            const double re = (double)psi[k].x, im = (double)psi[k].y;
-            p += re * re + im * im;
+        if (sm_d > 0) {
+            for (int j = 0; j < sm_d; ++j) {
+                const cv<R> a = psi[j * nv + v];
+                const double re = (double)a.x, im = (double)a.y;
+                p += re * re + im * im;
+            }
+        } else {
+            for (int k = off[v]; k < off[v + 1]; ++k) {
+                const double re = (double)psi[k].x, im = (double)psi[k].y;
+                p += re * re + im * im;
+            }
         }
         if (P) P[v] = p;
         acc += p;
@@ -146,19 +216,32 @@ __global__ __launch_bounds__(256) void k_graph_reduce(const double *__restrict__
     if (threadIdx.x == 0) *out = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
-template <typename R>
-__global__ void k_graph_widen(const cv<R> *__restrict__ in, double2 *__restrict__ out, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = make_double2((double)in[i].x, (double)in[i].y);
+// state index of arc i (row order): i itself, or j * nv + v (slot-major, sm_d > 0)
+__device__ __forceinline__ int64_t state_index(int64_t i, int64_t nv, int sm_d) {
+    if (sm_d <= 0) return i;
+    const int64_t v = i / sm_d;
+    return (i - v * sm_d) * nv + v;
 }
 
+// device state -> complex128 in row (arc) order
 template <typename R>
-__global__ void k_graph_narrow(const double2 *__restrict__ in, cv<R> *__restrict__ out, int64_t n) {
+__global__ void k_graph_widen(const cv<R> *__restrict__ in, double2 *__restrict__ out, int64_t n, int64_t nv,
+                              int sm_d) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const cv<R> a = in[state_index(i, nv, sm_d)];
+        out[i] = make_double2((double)a.x, (double)a.y);
+    }
+}
+
+// complex128 in row (arc) order -> device state
+template <typename R>
+__global__ void k_graph_narrow(const double2 *__restrict__ in, cv<R> *__restrict__ out, int64_t n, int64_t nv,
+                               int sm_d) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         cv<R> v;
         v.x = (R)in[i].x;
         v.y = (R)in[i].y;
-        out[i] = v;
+        out[state_index(i, nv, sm_d)] = v;
     }
 }
 
@@ -171,6 +254,7 @@ using namespace qw;
 struct qw_graph {
     int64_t nv = 0, narcs = 0;
     int32_t max_degree = 0;
+    int32_t sm_d = 0;        // > 0: slot-major state of this (regular) degree
     int prec = QW_C128;
     int kind = QW_COIN_GROVER;
     hipStream_t stream = nullptr;
@@ -322,10 +406,10 @@ int set_state(qw_graph *g, const double *psi0) {
         const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
         if (g->prec == QW_C128)
             hipLaunchKernelGGL(k_graph_narrow<double>, dim3(blocks), dim3(256), 0, g->stream, (const double2 *)tmp,
-                               (double2 *)g->psi[0], n);
+                               (double2 *)g->psi[0], n, g->nv, g->sm_d);
         else
             hipLaunchKernelGGL(k_graph_narrow<float>, dim3(blocks), dim3(256), 0, g->stream, (const double2 *)tmp,
-                               (float2 *)g->psi[0], n);
+                               (float2 *)g->psi[0], n, g->nv, g->sm_d);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
@@ -340,10 +424,10 @@ int launch_prob(qw_graph *g, double *P) {
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGraphRedBlocks, (g->nv + 255) / 256));
     if (g->prec == QW_C128)
         hipLaunchKernelGGL(k_graph_prob<double>, dim3(blocks), dim3(256), 0, g->stream, (const double2 *)g->psi[g->cur],
-                           (const int32_t *)g->off, g->nv, P, g->partial);
+                           (const int32_t *)g->off, g->nv, P, g->partial, g->sm_d);
     else
         hipLaunchKernelGGL(k_graph_prob<float>, dim3(blocks), dim3(256), 0, g->stream, (const float2 *)g->psi[g->cur],
-                           (const int32_t *)g->off, g->nv, P, g->partial);
+                           (const int32_t *)g->off, g->nv, P, g->partial, g->sm_d);
     hipLaunchKernelGGL(k_graph_reduce, dim3(1), dim3(256), 0, g->stream, (const double *)g->partial, (int)blocks,
                        g->norm);
     QG_HIP(hipGetLastError(), "probability kernel");
@@ -384,6 +468,21 @@ int graph_walk_create(int64_t nv, const int64_t *offsets, const int64_t *targets
     std::vector<int32_t> rev;
     int rc = pair_arcs(nv, offsets, targets, rev);
     if (rc) return rc;
+    // regular graph of small degree: slot-major state, rev in slot-major indices
+    int32_t sm_d = 0;
+    if (maxd >= 1 && maxd <= kSlotMajorDegree && narcs == nv * maxd) {
+        bool regular = true;
+        for (int64_t v = 0; v < nv && regular; ++v) regular = offsets[v + 1] - offsets[v] == maxd;
+        if (regular) {
+            sm_d = (int32_t)maxd;
+            std::vector<int32_t> rsm((size_t)narcs);
+            for (int64_t k = 0; k < narcs; ++k) {
+                const int64_t r = rev[(size_t)k];
+                rsm[(size_t)((k % maxd) * nv + k / maxd)] = (int32_t)((r % maxd) * nv + r / maxd);
+            }
+            rev.swap(rsm);
+        }
+    }
     std::vector<double> tab;
     std::vector<int32_t> toff;
     if (coin_kind != QW_COIN_GROVER) {
@@ -400,6 +499,7 @@ int graph_walk_create(int64_t nv, const int64_t *offsets, const int64_t *targets
     g->nv = nv;
     g->narcs = narcs;
     g->max_degree = (int32_t)maxd;
+    g->sm_d = sm_d;
     g->prec = prec;
     g->kind = coin_kind;
     g->stream = (hipStream_t)stream;
@@ -476,7 +576,23 @@ int graph_walk_step(qw_graph_t g, int64_t T) {
     for (int64_t s = 0; s < T; ++s) {
         const void *in = g->psi[g->cur];
         void *out = g->psi[g->cur ^ 1];
-        if (g->kind == QW_COIN_GROVER) {
+        if (g->sm_d > 0 && g->kind == QW_COIN_GROVER) {
+            if (g->prec == QW_C128)
+                hipLaunchKernelGGL(k_graph_grover_sm<double>, dim3(blocks), dim3(256), 0, g->stream,
+                                   (const double2 *)in, (double2 *)out, (const int32_t *)g->rev, g->nv, g->sm_d);
+            else
+                hipLaunchKernelGGL(k_graph_grover_sm<float>, dim3(blocks), dim3(256), 0, g->stream, (const float2 *)in,
+                                   (float2 *)out, (const int32_t *)g->rev, g->nv, g->sm_d);
+        } else if (g->sm_d > 0) {
+            if (g->prec == QW_C128)
+                hipLaunchKernelGGL(k_graph_table_sm<double>, dim3(blocks), dim3(256), 0, g->stream,
+                                   (const double2 *)in, (double2 *)out, (const int32_t *)g->rev, g->nv, g->sm_d,
+                                   (const double2 *)g->table, (const int32_t *)g->toff);
+            else
+                hipLaunchKernelGGL(k_graph_table_sm<float>, dim3(blocks), dim3(256), 0, g->stream, (const float2 *)in,
+                                   (float2 *)out, (const int32_t *)g->rev, g->nv, g->sm_d, (const float2 *)g->table,
+                                   (const int32_t *)g->toff);
+        } else if (g->kind == QW_COIN_GROVER) {
             if (g->prec == QW_C128)
                 hipLaunchKernelGGL(k_graph_grover<double>, dim3(blocks), dim3(256), 0, g->stream, (const double2 *)in,
                                    (double2 *)out, (const int32_t *)g->off, (const int32_t *)g->rev, g->nv);
@@ -540,10 +656,10 @@ int graph_walk_get_state(qw_graph_t g, double *out, int32_t out_on_device) {
     const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
     if (g->prec == QW_C128)
         hipLaunchKernelGGL(k_graph_widen<double>, dim3(blocks), dim3(256), 0, g->stream, (const double2 *)g->psi[g->cur],
-                           dst, n);
+                           dst, n, g->nv, g->sm_d);
     else
         hipLaunchKernelGGL(k_graph_widen<float>, dim3(blocks), dim3(256), 0, g->stream, (const float2 *)g->psi[g->cur],
-                           dst, n);
+                           dst, n, g->nv, g->sm_d);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && !out_on_device) {
         e = hipMemcpyAsync(out, dst, sizeof(double2) * n, hipMemcpyDeviceToHost, g->stream);
@@ -559,12 +675,13 @@ int graph_walk_info(qw_graph_t g, qw_graph_info *out) {
     out->nv = g->nv;
     out->narcs = g->narcs;
     out->max_degree = g->max_degree;
+    out->layout = g->sm_d > 0 ? 1 : 0;
     out->t = g->t;
     out->launches = g->launches;
     out->step_ms = g->step_ms;
     // per step: every arc's amplitude read and written once, its reverse index
-    // read; every vertex's two row offsets
-    out->bytes_per_step = (double)g->narcs * (2.0 * (double)esz(g) + 4.0) + (double)(g->nv + 1) * 4.0;
+    // read; the row offsets (row layout only)
+    out->bytes_per_step = (double)g->narcs * (2.0 * (double)esz(g) + 4.0) + (g->sm_d > 0 ? 0.0 : (double)(g->nv + 1) * 4.0);
     return QW_OK;
 }
 

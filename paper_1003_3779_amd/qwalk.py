@@ -44,7 +44,7 @@ KERNEL_NAMES = ("step", "ring_whole", "ring_tiles", "stream2d")
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("narcs", ctypes.c_int64), ("max_degree", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("t", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("layout", ctypes.c_int32), ("t", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("step_ms", ctypes.c_double), ("bytes_per_step", ctypes.c_double)]
 
 

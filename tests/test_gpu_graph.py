@@ -139,3 +139,64 @@ def test_reset_and_zero_steps():
     ref = oracle.graph_evolve(off, tgt, oracle.GROVER, psi, 7)
     assert np.max(np.abs(g.get_state() - ref)) <= TOL64
     g.destroy()
+
+
+def _regular(rng, nv, d):
+    """A d-regular multigraph on nv (even) vertices: the union of d random
+    perfect matchings (parallel edges allowed), rows shuffled."""
+    rows = [[] for _ in range(nv)]
+    for _ in range(d):
+        p = rng.permutation(nv)
+        for a, b in zip(p[0::2], p[1::2]):
+            rows[a].append(int(b))
+            rows[b].append(int(a))
+    for r in rows:
+        rng.shuffle(r)
+    off = np.arange(0, d * nv + 1, d, dtype=np.int64)
+    tgt = np.array([w for r in rows for w in r], dtype=np.int64)
+    return off, tgt
+
+
+@pytest.mark.parametrize("kind", [qwalk.GROVER, qwalk.FOURIER, qwalk.DENSE])
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+@pytest.mark.parametrize("d", [1, 3, 8])
+def test_regular_graph_slot_major_equals_rows_bitwise(kind, prec, d):
+    """Regular graphs of degree <= 8 are held slot-major; the same graph with
+    one isolated vertex appended is not regular and keeps the row layout.  The
+    per-vertex arithmetic is the same: states, P and norms agree bit for bit,
+    and both agree with the oracle."""
+    rng = np.random.default_rng(100 * d + kind + 7 * prec)
+    nv = 2 * 301
+    off, tgt = _regular(rng, nv, d)
+    off_iso = np.append(off, off[-1])                   # vertex nv: no arcs
+    dense = [inputs.haar_unitary(rng, k) for k in range(1, d + 1)] if kind == qwalk.DENSE else None
+    psi = _state(rng, tgt.size)
+    T = 29
+    P1, s1, n1, i1 = _run(off, tgt, kind, psi, T, prec, dense=dense)
+    P0, s0, n0, i0 = _run(off_iso, tgt, kind, psi, T, prec, dense=dense)
+    assert i1.layout == 1 and i0.layout == 0
+    assert np.array_equal(s1, s0)
+    assert np.array_equal(P1, P0[:nv]) and P0[nv] == 0.0
+    assert n1 == n0
+    okind = {qwalk.GROVER: oracle.GROVER, qwalk.FOURIER: oracle.FOURIER, qwalk.DENSE: oracle.DENSE}[kind]
+    ref = oracle.graph_evolve(off, tgt, okind, psi, T, dense=dense)
+    Pref = oracle.graph_prob(off, ref)
+    if prec == qwalk.QW_C128:
+        assert np.max(np.abs(s1 - ref)) <= TOL64
+        assert np.max(np.abs(P1 - Pref)) <= TOL64
+    else:
+        assert np.max(np.abs(P1 - Pref)) <= TOL32_P
+
+
+def test_layout_by_degree():
+    """Slot-major up to degree 8; a 9-regular graph keeps the row layout and
+    still matches the oracle."""
+    rng = np.random.default_rng(9)
+    for d, layout in ((8, 1), (9, 0)):
+        off, tgt = _regular(rng, 64, d)
+        psi = _state(rng, tgt.size)
+        P, s, n, info = _run(off, tgt, qwalk.GROVER, psi, 13, qwalk.QW_C128)
+        assert info.layout == layout
+        ref = oracle.graph_evolve(off, tgt, oracle.GROVER, psi, 13)
+        assert np.max(np.abs(s - ref)) <= TOL64
+        assert abs(n - 1.0) <= TOL64
