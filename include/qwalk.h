@@ -334,8 +334,10 @@ int walk_batch_binned(qw_batch_t b, float *out, int32_t out_on_device);
 /* sum_i N[i] doubles: walk i's P(x) at offset N[0] + ... + N[i-1]. */
 int walk_batch_probabilities(qw_batch_t b, double *out, int32_t out_on_device);
 int walk_batch_info(qw_batch_t b, qw_batch_info *out);
-/* Autotuner: per size bucket, time every tiled variant on `samples` walks of
- * the bucket (spread over their work) and keep the fastest; save != 0 writes
+/* Autotuner: per size bucket, time every tiled variant (one run each, after
+ * one warm-up run) on `samples` walks of the bucket (spread over their work,
+ * the heaviest included: its time bounds the run's) and keep the fastest;
+ * synchronises; on a bucket of rings near 1e6 sites this takes minutes.  save != 0 writes
  * the choice to the tuning cache ($QWALK_TUNE_CACHE, else
  * ~/.cache/qwalk_tune.txt), read by later walk_batch_create calls on the same
  * device and precision.  Overwrites outputs until the next walk_batch_run. */

@@ -1077,10 +1077,11 @@ int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save) {
             (void)hipFree(dw);
             return bfail(QW_ENOMEM, "hipMalloc for tuning failed");
         }
-        for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+        // one warm-up run (the bucket's current variant), then one timed run per variant
+        for (int cfg = -1; cfg < kNumCfg; ++cfg) {
             for (size_t s = 0; s < pick.size(); ++s) {
                 tw[s] = b->walks[pick[s]];
-                tw[s].cfg = cfg;
+                tw[s].cfg = cfg < 0 ? b->bucket_cfg[bk] : cfg;
                 torder[s] = (int32_t)s;
             }
             hipError_t e = hipMemcpyAsync(dw, tw.data(), sizeof(WalkDesc) * tw.size(), hipMemcpyHostToDevice, b->stream);
@@ -1091,7 +1092,16 @@ int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save) {
             const BatchArgs A = make_args(b, dw, dord, (int32_t)pick.size(), (int32_t)pick.size());
             const int grid = std::min<int>(b->grid, (int)pick.size());
             float ms = 0.0f;
-            if (e == hipSuccess) e = enqueue(b, A, grid);  // warm-up
+            if (cfg < 0) {
+                if (e == hipSuccess) e = enqueue(b, A, grid);
+                if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                if (e != hipSuccess) {
+                    (void)hipFree(dw);
+                    (void)hipFree(dord);
+                    return bfail(QW_EHIP, "tuning warm-up run: %s", hipGetErrorString(e));
+                }
+                continue;
+            }
             if (e == hipSuccess) e = hipEventRecord(b->ev[0], b->stream);
             if (e == hipSuccess) e = enqueue(b, A, grid);
             if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
