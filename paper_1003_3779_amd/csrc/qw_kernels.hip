@@ -219,6 +219,86 @@ __global__ __launch_bounds__(1024) void k_ring_whole(const cv<R> *__restrict__ i
 }
 
 // =====================================================================
+// a small ring (no broken links): four waves, windows with halos
+// =====================================================================
+// The ring lives in LDS.  Wave w (one per SIMD) owns the I = ceil(N/4) sites
+// from w*I and holds the window of 64*M sites starting kRingHalo sites before
+// them in registers (M per lane; a window longer than the ring repeats it,
+// which is the ring unrolled).  It takes up to kRingHalo steps with only
+// cross-lane moves -- a step spoils one more site at each window end -- then
+// writes its own sites back to LDS; two barriers per kRingHalo steps instead of
+// one per step.  The per-site arithmetic is k_ring_whole's (bitwise equal).
+constexpr int kRingHalo = 32;
+template <typename R, int M, bool REALC>
+__global__ __launch_bounds__(256) void k_ring_halo(const cv<R> *__restrict__ in, cv<R> *__restrict__ out, int N,
+                                                   int64_t ps, int64_t K, CoinR<R> C) {
+    constexpr int kMax = 32768 / (int)sizeof(cv<R>);  // 2 planes: 64 KiB of LDS
+    __shared__ cv<R> S0[kMax];
+    __shared__ cv<R> S1[kMax];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int x = threadIdx.x; x < N; x += 256) {
+        S0[x] = in[x];
+        S1[x] = in[ps + x];
+    }
+    __syncthreads();
+    const int I = (N + 3) / 4;
+    const int own0 = w * I;                          // first owned site
+    const int own1 = min(N, own0 + I);               // one past the last
+    int ws = (own0 - kRingHalo) % N;                 // window start (site)
+    ws = ws < 0 ? ws + N : ws;
+    const R c00r = C.re[0], c00i = C.im[0], c01r = C.re[1], c01i = C.im[1];
+    const R c10r = C.re[2], c10i = C.im[2], c11r = C.re[3], c11i = C.im[3];
+    cv<R> a0[M], a1[M];
+    for (int64_t done = 0; done < K; done += kRingHalo) {
+        const int h = K - done < kRingHalo ? (int)(K - done) : kRingHalo;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int x = (ws + lane * M + m) % N;
+            a0[m] = S0[x];
+            a1[m] = S1[x];
+        }
+        for (int st = 0; st < h; ++st) {
+            const cv<R> left = from_left<R>(a0[M - 1]);
+            const cv<R> right = from_right<R>(a1[0]);
+            cv<R> n0[M], n1[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const cv<R> g0 = m == 0 ? left : a0[m == 0 ? 0 : m - 1];
+                const cv<R> g1 = m == M - 1 ? right : a1[m == M - 1 ? m : m + 1];
+                if constexpr (REALC) {
+                    n0[m].x = fmaR(c01r, g1.x, c00r * g0.x);
+                    n0[m].y = fmaR(c01r, g1.y, c00r * g0.y);
+                    n1[m].x = fmaR(c11r, g1.x, c10r * g0.x);
+                    n1[m].y = fmaR(c11r, g1.y, c10r * g0.y);
+                } else {
+                    n0[m] = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
+                    n1[m] = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                a0[m] = n0[m];
+                a1[m] = n1[m];
+            }
+        }
+        __syncthreads();  // every window read before any owned site is overwritten
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int x = own0 + lane * M + m - kRingHalo;  // window position -> site
+            if (x >= own0 && x < own1) {
+                S0[x] = a0[m];
+                S1[x] = a1[m];
+            }
+        }
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < N; x += 256) {
+        out[x] = S0[x];
+        out[ps + x] = S1[x];
+    }
+}
+
+// =====================================================================
 // a long ring: K steps per launch in wave-sized register tiles
 // =====================================================================
 // Each wave loads 64*M consecutive sites (M per lane) of both planes, steps
@@ -874,6 +954,47 @@ static void ring_whole_t(const void *in, void *out, const Geom &g, const CoinF64
 #undef QW_RING_WHOLE
 }
 
+// sites per lane of the four-wave halo kernel: the smallest listed M whose
+// window holds a quarter of the ring plus both halos (0: the ring is too long)
+static int ring_halo_m(int prec, int64_t N) {
+    static const int mc128[] = {2, 4, 6, 8, 10}, mc64[] = {2, 4, 8, 12, 16, 18};
+    const int64_t kmax = prec == C128 ? 2048 : 4096;  // the ring in 64 KiB of LDS
+    if (N < 1 || N > kmax) return 0;
+    const int64_t I = (N + 3) / 4;
+    const int *ms = prec == C128 ? mc128 : mc64;
+    const int nm = prec == C128 ? 5 : 6;
+    for (int i = 0; i < nm; ++i)
+        if (64LL * ms[i] >= I + 2 * kRingHalo) return ms[i];
+    return 0;
+}
+
+template <typename R>
+static bool ring_halo_t(int m, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
+                        hipStream_t s) {
+    const bool real = C.im[0] == 0.0 && C.im[1] == 0.0 && C.im[2] == 0.0 && C.im[3] == 0.0;
+#define QW_RING_HALO(MV)                                                                                  \
+    do {                                                                                                  \
+        if (real)                                                                                         \
+            hipLaunchKernelGGL((k_ring_halo<R, MV, true>), dim3(1), dim3(256), 0, s, (const cv<R> *)in,   \
+                               (cv<R> *)out, g.Lx, g.ps, K, to_coin<R>(C));                               \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_ring_halo<R, MV, false>), dim3(1), dim3(256), 0, s, (const cv<R> *)in,  \
+                               (cv<R> *)out, g.Lx, g.ps, K, to_coin<R>(C));                               \
+    } while (0)
+    switch (m) {
+    case 2: QW_RING_HALO(2); return true;
+    case 4: QW_RING_HALO(4); return true;
+    case 6: if constexpr (sizeof(R) == 8) { QW_RING_HALO(6); return true; } return false;
+    case 8: QW_RING_HALO(8); return true;
+    case 10: if constexpr (sizeof(R) == 8) { QW_RING_HALO(10); return true; } return false;
+    case 12: if constexpr (sizeof(R) == 4) { QW_RING_HALO(12); return true; } return false;
+    case 16: if constexpr (sizeof(R) == 4) { QW_RING_HALO(16); return true; } return false;
+    case 18: if constexpr (sizeof(R) == 4) { QW_RING_HALO(18); return true; } return false;
+    default: return false;
+    }
+#undef QW_RING_HALO
+}
+
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
                              hipStream_t s, LaunchInfo *info, const Links *links, int64_t t0) {
     const int m = ring_whole_m(prec, g.Lx);
@@ -882,6 +1003,15 @@ hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
         const double bytes = (double)g.Lx * 2 * (prec == C128 ? 16.0 : 8.0);
         info->bytes_read = bytes;
         info->bytes_written = bytes;
+    }
+    if (!links) {
+        const int mh = ring_halo_m(prec, g.Lx);
+        if (mh > 0) {
+            const bool ok = prec == C128 ? ring_halo_t<double>(mh, in, out, g, C, K, s)
+                                         : ring_halo_t<float>(mh, in, out, g, C, K, s);
+            if (!ok) return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
     }
     if (prec == C128) {
         switch (m) {

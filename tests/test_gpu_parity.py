@@ -411,6 +411,40 @@ def test_fourier_workloads_full_size(name):
 
 
 @pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+@pytest.mark.parametrize("real", [True, False])
+def test_small_ring_halo_kernel_bitwise(prec, real):
+    """Rings of up to 2048 (c128) / 4096 (c64) sites run in four waves with
+    32-site halos, exchanging through LDS every 32 steps: bit for bit the one-step
+    kernel's amplitudes, for rings shorter than a wave's window (repeated in it),
+    block boundaries inside and between the pieces a walk is stepped in, and
+    both coin paths; c128 also against the oracle."""
+    sizes = [1, 2, 3, 5, 63, 64, 65, 255, 256, 257, 600, 1000, 2001, 2048]
+    if prec == qwalk.QW_C64:
+        sizes += [2049, 3000, 4096]
+    for N in sizes:
+        rng = np.random.default_rng(N + 3 * real + 7 * prec)
+        if real:
+            th = float(rng.uniform(0, np.pi))
+            U = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]], dtype=np.complex128)
+        else:
+            U = inputs.haar_unitary(rng, 2)
+        psi0 = inputs.haar_state(rng, 2)
+        x0 = (int(rng.integers(0, N)), 0)
+        res = []
+        for depth in (1, 0):
+            w = qwalk.Walk((N,), inputs.RING, qwalk.DENSE, psi0, x0, prec=prec, dense=U)
+            w.set_options(block_depth=depth, renorm_every=0)
+            for n in (7, 1, 25, 0, 64, 33):
+                w.step(n)
+            res.append(w.get_state())
+            w.destroy()
+        assert np.array_equal(res[0], res[1]), N
+        if prec == qwalk.QW_C128:
+            _, psir = _oracle_run((N,), inputs.RING, U, psi0, x0, 130)
+            assert np.max(np.abs(_as_oracle_layout(res[1]) - psir)) <= TOL64, N
+
+
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
 def test_ring_real_coin_bitwise(prec):
     """Real coins (Hadamard, real rotations) take a real-arithmetic path in the
     whole-ring kernel: the same amplitudes as one step per launch (complex
