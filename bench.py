@@ -654,6 +654,14 @@ def main():
     u1 = w.stats().updates
     prof = w.profile(reset=True)
     w.set_options(profile=0)
+    # the same walks again without the per-launch HIP events that time the
+    # kernel live above: on small workloads their host cost shows in the walk time
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        one_walk()
+    torch.cuda.synchronize()
+    ms_unprofiled = 1e3 * (time.perf_counter() - t2) / args.steps
     elapsed = t1 - t0
     updates_per_walk = (u1 - u0) / args.steps
     ms_per_step = 1e3 * elapsed / args.steps
@@ -694,7 +702,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == qwalk.QW_C128 else "f32",
-        "data": "synthetic",
+        "data": "synthetic", "ms_per_step_without_launch_events": round(ms_unprofiled, 3),
         "config": {"workload": f"{args.workload}: {'x'.join(str(e) for e in ext)} "
                                f"{'ring' if cfg['dim'] == 1 else 'torus'}, T={T}, {prec_name}",
                    "lattice": list(ext), "T": T, "coin_dim": d, "precision": prec_name,

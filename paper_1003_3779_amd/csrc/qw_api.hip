@@ -319,25 +319,40 @@ hipEvent_t take_event(qw_walk *w) {
 }
 
 // Opens a profiled launch: records the start event when profiling is on.
+// attach: the launch stamps the two events itself (start(), stop() passed to
+// it); otherwise events are recorded on the stream around the launch
 struct Timed {
     qw_walk *w;
-    hipEvent_t a = nullptr;
-    explicit Timed(qw_walk *w_) : w(w_) {
-        if (w->opt.profile) {
-            a = take_event(w);
-            if (a) (void)hipEventRecord(a, w->stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    bool attached = false;
+    explicit Timed(qw_walk *w_, bool attach = false) : w(w_) {
+        if (!w->opt.profile) return;
+        a = take_event(w);
+        if (!a) return;
+        if (attach) {
+            b = take_event(w);
+            if (b) {
+                attached = true;
+                return;
+            }
         }
+        (void)hipEventRecord(a, w->stream);
     }
+    hipEvent_t start() const { return attached ? a : nullptr; }
+    hipEvent_t stop() const { return attached ? b : nullptr; }
     void done(int kind, const LaunchInfo &li, double updates) {
         if (!a) return;
-        hipEvent_t b = take_event(w);
-        if (!b) {
-            w->spare.push_back(a);
-            return;
+        if (!attached) {
+            b = take_event(w);
+            if (!b) {
+                w->spare.push_back(a);
+                a = nullptr;
+                return;
+            }
+            (void)hipEventRecord(b, w->stream);
         }
-        (void)hipEventRecord(b, w->stream);
         w->pending.push_back({a, b, kind, li.bytes_read, li.bytes_written, updates});
-        a = nullptr;
+        a = b = nullptr;
     }
 };
 
@@ -366,14 +381,16 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     }
     const Box b = state_box(w);
     LaunchInfo li;
-    Timed tm(w);
+    Timed tm(w, !ring && b.wx > 0 && b.wy > 0);  // (an empty box launches nothing)
     if (ring)
         QW_HIP(launch_ring_tiles(w->prec, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream, &li),
                "ring tile kernel");
     else
     {
         const int linear = w->opt.block_order == 1;
-        const StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
+        StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
+        tu.ev_start = tm.start();
+        tu.ev_stop = tm.stop();
         QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
                                w->stream, &li, links, w->t),
                "2D streaming kernel");

@@ -93,6 +93,9 @@ struct StreamTune {
     int prefetch;  // input rows read ahead, in registers: 1 or 3
     int waves;     // waves to launch (0 = default)
     int linear;    // 1: blocks take strips in launch order; 0: XCD-aware order
+    // non-null: events that the launch itself stamps with the kernel's start and
+    // end (no separate event packets around it)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 // links != NULL: the walk has broken links / walls; t0 = its time at the launch
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out,

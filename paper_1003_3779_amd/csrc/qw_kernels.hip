@@ -23,6 +23,8 @@
 // a box growing by one site per step are exactly zero.  Kernels take the
 // box they must write; both buffers are zero outside the boxes ever written.
 #include "qw_internal.h"
+
+#include <hip/hip_ext.h>
 #include "qw_device.h"
 
 #include <math.h>
@@ -1106,14 +1108,26 @@ static void stream_t(const void *in, void *out, const Geom &g, const Box &b, con
     if (sl) {
         // broken links: one read-ahead row (the generator's registers take the place of the others)
         if constexpr (PD == 1)
-            hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, 1, true>), dim3((unsigned)blocks), dim3(256), 0, s,
-                               (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), *sl,
-                               tu.linear ? 0 : 1);
+        {
+            if (tu.ev_start)
+                hipExtLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, 1, true>), dim3((unsigned)blocks), dim3(256),
+                                      0, s, tu.ev_start, tu.ev_stop, 0u, (const cv<R> *)in, (cv<R> *)out, g, b,
+                                      seg_rows, nstrips, to_coin<R>(C), *sl, tu.linear ? 0 : 1);
+            else
+                hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, 1, true>), dim3((unsigned)blocks), dim3(256),
+                                   0, s, (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C),
+                                   *sl, tu.linear ? 0 : 1);
+        }
         return;
     }
-    hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), StreamLinks{},
-                       tu.linear ? 0 : 1);
+    if (tu.ev_start)
+        hipExtLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
+                              tu.ev_start, tu.ev_stop, 0u, (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows,
+                              nstrips, to_coin<R>(C), StreamLinks{}, tu.linear ? 0 : 1);
+    else
+        hipLaunchKernelGGL((k_stream2d<R, K, M, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips, to_coin<R>(C), StreamLinks{},
+                           tu.linear ? 0 : 1);
 }
 
 template <typename R, int K, int M, int TABLE, int PD>
