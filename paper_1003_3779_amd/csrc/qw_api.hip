@@ -381,7 +381,10 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     }
     const Box b = state_box(w);
     LaunchInfo li;
-    Timed tm(w, !ring && b.wx > 0 && b.wy > 0);  // (an empty box launches nothing)
+    // large launches stamp their own timing events (no event packets between
+    // kernels); small ones, whose host enqueue time shows, get events recorded
+    // around them, which the host issues faster (an empty box launches nothing)
+    Timed tm(w, !ring && b.wx > 0 && b.wy > 0 && box_sites(b) >= (int64_t)1 << 18);
     if (ring)
         QW_HIP(launch_ring_tiles(w->prec, cur_buf(w), oth_buf(w), w->g, b, w->C, K, w->stream, &li),
                "ring tile kernel");
