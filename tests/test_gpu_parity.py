@@ -464,3 +464,38 @@ def test_ring_real_coin_bitwise(prec):
         if prec == qwalk.QW_C128:
             Pr, psir = _oracle_run((N,), inputs.RING, oc, psi0, x0, T)
             assert np.max(np.abs(_as_oracle_layout(res[1]) - psir)) <= TOL64
+
+
+def test_live_kernel_timing_leaves_results_and_counts_every_launch():
+    """With the profile option on, large stream launches stamp their own timing
+    events and small ones are bracketed by recorded events: the amplitudes are
+    those of the untimed walk bit for bit, every launch is counted once, and
+    every timed kernel reports a positive time."""
+    import time
+    import torch
+    L, T = 1024, 300                                    # boxes grow past 2^18 sites
+    psi0 = inputs.haar_state(np.random.default_rng(21), 4)
+    res, profs = [], []
+    for prof in (0, 1):
+        w = qwalk.Walk((L, L), inputs.PAIR, qwalk.GROVER, psi0, (L // 2, L // 2), prec=qwalk.QW_C128)
+        w.set_options(profile=prof)
+        w.profile(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w.step(T)
+        torch.cuda.synchronize()
+        wall_ms = 1e3 * (time.perf_counter() - t0)
+        p = w.profile(reset=True)
+        st = w.stats()
+        res.append(w.get_state())
+        profs.append((p, st, wall_ms))
+        w.destroy()
+    assert np.array_equal(res[0], res[1])
+    p, st, wall_ms = profs[1]
+    assert sum(k["launches"] for k in p.values()) == st.launches
+    assert p["stream2d"]["launches"] > 0
+    for name, k in p.items():
+        if k["launches"]:
+            assert k["ms"] > 0.0, name
+    assert sum(k["ms"] for k in p.values()) <= wall_ms
+    assert sum(k["launches"] for k in profs[0][0].values()) == 0     # profile off: nothing timed
