@@ -135,6 +135,9 @@ typedef struct {
     double bytes_read;      /* HBM bytes the launches read by construction (state incl. halo) */
     double bytes_written;   /* HBM bytes the launches wrote */
     double updates;         /* site*coin updates of the walk those launches advanced */
+    double min_bytes;       /* the least those launches must move: each launch's input
+                               (light-cone box of the state it starts from) read once and
+                               its output box written once, no halo re-reads */
 } qw_kernel_profile;
 
 typedef struct {

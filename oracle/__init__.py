@@ -17,13 +17,20 @@ Functions and the passages they follow (see ``qw_oracle.c`` for the details):
   norm(P)                   sum_x P(x)
   bin_ring(P, x0, nbins)    symmetric binning of a ring distribution
   philox(ctr, key)          Philox4x32-10 (the random source of the broken links)
-  rbl_threshold(p)          floor(p * 2^32): a link is broken when Philox's word 0 is below it
+  rbl_threshold(p)          floor(p * 2^32): a link is broken when its Philox output word
+                            (word 2 (y & 1) + pair of the call of its row pair) is below it
   evolve_rbl(psi, ...)      T steps with random broken links, Sec. 3 Eqs. (9)-(10), and
                             the finite segment / box with reflecting walls (Fig. 3)
   graph_reverse(off, tgt)   the other end of every arc's edge (general graphs)
   graph_evolve(off, tgt, kind, psi, T)  T steps of U = S (I (x) C) on a general graph,
                             Sec. 2.1 Eqs. (1)-(3) (one amplitude per arc)
   graph_prob(off, psi)      P(v) = sum over v's arcs of |psi|^2
+  set_threads(n)            threads of the site loops (OpenMP; results are bitwise
+                            independent of the count)
+
+The spectral ring walk (psi_T through the diagonalisation of U by the lattice
+Fourier transform) is in ``oracle.spectral``; the fp64 network of the learned
+surrogate in ``oracle.surrogate``.
 """
 from __future__ import annotations
 
@@ -49,7 +56,7 @@ def build(force: bool = True) -> str:
     if force or stale:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call([
-            "gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+            "gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
             _SRC, "-o", tmp, "-lm",
         ])
         os.replace(tmp, _LIB_PATH)
@@ -83,6 +90,8 @@ def _open(path: str):
     lib.orc_graph_evolve.restype = i32
     lib.orc_graph_prob.argtypes = [i64, dp, dp, dp]
     lib.orc_graph_prob.restype = None
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_set_threads.restype = i32
     return lib
 
 
@@ -92,6 +101,12 @@ def _load():
         build(force=False)                      # compiles when missing or older than the source
         _lib = _open(_LIB_PATH)
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's site loops; n <= 0 keeps the current setting
+    (the OpenMP default follows OMP_NUM_THREADS).  Returns the count in use."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):

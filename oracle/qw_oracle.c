@@ -34,11 +34,20 @@
  *   orc_philox         -- the Philox4x32-10 counter-based generator
  *   orc_evolve_rbl     -- T steps with random broken links (Sec. 3, Eqs. (9)-(10)),
  *                         optionally with reflecting walls (the finite segment)
+ *   orc_set_threads    -- threads of the site loops (OpenMP; 1 = serial)
+ *
+ * Threads.  Built with -fopenmp, the loops over lattice rows of one step (and
+ * of P(x)) are split among threads.  Every output element is still computed
+ * by one thread with the same expression in the same order, so the results
+ * are bit for bit those of the serial loops, for any thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double re, im; } cx;
 
@@ -56,6 +65,19 @@ static cx c_expi(double t) { cx r = { cos(t), sin(t) }; return r; }
 static int64_t wrap(int64_t v, int64_t L) {
     v %= L;
     return v < 0 ? v + L : v;
+}
+
+/* Threads of the site loops (OpenMP builds; a serial build ignores it).
+ * n <= 0 keeps the runtime's default (OMP_NUM_THREADS).  Returns the count
+ * now in use (1 in a serial build). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 enum { ORC_HADAMARD = 0, ORC_SU2 = 1, ORC_GROVER = 2, ORC_HADAMARD2 = 3, ORC_FOURIER = 4, ORC_DENSE = 5 };
@@ -145,6 +167,7 @@ static void one_step(int64_t Lx, int64_t Ly, int d, const int *disp, const cx *C
     int64_t xs, xn, ys, yn, i, j;
     axis_range(Lx, cx0, rx, &xs, &xn);
     axis_range(Ly, cy0, ry, &ys, &yn);
+#pragma omp parallel for schedule(static) private(i) if (xn * yn * d >= 4096)
     for (j = 0; j < yn; j++) {
         int64_t y = wrap(ys + j, Ly);
         for (i = 0; i < xn; i++) {
@@ -213,6 +236,7 @@ int orc_evolve_inverse(int64_t Lx, int64_t Ly, int d, const int *disp, const dou
     if (!b) return -1;
     for (s = 0; s < T; s++) {
         cx *tmp;
+#pragma omp parallel for schedule(static) private(x) if (Lx * Ly * d >= 4096)
         for (y = 0; y < Ly; y++)
             for (x = 0; x < Lx; x++) {
                 int c, cp;
@@ -241,6 +265,7 @@ int orc_evolve_inverse(int64_t Lx, int64_t Ly, int d, const int *disp, const dou
  * (normalisation constraint of Eqs. (4)-(6)). */
 void orc_prob(int64_t V, int d, const double *psi, double *P) {
     int64_t x;
+#pragma omp parallel for schedule(static) if (V >= 65536)
     for (x = 0; x < V; x++) {
         double s = 0.0;
         int c;

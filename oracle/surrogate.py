@@ -22,6 +22,13 @@ share to the bin that holds it (the binning of the ring distributions: bins of
 w = 8 sites, the start site half to each of the two middle bins).
 Loss: mean over the batch of KL(y || p) = sum_b y_b (log y_b - log p_b), with
 0 log 0 = 0.
+
+bf16=True rounds, as a bf16 matrix-core pipeline with fp32 accumulation must,
+the operands of every matrix product to bfloat16 (round to nearest even of
+their fp32 value): the hidden activations h1, h2, h3 that feed the next layer,
+and in the backward pass each layer's dZ where it enters the two products
+dZ^T H and dZ W (the bias gradients sum the unrounded dZ).  The inputs and the
+weights are rounded by the caller.  Everything else stays float64.
 """
 from __future__ import annotations
 
@@ -98,15 +105,23 @@ def resample_matrix(T: int, w: int = BIN_SITES) -> np.ndarray:
     return R
 
 
-def forward(p: dict, x: np.ndarray, T) -> dict:
+def bf16_round(v: np.ndarray) -> np.ndarray:
+    """v rounded to bfloat16 (nearest, ties to even) through its fp32 value, as float64."""
+    u = np.ascontiguousarray(np.asarray(v, dtype=np.float64).astype(np.float32)).view(np.uint32)
+    r = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
+    return r.view(np.float32).astype(np.float64)
+
+
+def forward(p: dict, x: np.ndarray, T, bf16: bool = False) -> dict:
     x = np.asarray(x, dtype=np.float64)
+    rnd = bf16_round if bf16 else (lambda v: v)
     a = {"x": x}
     a["z1"] = x @ p["W1"].T + p["b1"]
-    a["h1"] = np.maximum(a["z1"], 0.0)
+    a["h1"] = rnd(np.maximum(a["z1"], 0.0))
     a["z2"] = a["h1"] @ p["W2"].T + p["b2"]
-    a["h2"] = np.maximum(a["z2"], 0.0)
+    a["h2"] = rnd(np.maximum(a["z2"], 0.0))
     a["z3"] = a["h2"] @ p["W3"].T + p["b3"]
-    a["h3"] = np.maximum(a["z3"], 0.0)
+    a["h3"] = rnd(np.maximum(a["z3"], 0.0))
     a["z4"] = a["h3"] @ p["W4"].T + p["b4"]
     a["l"] = _conv(a["z4"].reshape(-1, 2, NBINS), p["cw"], p["cb"])
     m = a["l"].max(axis=1, keepdims=True)
@@ -124,14 +139,15 @@ def _kl_rows(y, pb):
     return np.sum(np.where(y > 0, y * (np.log(safe) - np.log(np.where(y > 0, pb, 1.0))), 0.0), axis=1)
 
 
-def loss(p: dict, x: np.ndarray, y: np.ndarray, T) -> float:
-    a = forward(p, x, T)
+def loss(p: dict, x: np.ndarray, y: np.ndarray, T, bf16: bool = False) -> float:
+    a = forward(p, x, T, bf16)
     return float(np.mean(_kl_rows(y, a["p"])))
 
 
-def backward(p: dict, x: np.ndarray, y: np.ndarray, T) -> dict:
+def backward(p: dict, x: np.ndarray, y: np.ndarray, T, bf16: bool = False) -> dict:
     """Gradients of loss() with respect to every parameter (chain rule written out)."""
-    a = forward(p, x, T)
+    a = forward(p, x, T, bf16)
+    rnd = bf16_round if bf16 else (lambda v: v)
     y = np.asarray(y, dtype=np.float64)
     B = x.shape[0]
     # dL/dp_b = -y_b / p_b; dL/dq = R^T dL/dp; softmax: dl = q (dq - <q, dq>)
@@ -150,19 +166,19 @@ def backward(p: dict, x: np.ndarray, y: np.ndarray, T) -> dict:
             g["cw"][c, j] = np.sum(dl * zp[:, c, j:j + NBINS])
             dzp[:, c, j:j + NBINS] += p["cw"][c, j] * dl
     dz4 = dzp[:, :, CONV_PAD:CONV_PAD + NBINS].reshape(B, 2 * NBINS)
-    g["W4"] = dz4.T @ a["h3"]
+    g["W4"] = rnd(dz4).T @ a["h3"]
     g["b4"] = dz4.sum(axis=0)
-    dh3 = dz4 @ p["W4"]
+    dh3 = rnd(dz4) @ p["W4"]
     dz3 = dh3 * (a["z3"] > 0)
-    g["W3"] = dz3.T @ a["h2"]
+    g["W3"] = rnd(dz3).T @ a["h2"]
     g["b3"] = dz3.sum(axis=0)
-    dh2 = dz3 @ p["W3"]
+    dh2 = rnd(dz3) @ p["W3"]
     dz2 = dh2 * (a["z2"] > 0)
-    g["W2"] = dz2.T @ a["h1"]
+    g["W2"] = rnd(dz2).T @ a["h1"]
     g["b2"] = dz2.sum(axis=0)
-    dh1 = dz2 @ p["W2"]
+    dh1 = rnd(dz2) @ p["W2"]
     dz1 = dh1 * (a["z1"] > 0)
-    g["W1"] = dz1.T @ a["x"]
+    g["W1"] = rnd(dz1).T @ a["x"]
     g["b1"] = dz1.sum(axis=0)
     return g
 

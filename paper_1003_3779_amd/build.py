@@ -3,13 +3,15 @@ from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libqwalk.so")
-SOURCES = ["qw_kernels.hip", "qw_api.hip", "qw_batch.hip", "qw_surrogate.hip", "qw_graph.hip"]
+SOURCES = ["qw_kernels.hip", "qw_api.hip", "qw_batch.hip", "qw_surrogate.hip", "qw_graph.hip",
+           "qw_static.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -25,16 +27,23 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile every HIP source into libqwalk.so (always recompiles)."""
-    objs = []
-    for src in SOURCES:
+def build_library(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every HIP source into libqwalk.so (always recompiles; the
+    sources compile in parallel, at most `jobs` at a time)."""
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    cmds, objs = [], []
+    for src in srcs:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    if jobs is None:
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(subprocess.check_call, cmd) for cmd in cmds]:
+            f.result()
     tmp = LIB_PATH + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -207,7 +207,7 @@ struct qw_walk {
     struct Pending {
         hipEvent_t a, b;
         int kind;
-        double bytes_read, bytes_written, updates;
+        double bytes_read, bytes_written, updates, min_bytes;
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> spare;
@@ -340,7 +340,8 @@ struct Timed {
     }
     hipEvent_t start() const { return attached ? a : nullptr; }
     hipEvent_t stop() const { return attached ? b : nullptr; }
-    void done(int kind, const LaunchInfo &li, double updates) {
+    // min_bytes: the launch's input box read once and output box written once
+    void done(int kind, const LaunchInfo &li, double updates, double min_bytes) {
         if (!a) return;
         if (!attached) {
             b = take_event(w);
@@ -351,20 +352,26 @@ struct Timed {
             }
             (void)hipEventRecord(b, w->stream);
         }
-        w->pending.push_back({a, b, kind, li.bytes_read, li.bytes_written, updates});
+        w->pending.push_back({a, b, kind, li.bytes_read, li.bytes_written, updates, min_bytes});
         a = b = nullptr;
     }
 };
 
 // one unblocked step
+// bytes of the boxes of n sites of the state (d components)
+double state_bytes_of(const qw_walk *w, int64_t sites) {
+    return (double)sites * w->d * (w->prec == QW_C128 ? 16.0 : 8.0);
+}
+
 int step1(qw_walk *w) {
+    const int64_t in_sites = box_sites(state_box(w));
     grow_forward(w, 1);
     const Box b = state_box(w);
     LaunchInfo li;
     Timed tm(w);
     QW_HIP(launch_step(w->prec, w->coin_impl, cur_buf(w), oth_buf(w), w->g, b, w->C, w->stream, &li),
            "step kernel");
-    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d);
+    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d, state_bytes_of(w, in_sites + box_sites(b)));
     w->cur ^= 1;
     w->launches++;
     w->updates += box_sites(b) * w->d;
@@ -374,6 +381,7 @@ int step1(qw_walk *w) {
 // K fused steps with a blocked kernel; returns QW_OK.  links: broken links /
 // walls of a torus walk (then w->t is the walk time at the launch)
 int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
+    const int64_t in_sites = box_sites(state_box(w));
     int64_t upd = 0;
     for (int s = 1; s <= K; ++s) {
         grow_forward(w, 1);
@@ -398,7 +406,8 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
                                w->stream, &li, links, w->t),
                "2D streaming kernel");
     }
-    tm.done(ring ? QW_KERNEL_RING_TILES : QW_KERNEL_STREAM2D, li, (double)upd);
+    tm.done(ring ? QW_KERNEL_RING_TILES : QW_KERNEL_STREAM2D, li, (double)upd,
+            state_bytes_of(w, in_sites + box_sites(b)));
     w->cur ^= 1;
     w->launches++;
     w->updates += upd;
@@ -445,13 +454,14 @@ int link_tables(const qw_walk *w, Links &L) {
 // one step with broken links: the pending shift (links of step t - 1), then the coin
 int step1_rbl(qw_walk *w) {
     const Links L = pending_links(w);
+    const int64_t in_sites = box_sites(state_box(w));
     grow_forward(w, 1);
     const Box b = state_box(w);
     LaunchInfo li;
     Timed tm(w);
     QW_HIP(launch_step_rbl(w->prec, w->coin_impl, cur_buf(w), oth_buf(w), w->g, b, w->C, L, w->stream, &li),
            "broken-link step kernel");
-    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d);
+    tm.done(QW_KERNEL_STEP, li, (double)box_sites(b) * w->d, state_bytes_of(w, in_sites + box_sites(b)));
     w->cur ^= 1;
     w->launches++;
     w->updates += box_sites(b) * w->d;
@@ -481,7 +491,7 @@ int run_forward(qw_walk *w, int64_t n) {
             Timed tm(w);
             QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li, &L, t0),
                    "ring kernel");
-            tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n);
+            tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n, state_bytes_of(w, 2 * w->g.Lx));
             w->cur ^= 1;
             w->launches++;
             w->updates += (int64_t)w->g.Lx * w->d * n;
@@ -518,7 +528,7 @@ int run_forward(qw_walk *w, int64_t n) {
         LaunchInfo li;
         Timed tm(w);
         QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li), "ring kernel");
-        tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n);
+        tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n, state_bytes_of(w, 2 * w->g.Lx));
         w->cur ^= 1;
         w->launches++;
         w->updates += (int64_t)w->g.Lx * w->d * n;
@@ -608,6 +618,7 @@ int drain_profile(qw_walk *w) {
         k.bytes_read += p.bytes_read;
         k.bytes_written += p.bytes_written;
         k.updates += p.updates;
+        k.min_bytes += p.min_bytes;
         w->spare.push_back(p.a);
         w->spare.push_back(p.b);
     }
@@ -659,7 +670,7 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     w->opt.prefetch_rows = 0;
     w->opt.stream_waves = 0;
     w->opt.block_order = 0;
-    for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0, 0.0};
     set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
 
@@ -766,7 +777,7 @@ int walk_profile(qw_walk_t w, qw_kernel_profile *out, int32_t reset) {
     if (rc) return rc;
     for (int k = 0; k < QW_KERNEL_KINDS; ++k) {
         out[k] = w->prof[k];
-        if (reset) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
+        if (reset) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0, 0.0};
     }
     return QW_OK;
 }

@@ -73,7 +73,7 @@ class Options(ctypes.Structure):
 
 class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes_read", ctypes.c_double),
-                ("bytes_written", ctypes.c_double), ("updates", ctypes.c_double)]
+                ("bytes_written", ctypes.c_double), ("updates", ctypes.c_double), ("min_bytes", ctypes.c_double)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -327,7 +327,7 @@ class Walk:
         out = {}
         for name, k in zip(KERNEL_NAMES, arr):
             out[name] = {"launches": k.launches, "ms": k.ms, "bytes_read": k.bytes_read,
-                         "bytes_written": k.bytes_written, "updates": k.updates}
+                         "bytes_written": k.bytes_written, "updates": k.updates, "min_bytes": k.min_bytes}
         return out
 
     def set_options(self, block_depth: int | None = None, window: int | None = None,

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import spectral
 from paper_1003_3779_amd import inputs, qwalk
 
 pytestmark = pytest.mark.gpu
@@ -177,7 +178,9 @@ def test_batch_ragged_rings_full_size():
     """The full ragged workload in the benchmark's launch (4096 rings, N odd in
     [1001, 999999], T in [256, N/2], PCG64 seed 4, complex64, 512 bins): every
     walk's norm and second moment; P and the bins of every walk with N < 1e4
-    against the oracle."""
+    against the oracle; P and the bins of a seeded sample of 20 rings with
+    N >= 1e4 -- the walk with the most steps among them -- against the spectral
+    oracle (the step-by-step one would take hours on them)."""
     import torch
     p = inputs.ragged_ring_batch(4, 4096)
     N, T = p["N"], p["T"]
@@ -200,6 +203,23 @@ def test_batch_ragged_rings_full_size():
         ref = _oracle_P(N[i], T[i], p["angles"][i], p["psi0"][i], N[i] // 2)
         assert np.max(np.abs(Pi - ref)) <= 2e-5, i
         assert np.max(np.abs(bins[i] - oracle.bin_ring(ref, int(N[i] // 2), 512))) <= 2e-5 + 1e-6, i
+    big = np.nonzero(N >= 10000)[0]
+    rng = np.random.Generator(np.random.PCG64(44))
+    sample = [int(big[np.argmax(T[big])])]
+    sample += [int(i) for i in rng.choice(np.setdiff1d(big, sample), size=19, replace=False)]
+    worst_P = worst_bins = 0.0
+    for i in sample:
+        Pi = flat[offs[i]:offs[i + 1]].cpu().numpy()
+        C = oracle.coin(oracle.SU2, 2, *p["angles"][i])
+        ref = spectral.ring_prob(int(N[i]), C, int(N[i] // 2), p["psi0"][i], int(T[i]))
+        bref = oracle.bin_ring(ref, int(N[i] // 2), 512)
+        eP, eb = np.max(np.abs(Pi - ref)), np.max(np.abs(bins[i] - bref))
+        worst_P, worst_bins = max(worst_P, eP), max(worst_bins, eb)
+        print(f"# ring {i}: N={N[i]} T={T[i]} max|dP| = {eP:.2e} (max P {ref.max():.2e}), "
+              f"max|dbin| = {eb:.2e}", flush=True)
+        assert eP <= 2e-5, i
+        assert eb <= 2e-5, i
+    print(f"# long rings: worst max|dP| = {worst_P:.2e}, worst max|dbin| = {worst_bins:.2e}", flush=True)
 
 
 def _oracle_rbl_P(N, T, ang, psi0, x0, p, seed, real, walls):

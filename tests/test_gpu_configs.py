@@ -1,0 +1,118 @@
+"""The benchmark workloads as configured, at full size and in the launch
+configuration the benchmark times, against the oracle element by element.
+
+* 4096^2 Grover torus (pair table), T = 2048, both starts -- the localising
+  (|0> - |1> - |2> + |3>)/2 and the uniform (1,1,1,1)/2 -- in complex128
+  (1e-12 on P) and complex64 (2e-5 on P after all 2048 steps), against the
+  light-cone oracle on the whole torus (its site loops on every host core).
+* 16384^2 H(x)H torus (pair table, Haar start of PCG64 seed 3, complex64 with
+  fp64 reductions, the default depth) on the whole lattice at T = 512, against
+  the oracle on a torus just wide enough for the light cone (the walk never
+  wraps, so the two agree site for site); nothing outside the cone.
+The ragged rings are checked in ``test_gpu_batch.py`` (long rings against the
+spectral oracle).  Expected values come from the oracle only.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_3779_amd import inputs, qwalk
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_P = 2e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    qwalk.load()
+    oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    yield
+
+
+_GROVER_CACHE = {}
+
+
+def _grover_oracle_P(name):
+    """P of the whole 4096^2 walk at T = 2048 from the light-cone oracle (cached
+    per start: the c128 and c64 tests share it)."""
+    if name not in _GROVER_CACHE:
+        cfg = inputs.config(name)
+        (Lx, Ly), T = cfg["extent"], cfg["T"]
+        print(f"# oracle: {name} {Lx}x{Ly} T={T} on {oracle.set_threads(0)} threads", flush=True)
+        psi = oracle.walk(Lx, Ly, cfg["disp"], oracle.coin(oracle.GROVER, 4), cfg["x0"], cfg["psi0"], T)
+        _GROVER_CACHE[name] = oracle.prob(psi)
+        del psi
+    return _GROVER_CACHE[name]
+
+
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+@pytest.mark.parametrize("name", ["grover2d", "grover2d_uniform"])
+def test_grover_4096_t2048_vs_oracle(name, prec):
+    """The whole benchmark walk (both starts, both precisions, library default
+    depth and launch shape) against the oracle after all 2048 steps."""
+    import torch
+    cfg = inputs.config(name)
+    ext, x0, T = cfg["extent"], cfg["x0"], cfg["T"]
+    print(f"# gpu: {name} prec={prec} T={T}", flush=True)
+    w = qwalk.Walk(ext, cfg["disp"], qwalk.GROVER, cfg["psi0"], x0, prec=prec)
+    w.step(T)
+    P = torch.empty((ext[1], ext[0]), dtype=torch.float64, device="cuda")
+    w.probabilities(out=P)
+    n = w.norm()
+    st = w.stats()
+    w.destroy()
+    Pr = torch.from_numpy(_grover_oracle_P(name)).cuda()
+    err = torch.max(torch.abs(P - Pr)).item()
+    print(f"# {name} prec={prec}: max|dP| = {err:.3e}, norm error {abs(n - 1.0):.2e}", flush=True)
+    if prec == qwalk.QW_C128:
+        assert err <= TOL64
+        assert abs(n - 1.0) <= TOL64
+    else:
+        assert err <= TOL32_P
+        assert abs(n - 1.0) <= 1e-5
+        assert st.renorm_checks == T // 64
+    del P, Pr
+    torch.cuda.empty_cache()
+
+
+def test_hh_16384_as_configured_t512_vs_oracle():
+    """The 16384^2 H(x)H workload as configured (pair table, H(x)H coin, Haar
+    start of seed 3 at the centre, complex64, default depth 12 and launch shape,
+    renormalisation check every 64 steps) on the whole lattice after 512 steps,
+    against the oracle site by site (2e-5); P is exactly zero outside the cone."""
+    import torch
+    cfg = inputs.config("hh2d")
+    (Lx, Ly), x0 = cfg["extent"], cfg["x0"]
+    T = 512
+    w = qwalk.Walk(cfg["extent"], cfg["disp"], qwalk.HADAMARD2, cfg["psi0"], x0, prec=qwalk.QW_C64)
+    assert w.get_options().block_depth == 0          # library default (12 in complex64)
+    w.step(T)
+    P = torch.empty((Ly, Lx), dtype=torch.float64, device="cuda")
+    w.probabilities(out=P)
+    n = w.norm()
+    w.destroy()
+    # the oracle on a (2T + 3)^2 torus with the start at its centre: the cone
+    # (|x - x0|_inf <= T) never reaches its seam, as it never wraps the big torus
+    r = T + 1
+    L = 2 * r + 1
+    psi = oracle.walk(L, L, cfg["disp"], oracle.coin(oracle.HADAMARD2, 4), (r, r), cfg["psi0"], T)
+    Pr = oracle.prob(psi)
+    box = P[x0[1] - r:x0[1] + r + 1, x0[0] - r:x0[0] + r + 1]
+    err = torch.max(torch.abs(box - torch.from_numpy(Pr).cuda())).item()
+    print(f"# hh2d T={T}: max|dP| = {err:.3e}, norm error {abs(n - 1.0):.2e}", flush=True)
+    assert err <= TOL32_P
+    assert abs(n - 1.0) <= 1e-5
+    inside = torch.sum(box).item()
+    assert abs(inside - n) <= 1e-9                   # every bit of probability lies in the cone box
+    P[x0[1] - r:x0[1] + r + 1, x0[0] - r:x0[0] + r + 1] = 0.0
+    assert torch.count_nonzero(P).item() == 0
+    del P, box
+    torch.cuda.empty_cache()

@@ -51,13 +51,15 @@ def test_forward_matches_oracle():
     q = s.forward(X, T)
     p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
     s.destroy()
-    xr = X.astype(np.float32).view(np.uint32)          # the GPU feeds bf16 inputs
-    xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
-    qr = S.forward(p, xr, T)["p"]
+    xr = S.bf16_round(X)                                # the GPU feeds bf16 inputs
     assert np.all(np.abs(q.sum(axis=1) - 1.0) <= 1e-4)
-    # bf16 activations between the layers: a few 1e-3 relative on the logits
+    # on the same bf16-rounded operands (inputs, weights, hidden activations)
+    # only the fp32 accumulation and the fp32 head differ from the fp64 oracle
+    qb = S.forward(p, xr, T, bf16=True)["p"]
+    assert np.max(S.tvd(q, qb)) <= 5e-3
+    # the fp64 network without the rounding of the activations is farther away
+    qr = S.forward(p, xr, T)["p"]
     assert np.max(S.tvd(q, qr)) <= 2e-2
-    assert np.median(S.tvd(q, qr)) <= 5e-3
 
 
 def test_gradients_match_oracle():
@@ -69,11 +71,12 @@ def test_gradients_match_oracle():
     loss, g = s.loss_grad(X, y.astype(np.float32), T)
     p = S.unflatten(s.params(bf16_rounded=True).astype(np.float64))
     s.destroy()
-    xr = X.astype(np.float32).view(np.uint32)
-    xr = ((xr + 0x7FFF + ((xr >> 16) & 1)) & 0xFFFF0000).view(np.float32).astype(np.float64)
-    lref = S.loss(p, xr, y, T)
-    assert abs(loss - lref) <= 2e-2 * abs(lref)
-    gr = S.backward(p, xr, y, T)
+    xr = S.bf16_round(X)
+    # the oracle on the GPU's bf16 operands: inputs, weights, hidden activations
+    # and each layer's dZ where it enters a matrix product
+    lref = S.loss(p, xr, y, T, bf16=True)
+    assert abs(loss - lref) <= 5e-3 * abs(lref)
+    gr = S.backward(p, xr, y, T, bf16=True)
     gg = S.unflatten(g.astype(np.float64))
     for k in S.ORDER:
         if k == "cb":
@@ -82,7 +85,8 @@ def test_gradients_match_oracle():
             assert abs(gr[k][0]) <= 1e-12 and abs(gg[k][0]) <= 1e-4, (gr[k], gg[k])
             continue
         rel = np.linalg.norm(gg[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
-        assert rel <= 5e-2, (k, rel)
+        print(f"# gradient {k}: relative error {rel:.2e}", flush=True)
+        assert rel <= 1e-2, (k, rel)
 
 
 def test_training_reduces_loss_and_save_load(tmp_path):

@@ -102,3 +102,39 @@ def test_features_invariants():
     X2 = S.features(np.full(5, 4097), np.full(5, 300), ang, psi * np.exp(1j * 0.7))
     assert np.allclose(X1, X2, atol=1e-12)
     assert np.allclose(X1[:, 6] ** 2 + X1[:, 7] ** 2 + X1[:, 8] ** 2, 1.0)
+
+
+def test_bf16_round_matches_torch_and_ties_to_even():
+    """The oracle's bf16 rounding (round to nearest, ties to even, through fp32)
+    against torch's CPU conversion on random and on tie values."""
+    import torch
+    rng = np.random.default_rng(2)
+    v = np.concatenate([rng.normal(size=4096) * 10.0 ** rng.integers(-20, 20, size=4096),
+                        [0.0, -0.0, 1.0, -2.5, 3.0e38, 1e-39]])
+    want = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(S.bf16_round(v), want)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: to the even mantissa, 1;
+    # 1 + 3 * 2^-8 halfway between 1 + 2^-7 and 1 + 2^-6: to 1 + 2^-6
+    assert S.bf16_round(np.array([1 + 2.0 ** -8]))[0] == 1.0
+    assert S.bf16_round(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+    assert S.bf16_round(np.array([1 + 2.0 ** -8 + 2.0 ** -20]))[0] == 1 + 2.0 ** -7
+
+
+def test_bf16_option_changes_only_the_rounding():
+    """With bf16 operands the fp64 network moves by the rounding only: loss and
+    gradients stay within a few 1e-3 relative of the unrounded network's, and
+    differ from them."""
+    rng = np.random.default_rng(8)
+    p = {k: rng.normal(size=v) * 0.05 for k, v in S.SHAPES.items()}
+    x = S.bf16_round(rng.normal(size=(6, 32)))
+    T = rng.integers(256, 2048, size=6)
+    y = S.forward(p, rng.normal(size=(6, 32)), T)["p"]      # targets on the walks' support
+    l0, l1 = S.loss(p, x, y, T), S.loss(p, x, y, T, bf16=True)
+    assert l0 != l1 and abs(l0 - l1) <= 1e-2 * abs(l0)
+    g0, g1 = S.backward(p, x, y, T), S.backward(p, x, y, T, bf16=True)
+    for k in S.ORDER:
+        if k == "cb":                    # exactly zero (softmax is shift invariant)
+            assert abs(g0[k][0]) <= 1e-12 and abs(g1[k][0]) <= 1e-12
+            continue
+        rel = np.linalg.norm(g1[k] - g0[k]) / max(np.linalg.norm(g0[k]), 1e-30)
+        assert 0.0 < rel <= 5e-2, k
