@@ -61,7 +61,12 @@ def parse():
                     help="torus kernel: block order 0 = library default, 1 = linear, 2 = XCD-aware")
     ap.add_argument("--broken-links", type=float, default=0.0, metavar="P",
                     help="random broken links: each link breaks with probability P at every step")
-    ap.add_argument("--cpu-sample-steps", type=int, default=900)
+    ap.add_argument("--kernel", type=int, default=0, choices=(0, 1, 2),
+                    help="torus kernel variant: 0 = library default, 1 = one-wave strips, 2 = workgroup strips")
+    ap.add_argument("--cpu-sample-steps", type=int, default=512,
+                    help="steps of the one-thread oracle sample")
+    ap.add_argument("--cpu-all-cores-steps", type=int, default=2048,
+                    help="steps of the all-threads oracle run (the whole walk by default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
@@ -173,6 +178,7 @@ def rbl_segment(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
+        oracle.set_threads(1)
         C = oracle.coin(oracle.SU2, 2, math.pi / 4, -math.pi / 2, -math.pi / 2)
         worst = 0.0
         tc0 = time.perf_counter()
@@ -258,6 +264,7 @@ def ragged_rings(args):
         # the oracle (light-cone windowed, plain C, fp64, 1 thread) on the walks
         # with N < 1e4, against the GPU's bins of the same walks
         import oracle
+        oracle.set_threads(1)
         Ns, Ts_, As, Ps = p["N"], p["T"], p["angles"], p["psi0"]
         pick = [i for i in np.argsort(Ns) if Ns[i] < 10000][:64]
         upd, worst = 0, 0.0
@@ -297,7 +304,7 @@ def ragged_rings(args):
     if cpu:
         out["cpu_baseline"] = cpu
     b.destroy()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def _surrogate_walks(seed: int, n: int):
@@ -451,7 +458,7 @@ def surrogate(args):
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
         "train_s": t2 - t1, "datagen_ms": gen_ms, "setup_s": t1 - t0,
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def traffic_from_profile(kernel_sha: str):
@@ -475,11 +482,13 @@ def traffic_from_profile(kernel_sha: str):
 
 
 def kernel_source_sha():
-    """sha256 of what sets the torus walk's launches: the streaming kernel's
-    source (the regions of qw_kernels.hip between its begin / end markers,
-    device code and launcher) and the choice of launches (the marked regions
-    of qw_api.hip)."""
+    """sha256 of what sets the torus walk's launches: the streaming kernels'
+    source (qw_stream_wg.hip and the regions of qw_kernels.hip between the
+    begin / end markers, device code and launchers) and the choice of launches
+    (the marked regions of qw_api.hip)."""
     h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", "qw_stream_wg.hip"), "rb") as f:
+        h.update(f.read())
     for fname, tag in (("qw_kernels.hip", b"torus streaming kernel"), ("qw_api.hip", b"torus launch choice")):
         with open(os.path.join(ROOT, "paper_1003_3779_amd", "csrc", fname), "rb") as f:
             src = f.read()
@@ -559,6 +568,7 @@ def graph_bench(args):
     Pg = g.probabilities()
     g.destroy()
     import oracle
+    oracle.set_threads(1)
     tc0 = time.perf_counter()
     ref = oracle.graph_evolve(off, tgt, oracle.GROVER, psi0, Ts)
     tc1 = time.perf_counter()
@@ -583,6 +593,344 @@ def graph_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads of the all-cores oracle leg: OMP_NUM_THREADS when set (the
+    process's share of the host), else every core it may run on."""
+    n = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return n if n > 0 else len(os.sched_getaffinity(0))
+
+
+def time_walks(w, psi0, x0, T, P, steps: int, warmup: int):
+    """`warmup` untimed walks, then `steps` timed whole walks (walk_reset,
+    walk_step(T), walk_probabilities into the device buffer P, walk_norm) with
+    the live kernel timing on, then the same walks again without it."""
+    import torch
+
+    def one_walk():
+        w.reset(psi0, x0)
+        w.step(T)
+        w.probabilities(out=P)
+        return w.norm()                      # synchronises the stream
+
+    for _ in range(warmup):
+        one_walk()
+    w.set_options(profile=1)
+    w.profile(reset=True)
+    u0 = w.stats().updates
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norms = [one_walk() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    u1 = w.stats().updates
+    prof = w.profile(reset=True)
+    w.set_options(profile=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        one_walk()
+    torch.cuda.synchronize()
+    ms_plain = 1e3 * (time.perf_counter() - t2) / steps
+    return {"elapsed_s": t1 - t0, "updates_per_walk": (u1 - u0) / steps, "prof": prof, "norms": norms,
+            "ms_without_events": ms_plain}
+
+
+def hbm_roofline(prof: dict, elapsed_s: float, ref: dict | None = None, traffic: float | None = None) -> dict:
+    """Roofline of the dominant kernel of a timed region.  achieved = the
+    launches' algorithmic bytes (each launch's input box read once and output
+    box written once: d complex numbers per site) / their average duration
+    (HIP events on the walk's stream); the bytes the launcher moves by
+    construction (strip and segment halo re-reads included) are reported
+    beside it, and traffic is the rocprofv3-counted HBM bytes per launch."""
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    pk = prof[dom]
+    n = max(pk["launches"], 1)
+    avg_ms = pk["ms"] / n
+    alg = pk["min_bytes"] / n
+    bc = (pk["bytes_read"] + pk["bytes_written"]) / n
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": round(traffic) if traffic else None,
+         "launches": pk["launches"], "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": round(alg),
+         "kernel_share_of_step": round(pk["ms"] / (elapsed_s * 1e3), 4),
+         "by_construction": {"bytes_per_launch": round(bc), "GBps": round(bc / (avg_ms * 1e-3) / 1e9, 1)}}
+    if traffic:
+        r["traffic_over_alg"] = round(traffic / alg, 4)
+        r["traffic_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+    if ref:
+        r["measured_ceiling"] = ref
+        r["frac_of_copy_ceiling"] = round(achieved / ref["copy_GBps"], 4)
+    return r
+
+
+def walk_bench(args):
+    """One of the single-walk workloads (default: the 4096^2 Grover torus in
+    complex128); with the default workload and no --no-extras, the other
+    configurations follow as extras, each timed on the GPU and checked against
+    the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1003_3779_amd import inputs, qwalk
+    cfg = inputs.config(args.workload)
+    prec_name = args.prec or cfg["prec"]
+    prec = qwalk.QW_C128 if prec_name == "c128" else qwalk.QW_C64
+    ext, disp, T, x0, psi0 = cfg["extent"], cfg["disp"], cfg["T"], cfg["x0"], cfg["psi0"]
+    if cfg["dim"] == 1:
+        ext = (ext[0],)
+    V = ext[0] * (ext[1] if len(ext) > 1 else 1)
+    d = len(disp)
+
+    w = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=prec)
+    if args.depth or args.prefetch or args.waves or args.block_order or args.kernel:
+        w.set_options(block_depth=args.depth, prefetch_rows=args.prefetch, stream_waves=args.waves,
+                      block_order=args.block_order, stream_kernel=args.kernel)
+    if args.broken_links > 0.0:
+        w.set_broken_links(args.broken_links, seed=1, realization=0)
+    P = torch.empty(V, dtype=torch.float64, device="cuda")
+    print(f"# bench: workload={args.workload} prec={prec_name} T={T} V={V} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
+    tw = time_walks(w, psi0, x0, T, P, args.steps, args.warmup)
+    elapsed = tw["elapsed_s"]
+    updates_per_walk = tw["updates_per_walk"]
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = updates_per_walk * args.steps / elapsed
+    P_host = P.view(ext[1] if len(ext) > 1 else 1, ext[0]).cpu().numpy()
+    origin_p = float(P_host[x0[1] if len(x0) > 1 else 0, x0[0]])
+    sha = kernel_source_sha()
+    traffic = traffic_from_profile(sha) if (args.workload == "grover2d" and prec == qwalk.QW_C128
+                                            and not (args.depth or args.prefetch or args.waves
+                                                     or args.block_order or args.kernel)) else None
+    roofline = hbm_roofline(tw["prof"], elapsed, hbm_reference(), traffic)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == qwalk.QW_C128 else "f32",
+        "data": "synthetic", "ms_per_step_without_launch_events": round(tw["ms_without_events"], 3),
+        "config": {"workload": f"{args.workload}: {'x'.join(str(e) for e in ext)} "
+                               f"{'ring' if cfg['dim'] == 1 else 'torus'}, T={T}, {prec_name}",
+                   "lattice": list(ext), "T": T, "coin_dim": d, "precision": prec_name,
+                   "block_depth": args.depth or "library default", "parallelism": "single GPU",
+                   **({"broken_link_probability": args.broken_links} if args.broken_links > 0 else {})},
+        "roofline": roofline,
+        "updates_per_walk": updates_per_walk,
+        "dense_equiv_updates_per_s": V * d * T * args.steps / elapsed,
+        "norm_error": max(abs(n - 1.0) for n in tw["norms"]),
+        "origin_probability": origin_p,
+    }
+    default_run = args.workload == "grover2d" and args.broken_links == 0.0 and not args.no_extras
+    P_other = None
+    if not args.no_extras and args.workload.startswith("grover2d") and args.broken_links == 0.0:
+        extras = {}
+        # unblocked kernel, for the HBM roofline of one step per launch
+        w.set_options(block_depth=1)
+        t1 = time_walks(w, psi0, x0, T, P, 1, 0)
+        p1 = t1["prof"]["step"]
+        a1 = p1["min_bytes"] / (p1["ms"] * 1e-3) / 1e9
+        extras["one_step_kernel"] = {"ms_per_walk": round(1e3 * t1["elapsed_s"], 3), "achieved_GBps": round(a1, 1),
+                                     "frac": round(a1 / HBM_PEAK_GBPS, 4), "launches": p1["launches"]}
+        w.set_options(block_depth=args.depth)
+        # the same walk in the other precision (complex64: fp64 reductions,
+        # renormalisation check every 64 steps)
+        other = qwalk.QW_C64 if prec == qwalk.QW_C128 else qwalk.QW_C128
+        w2 = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=other)
+        t2 = time_walks(w2, psi0, x0, T, P, 3, 1)
+        st2 = w2.stats()
+        P_other = P.view(ext[1], ext[0]).cpu().numpy()
+        key = "c64" if other == qwalk.QW_C64 else "c128"
+        extras[key] = {
+            "ms_per_walk": round(1e3 * t2["elapsed_s"] / 3, 3),
+            "updates_per_s": t2["updates_per_walk"] * 3 / t2["elapsed_s"],
+            "roofline_frac": hbm_roofline(t2["prof"], t2["elapsed_s"])["frac"],
+            "norm_error": max(abs(n - 1.0) for n in t2["norms"]),
+            "renorms_applied": st2.renorms,
+            "max_abs_dP_vs_c128_run": float(np.max(np.abs(P_other - P_host))) if other == qwalk.QW_C64 else None,
+        }
+        w2.destroy()
+        out["extras"] = extras
+    w.destroy()
+    del P
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline and cfg["dim"] == 2 and args.broken_links == 0.0:
+        cpu, errs = torus_cpu_baseline(args, cfg, P_host if prec == qwalk.QW_C128 else P_other,
+                                       P_other if prec == qwalk.QW_C128 else P_host)
+        out["cpu_baseline"] = cpu
+        out["max_abs_dP_vs_oracle"] = errs
+    if default_run:
+        ex = out.setdefault("extras", {})
+        for name, fn in (("ring1d", extra_ring1d), ("hh2d", extra_hh2d), ("ragged_rings", extra_ragged),
+                         ("surrogate", extra_surrogate)):
+            print(f"# bench: extra {name}", file=sys.stderr, flush=True)
+            ex[name] = fn(args)
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+def torus_cpu_baseline(args, cfg, P_c128, P_c64):
+    """The oracle (plain C, fp64, light-cone windowed) on the workload itself:
+    one thread on its first steps, and every host thread on the whole walk,
+    whose P(x) the GPU's complex128 and complex64 runs are compared with."""
+    import numpy as np
+
+    import oracle
+    ext, disp, T, x0, psi0 = cfg["extent"], cfg["disp"], cfg["T"], cfg["x0"], cfg["psi0"]
+    Lx, Ly = ext
+    from paper_1003_3779_amd import qwalk
+    okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2, qwalk.FOURIER: oracle.FOURIER}[cfg["coin"]]
+    C = oracle.coin(okind, 4)
+
+    def upd(t_from, t_to):
+        # the oracle's window at step s is the box of radius s about x0
+        return sum(min(2 * r + 1, Lx) * min(2 * r + 1, Ly) for r in range(t_from + 1, t_to + 1)) * 4
+
+    def run(Ts, threads, label):
+        oracle.set_threads(threads)
+        psi = oracle.initial_state(Lx, Ly, 4, x0, psi0)
+        tc0 = time.perf_counter()
+        for t0 in range(0, Ts, 256):           # in chunks, with a progress line each
+            psi = oracle.evolve(psi, disp, C, min(256, Ts - t0), windowed=True, x0=x0, t0=t0)
+            print(f"# cpu baseline ({label}): oracle at step {min(t0 + 256, Ts)} of {Ts}", file=sys.stderr,
+                  flush=True)
+        return psi, time.perf_counter() - tc0
+
+    Ts1 = min(args.cpu_sample_steps, T)
+    psi1, s1 = run(Ts1, 1, "1 thread")
+    del psi1
+    nt = host_threads()
+    Ts = min(args.cpu_all_cores_steps, T)
+    psi, s = run(Ts, nt, f"{nt} threads")
+    Po = oracle.prob(psi)
+    del psi
+    oracle.set_threads(1)
+    errs = {"T": Ts}
+    if Ts == T:
+        for name, Pg in (("c128", P_c128), ("c64", P_c64)):
+            if Pg is not None:
+                errs[name] = float(np.max(np.abs(Pg - Po)))
+    cpu = {
+        "value": upd(0, Ts) / s, "unit": UNIT, "cores": nt, "kind": "oracle",
+        "sample": f"light-cone windowed oracle (plain C, fp64, site loops on {nt} threads), same torus and "
+                  f"start, steps 1-{Ts} of {T} ({upd(0, Ts):.3e} site*coin updates, {s:.1f} s)",
+        "cpu_model": cpu_model(), "host_cores": os.cpu_count(),
+        "single_thread": {"value": upd(0, Ts1) / s1, "cores": 1,
+                          "sample": f"the same oracle on 1 thread, steps 1-{Ts1} ({upd(0, Ts1):.3e} site*coin "
+                                    f"updates, {s1:.1f} s)"},
+    }
+    return cpu, errs
+
+
+def extra_ring1d(args):
+    """The 2001-site Hadamard ring, T = 1000, complex128: time per whole walk
+    (median of 50) and P against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1003_3779_amd import inputs, qwalk
+    cfg = inputs.config("ring1d")
+    N, T, x0, psi0 = cfg["extent"][0], cfg["T"], cfg["x0"], cfg["psi0"]
+    w = qwalk.Walk((N,), cfg["disp"], cfg["coin"], psi0, x0, prec=qwalk.QW_C128)
+    P = torch.empty(N, dtype=torch.float64, device="cuda")
+    ms = []
+    for i in range(55):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w.reset(psi0, x0)
+        w.step(T)
+        w.probabilities(out=P)
+        n = w.norm()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    Pg = P.cpu().numpy()
+    w.destroy()
+    oracle.set_threads(1)
+    tc0 = time.perf_counter()
+    Po = oracle.prob(oracle.walk(N, 1, cfg["disp"], oracle.coin(oracle.HADAMARD, 2), x0, psi0, T))[0]
+    tc1 = time.perf_counter()
+    return {"workload": f"ring1d: {N}-site ring, Hadamard, T={T}, c128", "us_per_walk": round(1e3 * float(np.median(ms[5:])), 1),
+            "norm_error": abs(n - 1.0), "max_abs_dP_vs_oracle": float(np.max(np.abs(Pg - Po))),
+            "oracle_1_thread_ms": round(1e3 * (tc1 - tc0), 1)}
+
+
+def extra_hh2d(args):
+    """The 16384^2 H(x)H torus (Haar start of seed 3, complex64, fp64
+    reductions): whole walks of T = 4096 with the roofline of their dominant
+    kernel, and a T = 512 walk against the oracle on the light-cone box."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1003_3779_amd import inputs, qwalk
+    cfg = inputs.config("hh2d")
+    (Lx, Ly), T, x0, psi0 = cfg["extent"], cfg["T"], cfg["x0"], cfg["psi0"]
+    w = qwalk.Walk((Lx, Ly), cfg["disp"], cfg["coin"], psi0, x0, prec=qwalk.QW_C64)
+    P = torch.empty(Lx * Ly, dtype=torch.float64, device="cuda")
+    tw = time_walks(w, psi0, x0, T, P, 2, 1)
+    rf = hbm_roofline(tw["prof"], tw["elapsed_s"])
+    # T = 512 against the oracle on a (2T + 3)^2 torus centred on the start
+    Ts = 512
+    w.reset(psi0, x0)
+    w.step(Ts)
+    w.probabilities(out=P)
+    r = Ts + 1
+    box = P.view(Ly, Lx)[x0[1] - r:x0[1] + r + 1, x0[0] - r:x0[0] + r + 1].cpu().numpy()
+    w.destroy()
+    del P
+    oracle.set_threads(host_threads())
+    psi = oracle.walk(2 * r + 1, 2 * r + 1, cfg["disp"], oracle.coin(oracle.HADAMARD2, 4), (r, r), psi0, Ts)
+    err = float(np.max(np.abs(box - oracle.prob(psi))))
+    oracle.set_threads(1)
+    return {"workload": f"hh2d: {Lx}x{Ly} torus, H(x)H, Haar start (seed 3), T={T}, c64",
+            "ms_per_walk": round(1e3 * tw["elapsed_s"] / 2, 2),
+            "updates_per_s": tw["updates_per_walk"] * 2 / tw["elapsed_s"],
+            "roofline": {k: rf[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms", "alg_bytes_per_launch",
+                                            "launches", "by_construction")},
+            "norm_error": max(abs(n - 1.0) for n in tw["norms"]),
+            "max_abs_dP_vs_oracle": {"T": Ts, "c64": err}}
+
+
+def extra_ragged(args):
+    """The 4096 ragged rings in one persistent launch (one run; the oracle on
+    the walks with N < 1e4)."""
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup, a.tune, a.rings, a.nmax = 1, 0, False, 4096, 999999
+    r = ragged_rings(a)
+    keep = ("walks_per_s", "kernel_ms", "est_updates_per_run", "norm_error_max", "second_moment_vs_limit_max",
+            "tiled_variant_per_bucket")
+    out = {"workload": r["config"]["workload"], "updates_per_s": r["value"], "ms_per_run": r["ms_per_step"],
+           **{k: r[k] for k in keep}, "roofline": r["roofline"]}
+    if "cpu_baseline" in r:
+        out["max_abs_dbins_vs_oracle"] = r["cpu_baseline"]["max_abs_dbins_vs_oracle"]
+        out["oracle_sample"] = r["cpu_baseline"]["sample"]
+    return out
+
+
+def extra_surrogate(args):
+    """The learned surrogate against the plain batched walk at TVD <= 1e-3
+    (train on 2^18 generated walks, evaluate on 65536 held-out ones)."""
+    a = argparse.Namespace(**vars(args))
+    a.train_walks, a.eval_walks, a.epochs, a.save = 1 << 18, 65536, 30, ""
+    r = surrogate(a)
+    keep = ("plain_walks_per_s", "surrogate_walks_per_s", "speedup", "fallback_rate", "failed_chunks",
+            "recheck_max_tvd", "network_ms", "tvd_network", "tvd_output_max", "tvd_baselines_median",
+            "at_looser_tolerance", "train_s")
+    return {"workload": r["config"]["workload"], "tolerance": 1e-3, **{k: r[k] for k in keep},
+            "roofline": r["roofline"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -603,10 +951,10 @@ def main():
         copy_reference(args.copy_ref)
         return
     if args.workload == "ragged_rings":
-        ragged_rings(args)
+        print(json.dumps(ragged_rings(args)), flush=True)
         return
     if args.workload == "surrogate":
-        surrogate(args)
+        print(json.dumps(surrogate(args)), flush=True)
         return
     if args.workload == "rbl_segment":
         rbl_segment(args)
@@ -614,183 +962,7 @@ def main():
     if args.workload in ("graph_torus", "graph_random"):
         graph_bench(args)
         return
-    cfg = inputs.config(args.workload)
-    prec_name = args.prec or cfg["prec"]
-    prec = qwalk.QW_C128 if prec_name == "c128" else qwalk.QW_C64
-    ext, disp, T, x0, psi0 = cfg["extent"], cfg["disp"], cfg["T"], cfg["x0"], cfg["psi0"]
-    if cfg["dim"] == 1:
-        ext = (ext[0],)
-    V = ext[0] * (ext[1] if len(ext) > 1 else 1)
-    d = len(disp)
-
-    w = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=prec)
-    if args.depth or args.prefetch or args.waves or args.block_order:
-        w.set_options(block_depth=args.depth, prefetch_rows=args.prefetch, stream_waves=args.waves,
-                      block_order=args.block_order)
-    if args.broken_links > 0.0:
-        w.set_broken_links(args.broken_links, seed=1, realization=0)
-    P = torch.empty(V, dtype=torch.float64, device="cuda")
-
-    def one_walk():
-        w.reset(psi0, x0)
-        w.step(T)
-        w.probabilities(out=P)
-        return w.norm()                      # synchronises the stream
-
-    print(f"# bench: workload={args.workload} prec={prec_name} T={T} V={V} warmup={args.warmup} "
-          f"steps={args.steps}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        one_walk()
-    w.set_options(profile=1)
-    w.profile(reset=True)
-    u0 = w.stats().updates
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    norms = []
-    for _ in range(args.steps):
-        norms.append(one_walk())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    u1 = w.stats().updates
-    prof = w.profile(reset=True)
-    w.set_options(profile=0)
-    # the same walks again without the per-launch HIP events that time the
-    # kernel live above: on small workloads their host cost shows in the walk time
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        one_walk()
-    torch.cuda.synchronize()
-    ms_unprofiled = 1e3 * (time.perf_counter() - t2) / args.steps
-    elapsed = t1 - t0
-    updates_per_walk = (u1 - u0) / args.steps
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = updates_per_walk * args.steps / elapsed
-    esz = 16 if prec == qwalk.QW_C128 else 8
-    P_host = P.view(ext[1] if len(ext) > 1 else 1, ext[0]).cpu().numpy()
-    origin_p = float(P_host[x0[1] if len(x0) > 1 else 0, x0[0]])
-
-    # dominant kernel of the timed region
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    pk = prof[dom]
-    launches = max(pk["launches"], 1)
-    bytes_per_launch = (pk["bytes_read"] + pk["bytes_written"]) / launches
-    avg_ms = pk["ms"] / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    sha = kernel_source_sha()
-    traffic = traffic_from_profile(sha) if (dom == "stream2d" and args.workload == "grover2d"
-                                            and prec == qwalk.QW_C128 and not args.depth) else None
-    ref = hbm_reference()
-    roofline = {
-        "bound": "hbm", "kernel": dom,
-        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": traffic,
-        "launches": pk["launches"], "avg_launch_ms": round(avg_ms, 5),
-        "alg_bytes_per_launch": round(bytes_per_launch),
-        "kernel_share_of_step": round(pk["ms"] / (elapsed * 1e3), 4),
-        "measured_ceiling": ref,
-        "frac_of_copy": round(achieved / ref["copy_GBps"], 4),
-        # the least any launch of this kernel must move: its box read once and
-        # written once (halo re-reads excluded)
-        "min_bytes_per_launch": round(2 * pk["bytes_written"] / launches),
-        "frac_min_bytes": round(2 * pk["bytes_written"] / launches / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-    }
-
-    out = {
-        "metric": METRIC, "value": value, "unit": UNIT,
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == qwalk.QW_C128 else "f32",
-        "data": "synthetic", "ms_per_step_without_launch_events": round(ms_unprofiled, 3),
-        "config": {"workload": f"{args.workload}: {'x'.join(str(e) for e in ext)} "
-                               f"{'ring' if cfg['dim'] == 1 else 'torus'}, T={T}, {prec_name}",
-                   "lattice": list(ext), "T": T, "coin_dim": d, "precision": prec_name,
-                   "block_depth": args.depth or "library default", "parallelism": "single GPU",
-                   **({"broken_link_probability": args.broken_links} if args.broken_links > 0 else {})},
-        "roofline": roofline,
-        "updates_per_walk": updates_per_walk,
-        "dense_equiv_updates_per_s": V * d * T * args.steps / elapsed,
-        "hbm_effective_GBps": value * 2 * esz / 1e9,
-        "norm_error": max(abs(n - 1.0) for n in norms),
-        "origin_probability": origin_p,
-    }
-
-    if not args.no_extras and args.workload.startswith("grover2d") and args.broken_links == 0.0:
-        extras = {}
-        # unblocked kernel, for the HBM roofline of one step per launch
-        w.set_options(block_depth=1, profile=1)
-        w.profile(reset=True)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        one_walk()
-        tb = time.perf_counter()
-        p1 = w.profile(reset=True)["step"]
-        a1 = (p1["bytes_read"] + p1["bytes_written"]) / (p1["ms"] * 1e-3) / 1e9
-        extras["one_step_kernel"] = {"ms_per_walk": round(1e3 * (tb - ta), 3), "achieved_GBps": round(a1, 1),
-                                     "frac": round(a1 / HBM_PEAK_GBPS, 4), "launches": p1["launches"]}
-        w.set_options(block_depth=args.depth, profile=0)
-        # the same walk in complex64 (fp64 reductions, renormalisation every 64 steps)
-        other = qwalk.QW_C64 if prec == qwalk.QW_C128 else qwalk.QW_C128
-        w2 = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=other)
-        w2.reset(psi0, x0)
-        w2.step(T)
-        w2.norm()
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        n2 = []
-        for _ in range(3):
-            w2.reset(psi0, x0)
-            w2.step(T)
-            w2.probabilities(out=P)
-            n2.append(w2.norm())
-        tb = time.perf_counter()
-        st2 = w2.stats()
-        P2 = P.view(ext[1], ext[0]).cpu().numpy()
-        extras["c64" if other == qwalk.QW_C64 else "c128"] = {
-            "ms_per_walk": round(1e3 * (tb - ta) / 3, 3),
-            "updates_per_s": updates_per_walk * 3 / (tb - ta),
-            "norm_error": max(abs(n - 1.0) for n in n2),
-            "renorms_applied": st2.renorms,
-            "max_abs_dP_vs_c128_run": float(np.max(np.abs(P2 - P_host))) if other == qwalk.QW_C64 else None,
-        }
-        w2.destroy()
-        out["extras"] = extras
-
-    if not args.no_cpu_baseline and cfg["dim"] == 2 and args.broken_links == 0.0:
-        import oracle
-        Ts = min(args.cpu_sample_steps, T)
-        Lx, Ly = ext
-        okind = {qwalk.GROVER: oracle.GROVER, qwalk.HADAMARD2: oracle.HADAMARD2,
-                 qwalk.FOURIER: oracle.FOURIER}[cfg["coin"]]
-        C = oracle.coin(okind, 4)
-        psi_o = oracle.initial_state(Lx, Ly, 4, x0, psi0)
-        tc0 = time.perf_counter()
-        for t0 in range(0, Ts, 256):           # in chunks, with a progress line each
-            psi_o = oracle.evolve(psi_o, disp, C, min(256, Ts - t0), windowed=True, x0=x0, t0=t0)
-            print(f"# cpu baseline: oracle at step {min(t0 + 256, Ts)} of {Ts}", file=sys.stderr, flush=True)
-        tc1 = time.perf_counter()
-        # the oracle's window at step s (s = 1..Ts) is the box of radius s about x0
-        upd = sum(min(2 * r + 1, Lx) * min(2 * r + 1, Ly) for r in range(1, Ts + 1)) * 4
-        Po = oracle.prob(psi_o)
-        del psi_o
-        # the GPU on the same sample, in both precisions, against the oracle
-        errs = {}
-        for pn, pc in (("c128", qwalk.QW_C128), ("c64", qwalk.QW_C64)):
-            wg = qwalk.Walk(ext, disp, cfg["coin"], psi0, x0, prec=pc)
-            wg.step(Ts)
-            Pg = wg.probabilities()
-            wg.destroy()
-            errs[pn] = float(np.max(np.abs(Pg - Po)))
-        out["cpu_baseline"] = {
-            "value": upd / (tc1 - tc0), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"light-cone windowed oracle (plain C, fp64, 1 thread), same torus and start, "
-                      f"first {Ts} of {T} steps ({upd:.3e} site*coin updates, {tc1 - tc0:.1f} s)",
-        }
-        out["max_abs_dP_vs_oracle"] = {"T": Ts, **errs}
-
-    w.destroy()
-    print(json.dumps(out), flush=True)
+    walk_bench(args)
 
 
 if __name__ == "__main__":

@@ -92,12 +92,15 @@ typedef struct {
 
 /* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
  * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
- * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3), stream_waves 0, block_order 0. */
+ * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3), stream_waves 0, block_order 0,
+ * stream_kernel 0. */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
                               or 2, 4, 8, 12, 16 (temporal blocking; a depth a kernel lacks
                               runs as the largest smaller one it has: rings 4, 8, 16; tori
-                              4, 8 in QW_C128 and 4, 8, 12, 16 in QW_C64); the steps left
+                              4, 8, 12, 16, except 4, 8 in QW_C128 on tables that are not
+                              axis-aligned, with broken links or walls, or on tori narrower
+                              than 256 sites); the steps left
                               after the last full block run at the largest smaller depth;
                               auto: rings 16, tori 8 (QW_C128) or 12 (QW_C64), small tori
                               (state under 32 MiB) 4, with broken links or walls on a
@@ -118,6 +121,12 @@ typedef struct {
                               the hardware deals to one XCD take neighbouring strips, which
                               share halo columns in that XCD's L2; 6 % faster on the 4096^2
                               QW_C128 torus); 1 = linear */
+    int32_t stream_kernel; /* torus streaming kernel variant: 0 = chosen by the library;
+                              1 = one-wave strips (64 columns, K halo columns per side);
+                              2 = workgroup strips (four waves on 256 columns exchanging
+                              their edge columns through LDS; axis-aligned tables without
+                              broken links, torus width >= 256).  A preference: a walk
+                              the preferred variant cannot take runs on the other. */
 } qw_options;
 
 /* Step kernels, as reported by walk_profile. */
@@ -161,12 +170,20 @@ typedef struct {
 int walk_create(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
                 const int64_t *x0, int32_t prec, void *stream, qw_walk_t *out);
 
-/* As walk_create, but the two state buffers (device, walk_state_bytes() each,
- * 256-byte aligned) are the caller's, e.g. torch tensors; the handle never
- * frees them. */
+/* As walk_create, but the device buffers are the caller's (e.g. torch
+ * tensors): state_a and state_b (walk_state_bytes() each) hold the state,
+ * scratch (walk_scratch_bytes(), or NULL: the handle allocates its own) the
+ * fp64 reduction partials, the norm and the renormalisation counters.  Each
+ * is 256-byte aligned, on the current device, distinct from the others, and
+ * must stay alive until walk_destroy, which never frees them.  Two walks must
+ * not share a scratch buffer while either has work in flight.  QW_EINVAL for a
+ * missing state buffer, a misaligned or repeated buffer. */
 int walk_create_ext(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
                     const int64_t *x0, int32_t prec, void *stream, void *state_a,
-                    void *state_b, qw_walk_t *out);
+                    void *state_b, void *scratch, qw_walk_t *out);
+
+/* Bytes of the scratch buffer walk_create_ext takes (a fixed size, a few KB). */
+int walk_scratch_bytes(size_t *bytes);
 
 /* Put the walk back to |x0> (x) psi0 at t = 0 without reallocating (same
  * lattice, coin, precision and options).  psi0 and x0 as for walk_create;
@@ -332,10 +349,16 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
 int walk_batch_run(qw_batch_t b);
 /* n x 3 doubles: sum P, sum P dx, sum P dx^2 per walk. */
 int walk_batch_moments(qw_batch_t b, double *out, int32_t out_on_device);
-/* n x nbins floats (the bins are summed in fp64, stored as fp32). */
+/* n x nbins floats: each site's fp64 P rounded once to a multiple of 2^-60,
+ * summed exactly in 64-bit integers (the same bins whatever the order of the
+ * sums), stored as fp32. */
 int walk_batch_binned(qw_batch_t b, float *out, int32_t out_on_device);
-/* sum_i N[i] doubles: walk i's P(x) at offset N[0] + ... + N[i-1]. */
-int walk_batch_probabilities(qw_batch_t b, double *out, int32_t out_on_device);
+/* Every walk's full P(x), in compressed rows: out receives sum_i N[i] doubles
+ * (device if out_on_device, else host, then synchronises), walk i's P at
+ * out[offsets[i] .. offsets[i + 1]) with offsets[i] = N[0] + ... + N[i-1];
+ * offsets (host, n + 1 int64) may be NULL.  QW_EINVAL unless the batch keeps
+ * its distributions (qw_batch_opts.keep_probabilities). */
+int walk_batch_probabilities(qw_batch_t b, double *out, int64_t *offsets, int32_t out_on_device);
 int walk_batch_info(qw_batch_t b, qw_batch_info *out);
 /* Autotuner: per size bucket, time every tiled variant (one run each, after
  * one warm-up run) on `samples` walks of the bucket (spread over their work,

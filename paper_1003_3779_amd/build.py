@@ -10,8 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libqwalk.so")
-SOURCES = ["qw_kernels.hip", "qw_api.hip", "qw_batch.hip", "qw_surrogate.hip", "qw_graph.hip",
-           "qw_static.hip"]
+SOURCES = ["qw_kernels.hip", "qw_stream_wg.hip", "qw_api.hip", "qw_batch.hip", "qw_surrogate.hip",
+           "qw_graph.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -188,6 +188,7 @@ struct qw_walk {
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     bool own = true;
+    bool own_scr = true;  // false: the caller's scratch buffer (walk_create_ext)
     Scratch *scr = nullptr;
     double *pbuf = nullptr;  // device P(x) staging for host outputs (lazy)
     size_t state_bytes = 0;
@@ -284,7 +285,8 @@ void *oth_buf(qw_walk *w) { return w->buf[1 - w->cur]; }
 int fit_depth(const qw_walk *w, int k, bool ring) {
     static const int ks[] = {16, 12, 8, 4};
     for (int kk : ks)
-        if (kk <= k && (ring ? kk != 12 : stream2d_supported(w->prec, w->table, kk))) return kk;
+        if (kk <= k && (ring ? kk != 12 : stream2d_supported(w->prec, w->table, kk, w->g.Lx, w->rbl_on)))
+            return kk;
     return 1;
 }
 
@@ -400,6 +402,7 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     {
         const int linear = w->opt.block_order == 1;
         StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
+        tu.kernel = w->opt.stream_kernel;
         tu.ev_start = tm.start();
         tu.ev_stop = tm.stop();
         QW_HIP(launch_stream2d(w->prec, w->coin_impl, w->table, cur_buf(w), oth_buf(w), w->g, b, w->C, K, tu,
@@ -627,7 +630,7 @@ int drain_profile(qw_walk *w) {
 }
 
 int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
-                  void *stream, void *sa, void *sb, qw_walk_t *out) {
+                  void *stream, void *sa, void *sb, void *scr_ext, qw_walk_t *out) {
     if (!out) return fail(QW_EINVAL, "out handle pointer is NULL");
     *out = nullptr;
     int rc = validate_lattice(l);
@@ -670,6 +673,7 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     w->opt.prefetch_rows = 0;
     w->opt.stream_waves = 0;
     w->opt.block_order = 0;
+    w->opt.stream_kernel = 0;
     for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0, 0.0};
     set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
@@ -697,13 +701,18 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
             }
         }
     }
-    e = hipMalloc((void **)&w->scr, sizeof(Scratch));
-    if (e != hipSuccess) {
-        if (w->own)
-            for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
-        delete w;
-        (void)hipGetLastError();
-        return fail(QW_ENOMEM, "hipMalloc of the scratch area failed: %s", hipGetErrorString(e));
+    if (scr_ext) {
+        w->scr = (Scratch *)scr_ext;
+        w->own_scr = false;
+    } else {
+        e = hipMalloc((void **)&w->scr, sizeof(Scratch));
+        if (e != hipSuccess) {
+            if (w->own)
+                for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
+            delete w;
+            (void)hipGetLastError();
+            return fail(QW_ENOMEM, "hipMalloc of the scratch area failed: %s", hipGetErrorString(e));
+        }
     }
     hipError_t e1 = launch_fill_zero(w->buf[0], w->state_bytes, w->stream);
     hipError_t e2 = launch_fill_zero(w->buf[1], w->state_bytes, w->stream);
@@ -714,7 +723,7 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
         (void)hipStreamSynchronize(w->stream);
         if (w->own)
             for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
-        (void)hipFree(w->scr);
+        if (w->own_scr) (void)hipFree(w->scr);
         delete w;
         return hip_fail(bad, "initial state kernels");
     }
@@ -741,16 +750,24 @@ int walk_state_bytes(const qw_lattice *l, int32_t prec, size_t *bytes) {
 
 int walk_create(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
                 void *stream, qw_walk_t *out) {
-    return create_common(l, coin, psi0, x0, prec, stream, nullptr, nullptr, out);
+    return create_common(l, coin, psi0, x0, prec, stream, nullptr, nullptr, nullptr, out);
+}
+
+int walk_scratch_bytes(size_t *bytes) {
+    if (!bytes) return fail(QW_EINVAL, "bytes pointer is NULL");
+    *bytes = sizeof(Scratch);
+    return QW_OK;
 }
 
 int walk_create_ext(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
-                    void *stream, void *state_a, void *state_b, qw_walk_t *out) {
+                    void *stream, void *state_a, void *state_b, void *scratch, qw_walk_t *out) {
     if (!state_a || !state_b) return fail(QW_EINVAL, "walk_create_ext needs two state buffers");
-    if (((uintptr_t)state_a & 255) || ((uintptr_t)state_b & 255))
-        return fail(QW_EINVAL, "state buffers must be 256-byte aligned");
+    if (((uintptr_t)state_a & 255) || ((uintptr_t)state_b & 255) || ((uintptr_t)scratch & 255))
+        return fail(QW_EINVAL, "state and scratch buffers must be 256-byte aligned");
     if (state_a == state_b) return fail(QW_EINVAL, "the two state buffers must differ");
-    return create_common(l, coin, psi0, x0, prec, stream, state_a, state_b, out);
+    if (scratch && (scratch == state_a || scratch == state_b))
+        return fail(QW_EINVAL, "the scratch buffer must differ from the state buffers");
+    return create_common(l, coin, psi0, x0, prec, stream, state_a, state_b, scratch, out);
 }
 
 int walk_reset(qw_walk_t w, const double *psi0, const int64_t *x0) {
@@ -945,6 +962,8 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
         return fail(QW_EINVAL, "stream_waves must be in [0, 2^20] (got %d)", o->stream_waves);
     if (o->block_order < 0 || o->block_order > 2)
         return fail(QW_EINVAL, "block_order must be 0, 1 or 2 (got %d)", o->block_order);
+    if (o->stream_kernel < 0 || o->stream_kernel > 2)
+        return fail(QW_EINVAL, "stream_kernel must be 0, 1 or 2 (got %d)", o->stream_kernel);
     w->opt = *o;
     w->since_check = 0;
     return QW_OK;
@@ -1022,7 +1041,7 @@ int walk_destroy(qw_walk_t w) {
     hipError_t e = hipStreamSynchronize(w->stream);
     if (w->own)
         for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
-    (void)hipFree(w->scr);
+    if (w->own_scr) (void)hipFree(w->scr);
     if (w->pbuf) (void)hipFree(w->pbuf);
     for (auto &p : w->pending) {
         (void)hipEventDestroy(p.a);

@@ -112,13 +112,23 @@ __device__ __forceinline__ int ring_offset(int x, int x0, int N) {
     return dx > N / 2 ? dx - N : dx;
 }
 
+// Bin sums are kept in LDS as 64-bit fixed-point integers with 60 fraction
+// bits: integer addition is associative, so the sum of a bin does not depend
+// on the order in which the workgroup's atomics land (deterministic bins).
+// Each site's P (at most 1) is rounded to a multiple of 2^-60 once; a ring of
+// 1e6 sites adds at most 1e6 such roundings, below 1e-12 -- far under the
+// fp32 the bins are stored in.
+typedef unsigned long long BinAcc;
+constexpr double kBinScale = 1152921504606846976.0;  // 2^60
+__device__ __forceinline__ BinAcc bin_fixed(double p) { return (BinAcc)__double2ull_rn(p * kBinScale); }
+
 // Accumulates one site of P into the moments and the bins.  Bins follow the
 // symmetric split: with h = nbins/2 and w = floor((N-1)/2 / h) sites per bin,
 // offsets -k*w .. -(k-1)*w-1 go to bin h-k, offsets (k-1)*w+1 .. k*w to bin
 // h+k-1, the start site half to each of bins h-1 and h.
 struct SiteAcc {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    __device__ __forceinline__ void add(double p, int dx, int N, int nbins, double *s_bins) {
+    __device__ __forceinline__ void add(double p, int dx, int N, int nbins, BinAcc *s_bins) {
         const double fx = (double)dx;
         s0 += p;
         s1 += p * fx;
@@ -128,14 +138,15 @@ struct SiteAcc {
             const int wb = ((N - 1) / 2) / h;
             if (wb >= 1) {
                 if (dx == 0) {
-                    atomicAdd(&s_bins[h - 1], 0.5 * p);
-                    atomicAdd(&s_bins[h], 0.5 * p);
+                    const BinAcc q = bin_fixed(0.5 * p);
+                    atomicAdd(&s_bins[h - 1], q);
+                    atomicAdd(&s_bins[h], q);
                 } else if (dx < 0) {
                     const int k = (-dx - 1) / wb;
-                    if (k < h) atomicAdd(&s_bins[h - 1 - k], p);
+                    if (k < h) atomicAdd(&s_bins[h - 1 - k], bin_fixed(p));
                 } else {
                     const int k = (dx - 1) / wb;
-                    if (k < h) atomicAdd(&s_bins[h + k], p);
+                    if (k < h) atomicAdd(&s_bins[h + k], bin_fixed(p));
                 }
             }
         }
@@ -202,7 +213,7 @@ __device__ __forceinline__ uint32_t whole_links(const WalkDesc &w, const BatchAr
 
 template <typename R, int M, typename CN, bool RB = false>
 __device__ __forceinline__ void walk_whole(const WalkDesc &w, const BatchArgs &A, cv<R> (*L0)[kBT], cv<R> (*L1)[kBT],
-                           double *s_bins, double (*s_norm)[kWaves], SiteAcc &acc) {
+                           BinAcc *s_bins, double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
     const int j = threadIdx.x;
     const int nl = (N + M - 1) / M;
@@ -333,7 +344,7 @@ static_assert(kCfgK[0] % kFactorEvery == 0 && kCfgK[1] % kFactorEvery == 0 && kC
 
 // ---------------------------------------------------------------- tiled ring
 template <typename R, int MT, typename CN>
-__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, const int K, double *s_bins,
+__device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, const int K, BinAcc *s_bins,
                                            double (*s_norm)[kWaves], SiteAcc &acc) {
     const int N = w.N;
     const int64_t se = A.slot_elems;
@@ -460,7 +471,7 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
 }
 
 template <typename R> __device__ __forceinline__ void finish_walk(const BatchArgs &A, int wi, SiteAcc &acc,
-                                                                   double *s_bins, double (*s_red)[kWaves]) {
+                                                                   BinAcc *s_bins, double (*s_red)[kWaves]) {
     wg_reduce3(acc, s_red);  // contains the barrier that orders the bin atomics
     if (threadIdx.x == 0) {
         A.moments[3 * (int64_t)wi + 0] = acc.s0;
@@ -468,9 +479,10 @@ template <typename R> __device__ __forceinline__ void finish_walk(const BatchArg
         A.moments[3 * (int64_t)wi + 2] = acc.s2;
     }
     if (A.bins)
-        for (int i = threadIdx.x; i < A.nbins; i += kBT) A.bins[(int64_t)wi * A.nbins + i] = (float)s_bins[i];
+        for (int i = threadIdx.x; i < A.nbins; i += kBT)
+            A.bins[(int64_t)wi * A.nbins + i] = (float)((double)s_bins[i] * (1.0 / kBinScale));
     __syncthreads();
-    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0.0;
+    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0;
     __syncthreads();
 }
 
@@ -483,10 +495,10 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
     __shared__ int s_q;
     __shared__ cv<R> L0[2][kBT];
     __shared__ cv<R> L1[2][kBT];
-    __shared__ double s_bins[kMaxBins];
+    __shared__ BinAcc s_bins[kMaxBins];
     __shared__ double s_red[3][kWaves];
     __shared__ double s_norm[2][kWaves];
-    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0.0;
+    for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0;
     for (;;) {
         if (threadIdx.x == 0) s_q = (int)atomicAdd(&A.queue[0], 1u);
         __syncthreads();
@@ -1011,10 +1023,15 @@ int walk_batch_binned(qw_batch_t b, float *out, int32_t on_device) {
     return QW_OK;
 }
 
-int walk_batch_probabilities(qw_batch_t b, double *out, int32_t on_device) {
+int walk_batch_probabilities(qw_batch_t b, double *out, int64_t *offsets, int32_t on_device) {
     if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
     if (!out) return bfail(QW_EINVAL, "output pointer is NULL");
     if (!b->keep) return bfail(QW_EINVAL, "the batch was created without keep_probabilities");
+    if (offsets) {
+        // compressed rows: walk i's P(x) is out[offsets[i] .. offsets[i + 1])
+        for (int64_t i = 0; i < b->n; ++i) offsets[i] = b->p_off[i];
+        offsets[b->n] = b->total_sites;
+    }
     QB_HIP(hipMemcpyAsync(out, b->d_P, sizeof(double) * b->total_sites,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream),
            "copy of the distributions");

@@ -93,6 +93,9 @@ struct StreamTune {
     int prefetch;  // input rows read ahead, in registers: 1 or 3
     int waves;     // waves to launch (0 = default)
     int linear;    // 1: blocks take strips in launch order; 0: XCD-aware order
+    // 0: the library picks; 1: one-wave strips; 2: workgroup-wide strips
+    // (axis-aligned tables without broken links)
+    int kernel = 0;
     // non-null: events that the launch itself stamps with the kernel's start and
     // end (no separate event packets around it)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -102,7 +105,17 @@ hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, v
                            const Geom &g, const Box &out_box, const CoinF64 &C, int K,
                            const StreamTune &tune, hipStream_t s, LaunchInfo *info,
                            const Links *links = nullptr, int64_t t0 = 0);
-bool stream2d_supported(int prec, int table, int K);
+// a kernel for depth K exists for this walk (Lx: torus width; links: the walk
+// has broken links or walls)
+bool stream2d_supported(int prec, int table, int K, int Lx, bool links);
+// the workgroup-strip variant (qw_stream_wg.hip): axis-aligned tables, no
+// broken links, K in {4, 8, 12, 16}, Lx >= 256
+bool stream2d_wg_supported(int prec, int table, int K, int Lx);
+// lanes it launches over a box of width wx
+int stream2d_wg_lanes(int K, int wx);
+hipError_t launch_stream2d_wg(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
+                              const Box &out_box, const CoinF64 &C, int K, const StreamTune &tune, hipStream_t s,
+                              LaunchInfo *info);
 // P(x) (if P != nullptr) and the fp64 norm into scratch->norm.  psi_box: the box
 // outside which psi is zero.
 // one step with random broken links: the pending shift of a_t uses the links

@@ -1158,10 +1158,15 @@ static bool stream_pd(int table, int coin_impl, const void *in, void *out, const
                                     : stream_table<R, K, M, 3>(table, coin_impl, in, out, g, b, C, tu, s, info, sl);
 }
 
-bool stream2d_supported(int prec, int table, int K) {
+// depths of the one-wave strip kernel
+static bool stream2d_wave_supported(int prec, int table, int K) {
     if (table == TABLE_OTHER) return false;
     if (prec == C128) return K == 4 || K == 8;
     return K == 4 || K == 8 || K == 12 || K == 16;
+}
+
+bool stream2d_supported(int prec, int table, int K, int Lx, bool links) {
+    return stream2d_wave_supported(prec, table, K) || (!links && stream2d_wg_supported(prec, table, K, Lx));
 }
 
 hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, void *out, const Geom &g,
@@ -1174,8 +1179,21 @@ hipError_t launch_stream2d(int prec, int coin_impl, int table, const void *in, v
     }
     const StreamLinks *slp = links ? &sl : nullptr;
     if (b.wx <= 0 || b.wy <= 0) return hipSuccess;
-    if (!stream2d_supported(prec, table, K)) return hipErrorInvalidValue;
     if (tu.prefetch != 1 && tu.prefetch != 3) return hipErrorInvalidValue;
+    // the variant: workgroup strips where they apply, unless the box is so
+    // narrow that one-wave strips launch fewer lanes; tu.kernel is a
+    // preference (a walk the preferred variant cannot take runs on the other)
+    const bool wave_ok = stream2d_wave_supported(prec, table, K);
+    const bool wg_ok = !links && stream2d_wg_supported(prec, table, K, g.Lx);
+    bool use_wg = wg_ok;
+    if (tu.kernel == 1) {
+        use_wg = wg_ok && !wave_ok;
+    } else if (tu.kernel == 0 && wg_ok && wave_ok) {
+        const int TW = 64 - 2 * K;
+        use_wg = !(TW > 0 && (b.wx + TW - 1) / TW * 64 < stream2d_wg_lanes(K, b.wx));
+    }
+    if (use_wg) return launch_stream2d_wg(prec, coin_impl, table, in, out, g, b, C, K, tu, s, info);
+    if (!wave_ok) return hipErrorInvalidValue;
     // a strip must not meet itself across the periodic x boundary
     if (g.Lx < 64) return hipErrorInvalidValue;
     bool ok = false;

@@ -26,7 +26,7 @@ _STATUS_NAMES = {0: "QW_OK", -1: "QW_EINVAL", -2: "QW_ENOMEM", -3: "QW_EHIP", -4
 
 # every symbol the header declares (checked by the tests)
 ABI_SYMBOLS = (
-    "walk_create", "walk_create_ext", "walk_state_bytes", "walk_step", "walk_step_inverse",
+    "walk_create", "walk_create_ext", "walk_scratch_bytes", "walk_state_bytes", "walk_step", "walk_step_inverse",
     "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
     "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
     "walk_reset", "walk_profile", "walk_set_broken_links", "walk_set_reflecting_walls",
@@ -68,7 +68,8 @@ class Options(ctypes.Structure):
     _fields_ = [("block_depth", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("renorm_every", ctypes.c_int64), ("renorm_tol", ctypes.c_double),
                 ("profile", ctypes.c_int32), ("prefetch_rows", ctypes.c_int32),
-                ("stream_waves", ctypes.c_int32), ("block_order", ctypes.c_int32)]
+                ("stream_waves", ctypes.c_int32), ("block_order", ctypes.c_int32),
+                ("stream_kernel", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -130,7 +131,8 @@ def load():
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "walk_create": [P, P, P, P, I32, P, P],
-        "walk_create_ext": [P, P, P, P, I32, P, P, P, P],
+        "walk_create_ext": [P, P, P, P, I32, P, P, P, P, P],
+        "walk_scratch_bytes": [P],
         "walk_state_bytes": [P, I32, P],
         "walk_step": [P, I64],
         "walk_step_inverse": [P, I64],
@@ -151,7 +153,7 @@ def load():
         "walk_batch_run": [P],
         "walk_batch_moments": [P, P, I32],
         "walk_batch_binned": [P, P, I32],
-        "walk_batch_probabilities": [P, P, I32],
+        "walk_batch_probabilities": [P, P, P, I32],
         "walk_batch_info": [P, P],
         "walk_batch_tune": [P, I32, I32],
         "walk_batch_destroy": [P],
@@ -232,7 +234,7 @@ class Walk:
 
     def __init__(self, extent, disp, coin_kind: int, psi0, x0, prec: int = QW_C128,
                  theta: float = 0.0, phi: float = 0.0, chi: float = 0.0, dense=None,
-                 stream=None, state_buffers=None, dim: int | None = None):
+                 stream=None, state_buffers=None, scratch=None, dim: int | None = None):
         lib = load()
         self._lib = lib
         self.lattice = make_lattice(extent, disp)
@@ -254,14 +256,15 @@ class Walk:
         p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
         x0a = (ctypes.c_int64 * 2)(int(x0[0]), int(x0[1]) if len(x0) > 1 else 0)
         h = ctypes.c_void_p()
-        self._keep = state_buffers
+        self._keep = (state_buffers, scratch)
         if state_buffers is None:
             rc = lib.walk_create(ctypes.byref(self.lattice), ctypes.byref(coin), p0.ctypes.data, x0a, prec,
                                  _stream_of(stream), ctypes.byref(h))
         else:
             a, b = state_buffers
             rc = lib.walk_create_ext(ctypes.byref(self.lattice), ctypes.byref(coin), p0.ctypes.data, x0a, prec,
-                                     _stream_of(stream), _ptr_of(a), _ptr_of(b), ctypes.byref(h))
+                                     _stream_of(stream), _ptr_of(a), _ptr_of(b),
+                                     _ptr_of(scratch) if scratch is not None else None, ctypes.byref(h))
         _check(rc)
         self.h = h
 
@@ -333,8 +336,11 @@ class Walk:
     def set_options(self, block_depth: int | None = None, window: int | None = None,
                     renorm_every: int | None = None, renorm_tol: float | None = None,
                     profile: int | None = None, prefetch_rows: int | None = None,
-                    stream_waves: int | None = None, block_order: int | None = None):
+                    stream_waves: int | None = None, block_order: int | None = None,
+                    stream_kernel: int | None = None):
         o = self.get_options()
+        if stream_kernel is not None:
+            o.stream_kernel = int(stream_kernel)
         if block_order is not None:
             o.block_order = int(block_order)
         if stream_waves is not None:
@@ -394,6 +400,13 @@ def state_bytes(extent, disp, prec: int) -> int:
     return n.value
 
 
+def scratch_bytes() -> int:
+    """Bytes of the scratch buffer walk_create_ext takes."""
+    n = ctypes.c_size_t()
+    _check(load().walk_scratch_bytes(ctypes.byref(n)))
+    return n.value
+
+
 def _bcheck(rc: int):
     if rc != QW_OK:
         msg = load().walk_batch_last_error().decode(errors="replace")
@@ -445,11 +458,12 @@ class Batch:
         """Every walk's P(x), walk after walk: a list of host arrays, or into
         `out` (a device tensor of sum(N) float64)."""
         if out is not None:
-            _bcheck(self._lib.walk_batch_probabilities(self.h, _ptr_of(out), 1))
+            _bcheck(self._lib.walk_batch_probabilities(self.h, _ptr_of(out), None, 1))
             return None
         flat = np.empty(int(self.N.sum()), dtype=np.float64)
-        _bcheck(self._lib.walk_batch_probabilities(self.h, flat.ctypes.data, 0))
-        return np.split(flat, np.cumsum(self.N)[:-1])
+        off = np.empty(self.n + 1, dtype=np.int64)
+        _bcheck(self._lib.walk_batch_probabilities(self.h, flat.ctypes.data, off.ctypes.data, 0))
+        return [flat[off[i]:off[i + 1]] for i in range(self.n)]
 
     def info(self) -> BatchInfo:
         i = BatchInfo()

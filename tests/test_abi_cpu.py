@@ -178,9 +178,20 @@ def test_ext_buffers_checked(lib):
     x0 = (ctypes.c_int64 * 2)(0, 0)
     h = ctypes.c_void_p()
     assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None, None, None,
+                               None, ctypes.byref(h)) == qwalk.QW_EINVAL
+    assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None,
+                               ctypes.c_void_p(4096 + 8), ctypes.c_void_p(8192), None,
+                               ctypes.byref(h)) == qwalk.QW_EINVAL
+    # a misaligned scratch buffer, or one that is also a state buffer
+    assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None,
+                               ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(12288 + 64),
                                ctypes.byref(h)) == qwalk.QW_EINVAL
     assert lib.walk_create_ext(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0, 0, None,
-                               ctypes.c_void_p(4096 + 8), ctypes.c_void_p(8192), ctypes.byref(h)) == qwalk.QW_EINVAL
+                               ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(8192),
+                               ctypes.byref(h)) == qwalk.QW_EINVAL
+    n = ctypes.c_size_t()
+    assert lib.walk_scratch_bytes(ctypes.byref(n)) == qwalk.QW_OK and 0 < n.value <= 1 << 16
+    assert lib.walk_scratch_bytes(None) == qwalk.QW_EINVAL
 
 
 def _batch_create(lib, N, T, angles, psi0, nbins=0, prec=qwalk.QW_C64, walls=0, link_p=0.0, realization0=0):

@@ -304,16 +304,20 @@ def test_device_outputs_and_ext_buffers():
     nb = qwalk.state_bytes((N,), inputs.RING, qwalk.QW_C128)
     a = torch.empty(nb, dtype=torch.uint8, device="cuda")
     b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    scr = torch.empty(qwalk.scratch_bytes(), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.Stream()
-    w = qwalk.Walk((N,), inputs.RING, qwalk.HADAMARD, inputs.PSI0_LR, (3000, 0), stream=stream,
-                   state_buffers=(a, b))
-    w.step(T)
-    P = torch.empty(N, dtype=torch.float64, device="cuda")
-    w.probabilities(out=P)
-    stream.synchronize()
     Pr, _ = _oracle_run((N,), inputs.RING, _oracle_coin(oracle.HADAMARD, 2), inputs.PSI0_LR, (3000, 0), T)
-    assert np.max(np.abs(P.cpu().numpy() - Pr[0])) <= TOL64
-    w.destroy()
+    for scratch in (None, scr):       # the library's own scratch area, then the caller's
+        w = qwalk.Walk((N,), inputs.RING, qwalk.HADAMARD, inputs.PSI0_LR, (3000, 0), stream=stream,
+                       state_buffers=(a, b), scratch=scratch)
+        w.step(T)
+        P = torch.empty(N, dtype=torch.float64, device="cuda")
+        w.probabilities(out=P)
+        n = w.norm()
+        stream.synchronize()
+        assert np.max(np.abs(P.cpu().numpy() - Pr[0])) <= TOL64
+        assert abs(n - 1.0) <= TOL64
+        w.destroy()
 
 
 # ---------------------------------------------------------------- full-size 2D runs
