@@ -273,6 +273,32 @@ int walk_destroy(qw_walk_t w);
 /* Message of the latest failing call on this thread ("" if none). */
 const char *walk_last_error(void);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: one whole
+ * walk in one call that allocates nothing (no hipMalloc / hipFree, no host
+ * heap): the same kernels and results as walk_create_ext, walk_step(T),
+ * walk_probabilities and walk_norm on a fresh handle.
+ *  lattice, coin, psi0, x0, prec, stream: as for walk_create.
+ *  opt: NULL (the defaults of walk_create) or options as for walk_set_options;
+ *      profile must be 0 (QW_EINVAL otherwise).
+ *  state_a, state_b: the caller's device buffers, walk_state_bytes() each,
+ *      256-byte aligned and distinct; on return the final state is in one of
+ *      them (which one is unspecified).
+ *  T >= 0 steps.
+ *  P_out: device, V doubles (P(x), layout of walk_probabilities), or NULL.
+ *  norm_out: host double (the fp64 norm), or NULL; when given, the call
+ *      synchronises the stream, else it returns with the work enqueued.
+ * The reduction partials, the norm and the renormalisation counters live in a
+ * fixed array of the library's device memory, 16 KiB per GPU, held until the
+ * process ends and shared by every call on that GPU: each call clears it
+ * first, and calls that overlap on one GPU (other threads, other streams)
+ * race and give wrong results.  The walk's scratch need does not grow with the
+ * lattice; a need beyond the array's size is refused with QW_ERANGE.  Errors
+ * as for walk_create and walk_step. */
+int walk_run_noalloc(const qw_lattice *lattice, const qw_coin *coin, const double *psi0,
+                     const int64_t *x0, int32_t prec, const qw_options *opt, void *stream,
+                     void *state_a, void *state_b, int64_t T, double *P_out, double *norm_out);
+
 /* ------------------------------------------------------------------------
  * Batches of independent ring walks in one persistent launch.
  *

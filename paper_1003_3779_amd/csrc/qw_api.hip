@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -629,10 +630,10 @@ int drain_profile(qw_walk *w) {
     return QW_OK;
 }
 
-int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
-                  void *stream, void *sa, void *sb, void *scr_ext, qw_walk_t *out) {
-    if (!out) return fail(QW_EINVAL, "out handle pointer is NULL");
-    *out = nullptr;
+// Validates the arguments of a walk and fills every field of w that needs no
+// device memory (lattice, coin, options, origin, device).  Allocates nothing.
+int configure(qw_walk *w, const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0,
+              int32_t prec, void *stream) {
     int rc = validate_lattice(l);
     if (rc) return rc;
     if (!coin) return fail(QW_EINVAL, "coin is NULL");
@@ -643,9 +644,6 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     if (rc) return rc;
     rc = check_psi0(psi0, l->d);
     if (rc) return rc;
-
-    qw_walk *w = new (std::nothrow) qw_walk();
-    if (!w) return fail(QW_ENOMEM, "host allocation failed");
     w->dim = l->dim;
     w->d = l->d;
     w->prec = prec;
@@ -677,14 +675,35 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
     for (int k = 0; k < QW_KERNEL_KINDS; ++k) w->prof[k] = qw_kernel_profile{0, 0.0, 0.0, 0.0, 0.0, 0.0};
     set_origin(w, x0);
     w->state_bytes = (size_t)w->g.ps * (size_t)w->d * (prec == QW_C128 ? 16 : 8);
-
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) {
-        delete w;
-        return hip_fail(e, "hipGetDevice");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     w->device = dev;
+    return QW_OK;
+}
+
+// The start state |x0> (x) psi0 in the walk's buffers (both cleared) and a
+// cleared scratch area: fill and place kernels on the walk's stream.
+hipError_t start_state(qw_walk *w, const double *psi0) {
+    hipError_t e1 = launch_fill_zero(w->buf[0], w->state_bytes, w->stream);
+    hipError_t e2 = launch_fill_zero(w->buf[1], w->state_bytes, w->stream);
+    hipError_t e3 = launch_fill_zero(w->scr, sizeof(Scratch), w->stream);
+    hipError_t e4 = launch_place(w->prec, w->buf[0], w->g, w->x0[0], w->x0[1], psi0, w->stream);
+    return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
+}
+
+int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
+                  void *stream, void *sa, void *sb, void *scr_ext, qw_walk_t *out) {
+    if (!out) return fail(QW_EINVAL, "out handle pointer is NULL");
+    *out = nullptr;
+    qw_walk *w = new (std::nothrow) qw_walk();
+    if (!w) return fail(QW_ENOMEM, "host allocation failed");
+    int rc = configure(w, l, coin, psi0, x0, prec, stream);
+    if (rc) {
+        delete w;
+        return rc;
+    }
+    hipError_t e = hipSuccess;
     if (sa && sb) {
         w->buf[0] = sa;
         w->buf[1] = sb;
@@ -714,12 +733,8 @@ int create_common(const qw_lattice *l, const qw_coin *coin, const double *psi0, 
             return fail(QW_ENOMEM, "hipMalloc of the scratch area failed: %s", hipGetErrorString(e));
         }
     }
-    hipError_t e1 = launch_fill_zero(w->buf[0], w->state_bytes, w->stream);
-    hipError_t e2 = launch_fill_zero(w->buf[1], w->state_bytes, w->stream);
-    hipError_t e3 = launch_fill_zero(w->scr, sizeof(Scratch), w->stream);
-    hipError_t e4 = launch_place(prec, w->buf[0], w->g, w->x0[0], w->x0[1], psi0, w->stream);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
-        hipError_t bad = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
+    hipError_t bad = start_state(w, psi0);
+    if (bad != hipSuccess) {
         (void)hipStreamSynchronize(w->stream);
         if (w->own)
             for (int k = 0; k < 2; ++k) (void)hipFree(w->buf[k]);
@@ -1050,6 +1065,93 @@ int walk_destroy(qw_walk_t w) {
     for (auto e : w->spare) (void)hipEventDestroy(e);
     delete w;
     if (e != hipSuccess) return hip_fail(e, "stream synchronise in walk_destroy");
+    return QW_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ allocation-free walk
+// The scratch area of walk_run_noalloc: the reduction partials, the norm and
+// the renormalisation counters of one walk (struct Scratch) in a fixed array
+// of the library's device memory.  Each GPU the library runs on holds its own
+// copy at its own address until the process ends; every call on that GPU
+// shares it.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it uses the device address
+// looked up once per device with hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = 16384;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `dev` (looked up on
+// the first call on that device).
+int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QW_ERANGE, "device %d is beyond the %d devices the scratch table covers", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress of the scratch array");
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int walk_run_noalloc(const qw_lattice *l, const qw_coin *coin, const double *psi0, const int64_t *x0, int32_t prec,
+                     const qw_options *opt, void *stream, void *state_a, void *state_b, int64_t T, double *P_out,
+                     double *norm_out) {
+    if (!state_a || !state_b) return fail(QW_EINVAL, "walk_run_noalloc needs two state buffers");
+    if (((uintptr_t)state_a & 255) || ((uintptr_t)state_b & 255))
+        return fail(QW_EINVAL, "state buffers must be 256-byte aligned");
+    if (state_a == state_b) return fail(QW_EINVAL, "the two state buffers must differ");
+    if (T < 0) return fail(QW_EINVAL, "step count must be >= 0 (got %lld)", (long long)T);
+    if (opt && opt->profile) return fail(QW_EINVAL, "walk_run_noalloc does not time launches (profile must be 0)");
+    // what the walk keeps in scratch does not grow with the lattice: one
+    // Scratch record (the reductions cap their first pass at a fixed number
+    // of blocks)
+    const size_t need = sizeof(Scratch);
+    if (need > kNoAllocScratchBytes)
+        return fail(QW_ERANGE, "the walk needs %zu bytes of scratch; the library's array holds %zu", need,
+                    kNoAllocScratchBytes);
+    qw_walk w;  // on the stack: no host allocation either
+    int rc = configure(&w, l, coin, psi0, x0, prec, stream);
+    if (rc) return rc;
+    if (opt) {
+        qw_options o = *opt;
+        rc = walk_set_options(&w, &o);
+        if (rc) return rc;
+    }
+    void *scr = nullptr;
+    rc = scratch_address(w.device, &scr);
+    if (rc) return rc;
+    w.buf[0] = state_a;
+    w.buf[1] = state_b;
+    w.own = false;
+    w.scr = (Scratch *)scr;
+    w.own_scr = false;
+    const hipError_t e = start_state(&w, psi0);
+    if (e != hipSuccess) return hip_fail(e, "initial state kernels");
+    rc = walk_step(&w, T);
+    if (rc) return rc;
+    if (P_out) {
+        rc = walk_probabilities(&w, P_out, 1);
+        if (rc) return rc;
+    }
+    if (norm_out) {
+        rc = walk_norm(&w, norm_out);
+        if (rc) return rc;
+    }
     return QW_OK;
 }
 

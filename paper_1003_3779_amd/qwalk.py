@@ -29,7 +29,7 @@ ABI_SYMBOLS = (
     "walk_create", "walk_create_ext", "walk_scratch_bytes", "walk_state_bytes", "walk_step", "walk_step_inverse",
     "walk_probabilities", "walk_norm", "walk_get_state", "walk_set_state", "walk_set_options",
     "walk_get_options", "walk_time", "walk_stats", "walk_destroy", "walk_last_error",
-    "walk_reset", "walk_profile", "walk_set_broken_links", "walk_set_reflecting_walls",
+    "walk_reset", "walk_profile", "walk_set_broken_links", "walk_set_reflecting_walls", "walk_run_noalloc",
     "walk_batch_create", "walk_batch_run", "walk_batch_moments", "walk_batch_binned",
     "walk_batch_probabilities", "walk_batch_info", "walk_batch_tune", "walk_batch_destroy",
     "walk_batch_last_error",
@@ -132,6 +132,7 @@ def load():
     sig = {
         "walk_create": [P, P, P, P, I32, P, P],
         "walk_create_ext": [P, P, P, P, I32, P, P, P, P, P],
+        "walk_run_noalloc": [P, P, P, P, I32, P, P, P, P, I64, P, P],
         "walk_scratch_bytes": [P],
         "walk_state_bytes": [P, I32, P],
         "walk_step": [P, I64],
@@ -398,6 +399,32 @@ def state_bytes(extent, disp, prec: int) -> int:
     n = ctypes.c_size_t()
     _check(load().walk_state_bytes(ctypes.byref(lat), prec, ctypes.byref(n)))
     return n.value
+
+
+def run_noalloc(extent, disp, coin_kind: int, psi0, x0, T: int, state_buffers, prec: int = QW_C128,
+                P_out=None, want_norm: bool = True, options: "Options | None" = None, stream=None,
+                theta: float = 0.0, phi: float = 0.0, chi: float = 0.0, dense=None):
+    """One whole walk through walk_run_noalloc (no device allocation inside the
+    call): the caller's two state buffers, P into the device tensor P_out (or
+    none); returns the norm (host float) when want_norm, else None."""
+    lib = load()
+    lat = make_lattice(extent, disp)
+    coin = Coin()
+    coin.kind = coin_kind
+    coin.theta, coin.phi, coin.chi = theta, phi, chi
+    dn = None
+    if dense is not None:
+        dn = np.ascontiguousarray(np.asarray(dense, dtype=np.complex128))
+        coin.dense = dn.ctypes.data
+    p0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    x0a = (ctypes.c_int64 * 2)(int(x0[0]), int(x0[1]) if len(x0) > 1 else 0)
+    a, b = state_buffers
+    nrm = ctypes.c_double()
+    _check(lib.walk_run_noalloc(ctypes.byref(lat), ctypes.byref(coin), p0.ctypes.data, x0a, prec,
+                                ctypes.byref(options) if options is not None else None, _stream_of(stream),
+                                _ptr_of(a), _ptr_of(b), int(T), _ptr_of(P_out) if P_out is not None else None,
+                                ctypes.byref(nrm) if want_norm else None))
+    return nrm.value if want_norm else None
 
 
 def scratch_bytes() -> int:
