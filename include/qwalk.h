@@ -92,7 +92,7 @@ typedef struct {
 
 /* Tunables of one walk (walk_set_options).  Defaults: block_depth 0 (chosen
  * by the library), window 1, renorm_every 0 for QW_C128 and 64 for QW_C64,
- * renorm_tol 1e-7, profile 0, prefetch_rows 0 (= 3), stream_waves 0, block_order 0,
+ * renorm_tol 1e-7, profile 0, prefetch_rows 0, stream_waves 0, block_order 0,
  * stream_kernel 0. */
 typedef struct {
     int32_t block_depth;   /* steps fused per kernel launch: 0 = auto, 1 = one step per launch,
@@ -102,9 +102,10 @@ typedef struct {
                               axis-aligned, with broken links or walls, or on tori narrower
                               than 256 sites); the steps left
                               after the last full block run at the largest smaller depth;
-                              auto: rings 16, tori 8 (QW_C128) or 12 (QW_C64), small tori
-                              (state under 32 MiB) 4, with broken links or walls on a
-                              torus 4 */
+                              auto: rings 16; tori 12 (QW_C64; QW_C128 with the Grover or
+                              H(x)H coin on an axis-aligned table, torus >= 256 wide) or 8
+                              (other QW_C128 walks), small tori (state under 32 MiB) 4,
+                              with broken links or walls on a torus 4 */
     int32_t window;        /* 1: update only the light cone of the start site (exact, the
                               rest is zero); 0: sweep the whole lattice every step */
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
@@ -113,10 +114,13 @@ typedef struct {
     int32_t profile;       /* 1: bracket every step-kernel launch with HIP events on the
                               walk's stream (read back by walk_profile) */
     int32_t prefetch_rows; /* torus streaming kernel: input rows each wave has requested
-                              ahead of the row it computes; 0 = default (3), 1 or 3 */
-    int32_t stream_waves;  /* torus streaming kernel: target waves per launch (rows are split
-                              into segments of at least 4 K rows to reach it); 0 = default
-                              (16384 for QW_C128, 4096 for QW_C64) */
+                              ahead of the row it computes; 0 = default (1 in QW_C128 at
+                              depth 12 or more, else 3), 1 or 3 */
+    int32_t stream_waves;  /* torus streaming kernel: target waves per launch.  One-wave
+                              strips split rows into segments of at least 4 K rows to reach
+                              it (0 = 16384 for QW_C128, 4096 for QW_C64); workgroup strips
+                              take stream_waves / 4 as their workgroup slots (0 = the slots
+                              the chip holds at once: the launch fills them once) */
     int32_t block_order;   /* torus streaming kernel: 0 (default) or 2 = XCD-aware (the blocks
                               the hardware deals to one XCD take neighbouring strips, which
                               share halo columns in that XCD's L2; 6 % faster on the 4096^2

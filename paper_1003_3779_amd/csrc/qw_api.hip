@@ -299,11 +299,17 @@ int default_depth(const qw_walk *w) {
     // 1.35 ms per walk against 1.55); on large tori the same switch for the
     // small early boxes was slower (4096^2: 49.5 ms against 49.0)
     if (2 * (int64_t)w->state_bytes < ((int64_t)64 << 20)) return 4;
-    // torus: complex128 fits 8 levels in registers; complex64 12, which keeps two
-    // waves per SIMD where 16 keeps one and halves the wasted halo lanes of 16
-    // (measured: 4096^2 Grover 27.3 ms per walk at K = 12, 31.5 at 16, 32.1 at 8;
-    // 16384^2 H(x)H 190 ms at 12, 241 at 16)
-    return w->prec == C64 ? 12 : 8;
+    // torus, complex64: 12 levels keep two waves per SIMD where 16 keeps one
+    // (16384^2 H(x)H on workgroup strips: 156 ms per walk at K = 12, 205 at 16,
+    // 201 at 8)
+    if (w->prec == C64) return 12;
+    // complex128 on workgroup strips (axis-aligned table, torus >= 256 wide) with
+    // the Grover or H(x)H coin: 12 levels, one wave per SIMD; a launch then costs
+    // more than at 8 (224 against 179 us on the 4096^2 Grover walk) but covers
+    // 1.5x the steps (40.1 against 48.1 ms per walk).  Dense coins need more
+    // registers at 12 and stay at 8, as do the one-wave strips.
+    const bool wg = stream2d_wg_supported(w->prec, w->table, 12, w->g.Lx);
+    return wg && (w->coin_impl == COIN_GROVER4 || w->coin_impl == COIN_HH4) ? 12 : 8;
 }
 // ---- torus launch choice: end ----
 
@@ -402,7 +408,10 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     else
     {
         const int linear = w->opt.block_order == 1;
-        StreamTune tu = {w->opt.prefetch_rows ? w->opt.prefetch_rows : 3, w->opt.stream_waves, linear};
+        // read-ahead rows: one in complex128 at K >= 12 (registers go to the levels:
+        // 40.1 ms per 4096^2 Grover walk at K = 12 against 41.1 with three), else three
+        const int pd = w->opt.prefetch_rows ? w->opt.prefetch_rows : (w->prec == C128 && K >= 12 ? 1 : 3);
+        StreamTune tu = {pd, w->opt.stream_waves, linear};
         tu.kernel = w->opt.stream_kernel;
         tu.ev_start = tm.start();
         tu.ev_stop = tm.stop();
