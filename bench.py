@@ -461,10 +461,10 @@ def surrogate(args):
     return res
 
 
-def traffic_from_profile(kernel_sha: str):
+def traffic_from_profile(kernel_sha: str, name: str = "grover4096_c128"):
     """Measured HBM bytes per launch of the dominant kernel (rocprofv3 PMC),
     if the committed summary was taken on this exact kernel source."""
-    path = os.path.join(ROOT, "profiles", "stream2d_grover4096_c128_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"stream2d_{name}_traffic.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -879,7 +879,7 @@ def extra_hh2d(args):
     w = qwalk.Walk((Lx, Ly), cfg["disp"], cfg["coin"], psi0, x0, prec=qwalk.QW_C64)
     P = torch.empty(Lx * Ly, dtype=torch.float64, device="cuda")
     tw = time_walks(w, psi0, x0, T, P, 2, 1)
-    rf = hbm_roofline(tw["prof"], tw["elapsed_s"])
+    rf = hbm_roofline(tw["prof"], tw["elapsed_s"], traffic=traffic_from_profile(kernel_source_sha(), "hh16384_c64"))
     # T = 512 against the oracle on a (2T + 3)^2 torus centred on the start
     Ts = 512
     w.reset(psi0, x0)
@@ -896,8 +896,9 @@ def extra_hh2d(args):
     return {"workload": f"hh2d: {Lx}x{Ly} torus, H(x)H, Haar start (seed 3), T={T}, c64",
             "ms_per_walk": round(1e3 * tw["elapsed_s"] / 2, 2),
             "updates_per_s": tw["updates_per_walk"] * 2 / tw["elapsed_s"],
-            "roofline": {k: rf[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms", "alg_bytes_per_launch",
-                                            "launches", "by_construction")},
+            "roofline": {k: rf[k] for k in ("kernel", "achieved", "frac", "traffic", "traffic_over_alg",
+                                            "avg_launch_ms", "alg_bytes_per_launch", "launches", "by_construction")
+                         if k in rf},
             "norm_error": max(abs(n - 1.0) for n in tw["norms"]),
             "max_abs_dP_vs_oracle": {"T": Ts, "c64": err}}
 

@@ -125,12 +125,17 @@ typedef struct {
                               the hardware deals to one XCD take neighbouring strips, which
                               share halo columns in that XCD's L2; 6 % faster on the 4096^2
                               QW_C128 torus); 1 = linear */
-    int32_t stream_kernel; /* torus streaming kernel variant: 0 = chosen by the library;
-                              1 = one-wave strips (64 columns, K halo columns per side);
-                              2 = workgroup strips (four waves on 256 columns exchanging
-                              their edge columns through LDS; axis-aligned tables without
-                              broken links, torus width >= 256).  A preference: a walk
-                              the preferred variant cannot take runs on the other. */
+    int32_t stream_kernel; /* torus streaming kernel variant: 0 = chosen by the library
+                              (workgroup strips where they apply, the real coins split over
+                              two lanes in QW_C128); 1 = one-wave strips (64 columns, K halo
+                              columns per side); 2 = workgroup strips (waves side by side on
+                              256 columns exchanging their edge columns through LDS;
+                              axis-aligned tables without broken links, torus width >= 256;
+                              with the real Grover and H(x)H coins each complex number is
+                              split over two lanes, real parts in four waves, imaginary
+                              parts in four more); 3 = workgroup strips with complex lanes
+                              for every coin.  A preference: a walk the preferred variant
+                              cannot take runs on another. */
 } qw_options;
 
 /* Step kernels, as reported by walk_profile. */

@@ -304,10 +304,12 @@ int default_depth(const qw_walk *w) {
     // 201 at 8)
     if (w->prec == C64) return 12;
     // complex128 on workgroup strips (axis-aligned table, torus >= 256 wide) with
-    // the Grover or H(x)H coin: 12 levels, one wave per SIMD; a launch then costs
-    // more than at 8 (224 against 179 us on the 4096^2 Grover walk) but covers
-    // 1.5x the steps (40.1 against 48.1 ms per walk).  Dense coins need more
-    // registers at 12 and stay at 8, as do the one-wave strips.
+    // the real Grover or H(x)H coin (each complex number split over two lanes):
+    // 12 levels at two waves per SIMD; a launch costs a little more than at 8
+    // (196 against 182 us on the 4096^2 Grover walk) but covers 1.5x the steps
+    // (35.4 against 48.8 ms per walk; 16 levels: 33.5 ms at 250 us per launch).
+    // Dense coins need more registers at 12 and stay at 8, as do the one-wave
+    // strips.
     const bool wg = stream2d_wg_supported(w->prec, w->table, 12, w->g.Lx);
     return wg && (w->coin_impl == COIN_GROVER4 || w->coin_impl == COIN_HH4) ? 12 : 8;
 }
@@ -986,8 +988,8 @@ int walk_set_options(qw_walk_t w, const qw_options *o) {
         return fail(QW_EINVAL, "stream_waves must be in [0, 2^20] (got %d)", o->stream_waves);
     if (o->block_order < 0 || o->block_order > 2)
         return fail(QW_EINVAL, "block_order must be 0, 1 or 2 (got %d)", o->block_order);
-    if (o->stream_kernel < 0 || o->stream_kernel > 2)
-        return fail(QW_EINVAL, "stream_kernel must be 0, 1 or 2 (got %d)", o->stream_kernel);
+    if (o->stream_kernel < 0 || o->stream_kernel > 3)
+        return fail(QW_EINVAL, "stream_kernel must be 0, 1, 2 or 3 (got %d)", o->stream_kernel);
     w->opt = *o;
     w->since_check = 0;
     return QW_OK;

@@ -94,7 +94,8 @@ struct StreamTune {
     int waves;     // waves to launch (0 = default)
     int linear;    // 1: blocks take strips in launch order; 0: XCD-aware order
     // 0: the library picks; 1: one-wave strips; 2: workgroup-wide strips
-    // (axis-aligned tables without broken links)
+    // (axis-aligned tables without broken links; real coins split each complex
+    // number over two lanes); 3: workgroup-wide strips with complex lanes
     int kernel = 0;
     // non-null: events that the launch itself stamps with the kernel's start and
     // end (no separate event packets around it)

@@ -217,15 +217,160 @@ __global__ __launch_bounds__(kWgLanes) void k_stream2d_wg(const cv<R> *__restric
     }
 }
 
+// ---------------------------------------------------------------------
+// Real coins (Grover, H (x) H): the real and imaginary parts of the state
+// evolve independently (U = S (I (x) C) with C real maps Re psi to
+// Re psi' and Im psi to Im psi'), so one lane can carry one real number per
+// site and component instead of one complex number.  A workgroup of eight
+// waves streams one 256-column strip: waves 0-3 the real parts, waves 4-7 the
+// imaginary parts, each half exchanging its edge columns through LDS as
+// above.  Per lane the level window holds half the registers of the complex
+// kernel (two waves per SIMD where the complex kernel holds one), and the
+// cross-lane moves carry half the words.  The arithmetic on each real part is
+// the same expression as the complex kernel's on that part: bit-identical.
+constexpr int kRW = 8;              // waves per workgroup (two halves of kNW)
+constexpr int kRLanes = 64 * kRW;
+
+// twice the coin (the factor 1/2 of Grover and H (x) H kept out), on one real
+// part of the four gathered components
+template <typename R, int COIN> __device__ __forceinline__ void real_coin_x2(const R (&g)[4], R (&o)[4]) {
+    if constexpr (COIN == COIN_GROVER4) {
+        const R s = (g[0] + g[1]) + (g[2] + g[3]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] = fmaR((R)-2, g[c], s);
+    } else {
+        const R u0 = g[0] + g[1], u1 = g[0] - g[1], u2 = g[2] + g[3], u3 = g[2] - g[3];
+        o[0] = u0 + u2;
+        o[1] = u1 + u3;
+        o[2] = u0 - u2;
+        o[3] = u1 - u3;
+    }
+}
+
+template <typename R, int K> struct WgRegsR {
+    R v[K][3][4];  // [level][row slot][component], one real part
+};
+
+// in / out: the state as R words (re, im interleaved), already offset by this
+// half's part; element (c, row, x) at 2 * (c * ps + row * Lx + x)
+template <typename R, int K, int TABLE, int COIN, int PD, int PH>
+__device__ __forceinline__ void wgr_iter(WgRegsR<R, K> &st, R (&pf)[PD][4], const R *__restrict__ in,
+                                         R *__restrict__ out, const Geom &g, int xcol, bool store_col,
+                                         int row_next, int row_out, bool do_store, R *xs, int wave, int lane) {
+    constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
+    constexpr int PS = PH % PD;
+    constexpr int WB = PH, RB = (PH + 2) % 3;
+    R cur[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        cur[c] = pf[PS][c];
+        pf[PS][c] = in[2 * ((int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol)];
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            st.v[s][NEW][c] = cur[c];
+            if (wg_ex(TABLE, c) > 0 && lane == 63) xs[xs_index<K>(WB, s, wave + 1, 0)] = cur[c];
+            if (wg_ex(TABLE, c) < 0 && lane == 0) xs[xs_index<K>(WB, s, wave + 1, 1)] = cur[c];
+        }
+        R gi[4], go[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int ex = wg_ex(TABLE, c), ey = wg_ey(TABLE, c);
+            if (ex > 0) gi[c] = shift_or<true>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave, 0)]);
+            else if (ex < 0) gi[c] = shift_or<false>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave + 2, 1)]);
+            else gi[c] = st.v[s][ey > 0 ? OLD : (ey < 0 ? NEW : MID)][c];
+        }
+        real_coin_x2<R, COIN>(gi, go);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cur[c] = go[c];
+    }
+    if (do_store && store_col) {
+        const R unscale = (R)1 / (R)(1u << K);  // 2^-K, exact
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[2 * ((int64_t)c * g.ps + (int64_t)row_out * g.Lx + xcol)] = cur[c] * unscale;
+    }
+    __syncthreads();
+}
+
+template <typename R, int K, int TABLE, int COIN, int PD>
+__global__ __launch_bounds__(kRLanes) void k_stream2d_wgr(const R *__restrict__ in, R *__restrict__ out, Geom g,
+                                                          Box b, int seg_rows, int nstrips, int xcd_order) {
+    static_assert(COIN == COIN_GROVER4 || COIN == COIN_HH4, "real coins only");
+    constexpr int TW = kWgLanes - 2 * K;
+    constexpr int NXS = 3 * K * (kNW + 2) * 2;  // per half
+    __shared__ R xs_all[2 * NXS];
+    for (int i = threadIdx.x; i < 2 * NXS; i += kRLanes) xs_all[i] = (R)0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int half = wv >> 2, wave = wv & 3;  // half 0: real parts, 1: imaginary parts
+    R *xs = xs_all + half * NXS;
+    int lb = blockIdx.x;
+    if (xcd_order) {
+        const int nb = gridDim.x, xcd = lb & 7, i = lb >> 3, per = nb >> 3, rem = nb & 7;
+        lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + i;
+    }
+    lb = __builtin_amdgcn_readfirstlane(lb);
+    const int strip = lb % nstrips, seg = lb / nstrips;
+    const int r0 = seg * seg_rows;
+    if (r0 >= b.wy) return;  // uniform over the workgroup
+    const int nrows = min(seg_rows, b.wy - r0);
+    const int c0 = strip * TW;
+    const int q = (int)(threadIdx.x & (kWgLanes - 1));  // column within the strip
+    int xcol = (b.x0 + c0 - K + q) % g.Lx;
+    xcol = xcol < 0 ? xcol + g.Lx : xcol;
+    const bool store_col = q >= K && q < kWgLanes - K && c0 + q - K < b.wx;
+    const R *inh = in + half;
+    R *outh = out + half;
+    WgRegsR<R, K> st;
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) st.v[s][r][c] = (R)0;
+    const int niter = nrows + 2 * K;
+    int row_ld = (b.y0 + r0 - K) % g.Ly;
+    row_ld = row_ld < 0 ? row_ld + g.Ly : row_ld;
+    int row_out = (b.y0 + r0 - 2 * K) % g.Ly;
+    row_out = row_out < 0 ? row_out + g.Ly : row_out;
+    R pf[PD][4];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pf[p][c] = inh[2 * ((int64_t)c * g.ps + (int64_t)row_ld * g.Lx + xcol)];
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+    }
+    for (int i = 0; i < niter; i += 3) {
+        wgr_iter<R, K, TABLE, COIN, PD, 0>(st, pf, inh, outh, g, xcol, store_col, row_ld, row_out,
+                                           i >= 2 * K && i < niter, xs, wave, lane);
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+        wgr_iter<R, K, TABLE, COIN, PD, 1>(st, pf, inh, outh, g, xcol, store_col, row_ld, row_out,
+                                           i + 1 >= 2 * K && i + 1 < niter, xs, wave, lane);
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+        wgr_iter<R, K, TABLE, COIN, PD, 2>(st, pf, inh, outh, g, xcol, store_col, row_ld, row_out,
+                                           i + 2 >= 2 * K && i + 2 < niter, xs, wave, lane);
+        row_out = row_out + 1 == g.Ly ? 0 : row_out + 1;
+        row_ld = row_ld + 1 == g.Ly ? 0 : row_ld + 1;
+    }
+}
+
 // Workgroups resident per CU for one instantiation (from its register and LDS
 // use), looked up once.
-template <typename R, int K, int TABLE, int COIN, int PD> int wg_per_cu() {
+template <typename R, int K, int TABLE, int COIN, int PD, bool REAL> int wg_per_cu() {
     static int n = 0;
     if (n == 0) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_stream2d_wg<R, K, TABLE, COIN, PD>, kWgLanes, 0) !=
-                hipSuccess ||
-            v < 1) {
+        hipError_t e;
+        if constexpr (REAL)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_stream2d_wgr<R, K, TABLE, COIN, PD>, kRLanes, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_stream2d_wg<R, K, TABLE, COIN, PD>, kWgLanes, 0);
+        if (e != hipSuccess || v < 1) {
             (void)hipGetLastError();
             v = 1;
         }
@@ -270,9 +415,19 @@ template <typename R, int K, int TABLE, int COIN, int PD>
 void wg_launch(const void *in, void *out, const Geom &g, const Box &b, const CoinF64 &C, const StreamTune &tu,
                hipStream_t s, LaunchInfo *info) {
     constexpr int TW = kWgLanes - 2 * K;
+    // real coins split each complex number over two lanes: by default in
+    // complex128 (4096^2 Grover walk at K = 12: 35.4 against 40.0 ms per walk);
+    // complex64 keeps complex lanes unless asked (the split's 4-byte strided
+    // loads cost more than the registers it frees: 16384^2 H(x)H at K = 12 178.6
+    // against 156.5 ms)
+    constexpr bool kRealCoin = COIN == COIN_GROVER4 || COIN == COIN_HH4;
+    const bool real = kRealCoin && (tu.kernel == 2 || (tu.kernel == 0 && sizeof(R) == 8));
     const int nstrips = (b.wx + TW - 1) / TW;
-    const long slots = tu.waves > 0 ? std::max(1L, (long)tu.waves / kNW)
-                                    : (long)device_cus() * wg_per_cu<R, K, TABLE, COIN, PD>();
+    const int wave_per_block = real ? kRW : kNW;
+    int per_cu = 0;
+    if constexpr (kRealCoin) per_cu = real ? wg_per_cu<R, K, TABLE, COIN, PD, true>() : 0;
+    if (per_cu == 0) per_cu = wg_per_cu<R, K, TABLE, COIN, PD, false>();
+    const long slots = tu.waves > 0 ? std::max(1L, (long)tu.waves / wave_per_block) : (long)device_cus() * per_cu;
     const int seg_rows = wg_seg_rows(b.wy, nstrips, K, slots);
     const int nseg = (b.wy + seg_rows - 1) / seg_rows;
     const long blocks = (long)nstrips * nseg;
@@ -281,6 +436,18 @@ void wg_launch(const void *in, void *out, const Geom &g, const Box &b, const Coi
         info->bytes_written = (double)b.wx * b.wy * 4 * sizeof(cv<R>);
     }
     const int xcd = tu.linear ? 0 : 1;
+    if constexpr (kRealCoin) {
+        if (real) {
+            if (tu.ev_start)
+                hipExtLaunchKernelGGL((k_stream2d_wgr<R, K, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(kRLanes), 0,
+                                      s, tu.ev_start, tu.ev_stop, 0u, (const R *)in, (R *)out, g, b, seg_rows,
+                                      nstrips, xcd);
+            else
+                hipLaunchKernelGGL((k_stream2d_wgr<R, K, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(kRLanes), 0,
+                                   s, (const R *)in, (R *)out, g, b, seg_rows, nstrips, xcd);
+            return;
+        }
+    }
     if (tu.ev_start)
         hipExtLaunchKernelGGL((k_stream2d_wg<R, K, TABLE, COIN, PD>), dim3((unsigned)blocks), dim3(kWgLanes), 0, s,
                               tu.ev_start, tu.ev_stop, 0u, (const cv<R> *)in, (cv<R> *)out, g, b, seg_rows, nstrips,

@@ -1,5 +1,6 @@
-"""The torus streaming kernel with workgroup-wide strips (four waves on 256
-columns, edge columns exchanged through LDS) against the one-wave strips, the
+"""The torus streaming kernel with workgroup-wide strips (waves side by side
+on 256 columns, edge columns exchanged through LDS; with real coins each
+complex number split over two lanes) against the one-wave strips, the
 one-step kernel and the oracle.
 
 Every stored amplitude is the same expression in the same order whichever
@@ -19,7 +20,9 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32_P = 2e-5
-WAVE, WG = 1, 2  # stream_kernel: one-wave strips, workgroup strips
+# stream_kernel: one-wave strips; workgroup strips (real coins: each complex
+# number split over two lanes); workgroup strips with complex lanes
+WAVE, WG, WGC = 1, 2, 3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -69,9 +72,10 @@ def test_wg_strips_bitwise_and_vs_oracle(prec, table, coin_name, kind, okind):
     print(f"# wg: prec={prec} table={table} coin={coin_name}", flush=True)
     _, ref, _ = _run(ext, disp, kind, psi0, x0, T, prec, dense=dense, block_depth=1, renorm_every=0)
     for depth in (4, 8, 12, 16):
-        _, psi, _ = _run(ext, disp, kind, psi0, x0, T, prec, dense=dense, block_depth=depth, stream_kernel=WG,
-                         renorm_every=0)
-        assert np.array_equal(psi, ref), depth
+        for variant in (WG, WGC):
+            _, psi, _ = _run(ext, disp, kind, psi0, x0, T, prec, dense=dense, block_depth=depth,
+                             stream_kernel=variant, renorm_every=0)
+            assert np.array_equal(psi, ref), (depth, variant)
         if prec == qwalk.QW_C64 or depth <= 8:
             _, psi_w, _ = _run(ext, disp, kind, psi0, x0, T, prec, dense=dense, block_depth=depth,
                                stream_kernel=WAVE, renorm_every=0)
@@ -90,23 +94,25 @@ def test_wg_strips_bitwise_and_vs_oracle(prec, table, coin_name, kind, okind):
 @pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
 def test_wg_launch_shape_is_bitwise_neutral(prec):
     """Segment length (target waves), read-ahead rows and block order change only
-    which workgroup computes which rows and when loads are issued."""
+    which workgroup computes which rows and when loads are issued (complex lanes
+    for a Haar coin, split lanes for the Grover coin)."""
     rng = np.random.default_rng(2024 + prec)
     U = inputs.haar_unitary(rng, 4)
     psi0 = inputs.haar_state(rng, 4)
     ext, x0, T = (517, 263), (250, 5), 120   # three strips (the last ragged), rows wrap
-    for depth in (8, 12):
-        res = []
-        for pd, waves, order in ((3, 0, 0), (1, 0, 2), (3, 4, 1), (3, 37, 2), (1, 5000, 1), (3, 100000, 2)):
-            _, psi, _ = _run(ext, inputs.PAIR, qwalk.DENSE, psi0, x0, T, prec, dense=U, block_depth=depth,
-                             stream_kernel=WG, prefetch_rows=pd, stream_waves=waves, block_order=order,
-                             renorm_every=0)
-            res.append(psi)
-        for r in res[1:]:
-            assert np.array_equal(res[0], r), depth
-    Pr, psir = _oracle(ext, inputs.PAIR, U, psi0, x0, T)
-    if prec == qwalk.QW_C128:
-        assert np.max(np.abs(res[0] - psir)) <= TOL64
+    for kind, dense, C in ((qwalk.DENSE, U, U), (qwalk.GROVER, None, oracle.coin(oracle.GROVER, 4))):
+        for depth in (8, 12):
+            res = []
+            for pd, waves, order in ((3, 0, 0), (1, 0, 2), (3, 4, 1), (3, 37, 2), (1, 5000, 1), (3, 100000, 2)):
+                _, psi, _ = _run(ext, inputs.PAIR, kind, psi0, x0, T, prec, dense=dense, block_depth=depth,
+                                 stream_kernel=WG, prefetch_rows=pd, stream_waves=waves, block_order=order,
+                                 renorm_every=0)
+                res.append(psi)
+            for r in res[1:]:
+                assert np.array_equal(res[0], r), (kind, depth)
+        if prec == qwalk.QW_C128:
+            Pr, psir = _oracle(ext, inputs.PAIR, C, psi0, x0, T)
+            assert np.max(np.abs(res[0] - psir)) <= TOL64
 
 
 def test_wg_cone_wraps_whole_torus():
@@ -118,11 +124,12 @@ def test_wg_cone_wraps_whole_torus():
     ext, x0, T = (258, 40), (255, 1), 170
     for table in ("PAIR", "EQ8"):
         disp = getattr(inputs, table)
-        P, psi, n = _run(ext, disp, qwalk.DENSE, psi0, x0, T, qwalk.QW_C128, dense=U, block_depth=8,
-                         stream_kernel=WG)
-        Pr, psir = _oracle(ext, disp, U, psi0, x0, T)
-        assert np.max(np.abs(psi - psir)) <= TOL64, table
-        assert abs(n - 1.0) <= TOL64
+        for kind, dense, C in ((qwalk.DENSE, U, U), (qwalk.HADAMARD2, None, oracle.coin(oracle.HADAMARD2, 4))):
+            P, psi, n = _run(ext, disp, kind, psi0, x0, T, qwalk.QW_C128, dense=dense, block_depth=8,
+                             stream_kernel=WG)
+            Pr, psir = _oracle(ext, disp, C, psi0, x0, T)
+            assert np.max(np.abs(psi - psir)) <= TOL64, (table, kind)
+            assert abs(n - 1.0) <= TOL64
 
 
 def test_wg_preference_falls_back():
