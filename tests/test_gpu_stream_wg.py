@@ -144,3 +144,21 @@ def test_wg_preference_falls_back():
                        stream_kernel=WG)
         _, b, _ = _run(ext, disp, qwalk.DENSE, psi0, (100, 30), 40, qwalk.QW_C128, dense=U, block_depth=1)
         assert np.array_equal(a, b), table
+
+
+@pytest.mark.parametrize("Ly", [1, 2, 3, 5, 31])
+def test_wg_short_tori(Ly):
+    """Tori of 1 to 31 rows (every row wraps onto itself within a launch) on
+    workgroup strips, both lane layouts, against the one-step kernel bit for bit
+    and the oracle."""
+    rng = np.random.default_rng(700 + Ly)
+    psi0 = inputs.haar_state(rng, 4)
+    ext, x0, T = (300, Ly), (290, Ly // 2), 37
+    _, ref, _ = _run(ext, inputs.PAIR, qwalk.GROVER, psi0, x0, T, qwalk.QW_C128, block_depth=1)
+    for depth in (4, 12):
+        for variant in (WG, WGC):
+            _, psi, _ = _run(ext, inputs.PAIR, qwalk.GROVER, psi0, x0, T, qwalk.QW_C128, block_depth=depth,
+                             stream_kernel=variant)
+            assert np.array_equal(psi, ref), (depth, variant)
+    _, psir = _oracle(ext, inputs.PAIR, oracle.coin(oracle.GROVER, 4), psi0, x0, T)
+    assert np.max(np.abs(ref - psir)) <= TOL64
