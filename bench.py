@@ -760,6 +760,14 @@ def walk_bench(args):
             "max_abs_dP_vs_c128_run": float(np.max(np.abs(P_other - P_host))) if other == qwalk.QW_C64 else None,
         }
         w2.destroy()
+        # the benchmark walk at 12 steps per launch: shallower launches run closer to
+        # their HBM bound, the default depth finishes the walk sooner
+        w.set_options(block_depth=12)
+        t12 = time_walks(w, psi0, x0, T, P, 3, 1)
+        r12 = hbm_roofline(t12["prof"], t12["elapsed_s"])
+        extras["depth_12"] = {"ms_per_walk": round(1e3 * t12["elapsed_s"] / 3, 3), "roofline_frac": r12["frac"],
+                              "avg_launch_ms": r12["avg_launch_ms"], "achieved_GBps": r12["achieved"]}
+        w.set_options(block_depth=args.depth)
         out["extras"] = extras
     w.destroy()
     del P

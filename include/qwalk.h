@@ -102,10 +102,10 @@ typedef struct {
                               axis-aligned, with broken links or walls, or on tori narrower
                               than 256 sites); the steps left
                               after the last full block run at the largest smaller depth;
-                              auto: rings 16; tori 12 (QW_C64; QW_C128 with the Grover or
-                              H(x)H coin on an axis-aligned table, torus >= 256 wide) or 8
-                              (other QW_C128 walks), small tori (state under 32 MiB) 4,
-                              with broken links or walls on a torus 4 */
+                              auto: rings 16; tori 16 (the Grover or H(x)H coin on an
+                              axis-aligned table, torus >= 256 wide), else 12 (QW_C64) or 8
+                              (QW_C128), small tori (state under 32 MiB) 4, with broken
+                              links or walls on a torus 4 */
     int32_t window;        /* 1: update only the light cone of the start site (exact, the
                               rest is zero); 0: sweep the whole lattice every step */
     int64_t renorm_every;  /* 0 = never; else check the fp64 norm every so many steps and
@@ -114,8 +114,8 @@ typedef struct {
     int32_t profile;       /* 1: bracket every step-kernel launch with HIP events on the
                               walk's stream (read back by walk_profile) */
     int32_t prefetch_rows; /* torus streaming kernel: input rows each wave has requested
-                              ahead of the row it computes; 0 = default (1 in QW_C128 at
-                              depth 12 or more, else 3), 1 or 3 */
+                              ahead of the row it computes; 0 = default (1 at depth 16
+                              and in QW_C128 at depth 12, else 3), 1 or 3 */
     int32_t stream_waves;  /* torus streaming kernel: target waves per launch.  One-wave
                               strips split rows into segments of at least 4 K rows to reach
                               it (0 = 16384 for QW_C128, 4096 for QW_C64); workgroup strips
@@ -127,7 +127,8 @@ typedef struct {
                               QW_C128 torus); 1 = linear */
     int32_t stream_kernel; /* torus streaming kernel variant: 0 = chosen by the library
                               (workgroup strips where they apply, the real coins split over
-                              two lanes in QW_C128); 1 = one-wave strips (64 columns, K halo
+                              two lanes in QW_C128, and in QW_C64 where complex lanes would
+                              hold one wave per SIMD); 1 = one-wave strips (64 columns, K halo
                               columns per side); 2 = workgroup strips (waves side by side on
                               256 columns exchanging their edge columns through LDS;
                               axis-aligned tables without broken links, torus width >= 256;

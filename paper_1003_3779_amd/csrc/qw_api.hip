@@ -299,19 +299,17 @@ int default_depth(const qw_walk *w) {
     // 1.35 ms per walk against 1.55); on large tori the same switch for the
     // small early boxes was slower (4096^2: 49.5 ms against 49.0)
     if (2 * (int64_t)w->state_bytes < ((int64_t)64 << 20)) return 4;
-    // torus, complex64: 12 levels keep two waves per SIMD where 16 keeps one
-    // (16384^2 H(x)H on workgroup strips: 156 ms per walk at K = 12, 205 at 16,
-    // 201 at 8)
-    if (w->prec == C64) return 12;
-    // complex128 on workgroup strips (axis-aligned table, torus >= 256 wide) with
-    // the real Grover or H(x)H coin (each complex number split over two lanes):
-    // 12 levels at two waves per SIMD; a launch costs a little more than at 8
-    // (196 against 182 us on the 4096^2 Grover walk) but covers 1.5x the steps
-    // (35.4 against 48.8 ms per walk; 16 levels: 33.5 ms at 250 us per launch).
-    // Dense coins need more registers at 12 and stay at 8, as do the one-wave
-    // strips.
-    const bool wg = stream2d_wg_supported(w->prec, w->table, 12, w->g.Lx);
-    return wg && (w->coin_impl == COIN_GROVER4 || w->coin_impl == COIN_HH4) ? 12 : 8;
+    // torus on workgroup strips (axis-aligned table, torus >= 256 wide) with the
+    // real Grover or H(x)H coin: 16 levels per launch.  A launch then moves the
+    // same bytes as at 12 in more time, but covers 4/3 the steps, and a norm check
+    // every 64 steps needs no shorter remainder launch (measured per walk: 4096^2
+    // Grover c128 29.1 ms at 16 against 34.2 at 12 and 48.9 at 8; c64 20.8
+    // against 23.8; 16384^2 H(x)H 134.0 against 156.2)
+    const bool wg = stream2d_wg_supported(w->prec, w->table, 16, w->g.Lx);
+    if (wg && (w->coin_impl == COIN_GROVER4 || w->coin_impl == COIN_HH4)) return 16;
+    // otherwise complex64 at 12 levels (two waves per SIMD where 16 keeps one),
+    // complex128 at 8 (the most the one-wave strips and dense coins hold)
+    return w->prec == C64 ? 12 : 8;
 }
 // ---- torus launch choice: end ----
 
@@ -410,9 +408,9 @@ int stepK(qw_walk *w, int K, bool ring, const Links *links = nullptr) {
     else
     {
         const int linear = w->opt.block_order == 1;
-        // read-ahead rows: one in complex128 at K >= 12 (registers go to the levels:
-        // 40.1 ms per 4096^2 Grover walk at K = 12 against 41.1 with three), else three
-        const int pd = w->opt.prefetch_rows ? w->opt.prefetch_rows : (w->prec == C128 && K >= 12 ? 1 : 3);
+        // read-ahead rows: one at K = 16 and in complex128 at K >= 12 (registers go
+        // to the levels; three would drop to one wave per SIMD or spill), else three
+        const int pd = w->opt.prefetch_rows ? w->opt.prefetch_rows : ((w->prec == C128 && K >= 12) || K >= 16 ? 1 : 3);
         StreamTune tu = {pd, w->opt.stream_waves, linear};
         tu.kernel = w->opt.stream_kernel;
         tu.ev_start = tm.start();

@@ -80,21 +80,27 @@ template <typename R, bool LEFT> __device__ __forceinline__ cv<R> cshift_or(cv<R
     return r;
 }
 
-// LDS slots of the edge exchange: [iteration mod 3][level][wave + 1][dir];
-// dir 0: the +x-moving component of a wave's lane 63 (read by the wave to its
-// right), dir 1: the -x-moving component of its lane 0 (read by the wave to
-// its left).  Wave slots 0 and kNW + 1 stay zero: the strip's outer lanes are
-// halo, their values never reach a stored column.
-template <int K> __host__ __device__ constexpr int xs_index(int buf, int s, int wslot, int dir) {
-    return ((buf * K + s) * (kNW + 2) + wslot) * 2 + dir;
+// LDS slots of the edge exchange: three buffers (iteration mod 3), each
+// [level][wave + 1][dir]; dir 0: the +x-moving component of a wave's lane 63
+// (read by the wave to its right), dir 1: the -x-moving component of its lane 0
+// (read by the wave to its left).  Wave slots 0 and kNW + 1 stay zero: the
+// strip's outer lanes are halo, their values never reach a stored column.
+// The three buffers are separate LDS arrays, so the compiler knows that an
+// iteration's reads (the previous iteration's buffer) never alias its writes
+// and may issue them early.
+template <int K> __host__ __device__ constexpr int xs_index(int s, int wslot, int dir) {
+    return (s * (kNW + 2) + wslot) * 2 + dir;
 }
+template <typename T> struct XBufs {
+    T *b[3];
+};
 
 // One stream iteration (PH = iteration mod 3; slot PH receives the newest row).
 template <typename R, int K, int TABLE, int COIN, int PD, int PH>
 __device__ __forceinline__ void wg_iter(WgRegs<R, K> &st, cv<R> (&pf)[PD][4], const cv<R> *__restrict__ in,
                                         cv<R> *__restrict__ out, const Geom &g, int xcol, bool store_col,
                                         int row_next, int row_out, bool do_store, const CoinR<R> &C,
-                                        cv<R> *xs, int wave, int lane) {
+                                        const XBufs<cv<R>> &xs, int wave, int lane) {
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
     constexpr int PS = PH % PD;
     constexpr int WB = PH, RB = (PH + 2) % 3;  // exchange buffers written / read this iteration
@@ -104,14 +110,22 @@ __device__ __forceinline__ void wg_iter(WgRegs<R, K> &st, cv<R> (&pf)[PD][4], co
         cur[c] = pf[PS][c];
         pf[PS][c] = in[(int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol];
     }
+    // the neighbours' edge values of level 0; each level requests those of the
+    // next one before its own work, so an LDS round trip hides behind a level
+    cv<R> eL = xs.b[RB][xs_index<K>(0, wave, 0)], eR = xs.b[RB][xs_index<K>(0, wave + 2, 1)];
 #pragma unroll
     for (int s = 0; s < K; ++s) {
+        cv<R> nL = eL, nR = eR;
+        if (s + 1 < K) {
+            nL = xs.b[RB][xs_index<K>(s + 1, wave, 0)];
+            nR = xs.b[RB][xs_index<K>(s + 1, wave + 2, 1)];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             st.v[s][NEW][c] = cur[c];
             // publish the edge values of the row entering level s
-            if (wg_ex(TABLE, c) > 0 && lane == 63) xs[xs_index<K>(WB, s, wave + 1, 0)] = cur[c];
-            if (wg_ex(TABLE, c) < 0 && lane == 0) xs[xs_index<K>(WB, s, wave + 1, 1)] = cur[c];
+            if (wg_ex(TABLE, c) > 0 && lane == 63) xs.b[WB][xs_index<K>(s, wave + 1, 0)] = cur[c];
+            if (wg_ex(TABLE, c) < 0 && lane == 0) xs.b[WB][xs_index<K>(s, wave + 1, 1)] = cur[c];
         }
         cv<R> gi[4], go[4];
 #pragma unroll
@@ -119,9 +133,9 @@ __device__ __forceinline__ void wg_iter(WgRegs<R, K> &st, cv<R> (&pf)[PD][4], co
             const int ex = wg_ex(TABLE, c), ey = wg_ey(TABLE, c);
             if (ex > 0) {
                 // from x - 1 in the same row: lane 0 takes the left wave's lane 63
-                gi[c] = cshift_or<R, true>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave, 0)]);
+                gi[c] = cshift_or<R, true>(st.v[s][MID][c], eL);
             } else if (ex < 0) {
-                gi[c] = cshift_or<R, false>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave + 2, 1)]);
+                gi[c] = cshift_or<R, false>(st.v[s][MID][c], eR);
             } else {
                 gi[c] = st.v[s][ey > 0 ? OLD : (ey < 0 ? NEW : MID)][c];
             }
@@ -133,6 +147,8 @@ __device__ __forceinline__ void wg_iter(WgRegs<R, K> &st, cv<R> (&pf)[PD][4], co
         else Coin<R, 4, COIN>::apply(gi, go, C);
 #pragma unroll
         for (int c = 0; c < 4; ++c) cur[c] = go[c];
+        eL = nL;
+        eR = nR;
     }
     if (do_store && store_col) {
         constexpr bool kScaled = COIN == COIN_GROVER4 || COIN == COIN_HH4;
@@ -155,10 +171,11 @@ __global__ __launch_bounds__(kWgLanes) void k_stream2d_wg(const cv<R> *__restric
                       wg_ey(TABLE, 2) * wg_ex(TABLE, 2) == 0 && wg_ey(TABLE, 3) * wg_ex(TABLE, 3) == 0,
                   "axis-aligned displacement tables only");
     constexpr int TW = kWgLanes - 2 * K;  // output columns per strip
-    constexpr int NXS = 3 * K * (kNW + 2) * 2;
-    __shared__ cv<R> xs[NXS];
-    for (int i = threadIdx.x; i < NXS; i += kWgLanes) xs[i] = czero<R>();
+    constexpr int NX1 = K * (kNW + 2) * 2;  // one exchange buffer
+    __shared__ cv<R> xs0[NX1], xs1[NX1], xs2[NX1];
+    for (int i = threadIdx.x; i < NX1; i += kWgLanes) xs0[i] = xs1[i] = xs2[i] = czero<R>();
     __syncthreads();
+    const XBufs<cv<R>> xs{{xs0, xs1, xs2}};
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // XCD-aware order: the hardware deals blocks to the 8 XCDs in turn (block b
@@ -256,7 +273,8 @@ template <typename R, int K> struct WgRegsR {
 template <typename R, int K, int TABLE, int COIN, int PD, int PH>
 __device__ __forceinline__ void wgr_iter(WgRegsR<R, K> &st, R (&pf)[PD][4], const R *__restrict__ in,
                                          R *__restrict__ out, const Geom &g, int xcol, bool store_col,
-                                         int row_next, int row_out, bool do_store, R *xs, int wave, int lane) {
+                                         int row_next, int row_out, bool do_store, const XBufs<R> &xs, int wave,
+                                         int lane) {
     constexpr int NEW = PH, MID = (PH + 2) % 3, OLD = (PH + 1) % 3;
     constexpr int PS = PH % PD;
     constexpr int WB = PH, RB = (PH + 2) % 3;
@@ -266,25 +284,33 @@ __device__ __forceinline__ void wgr_iter(WgRegsR<R, K> &st, R (&pf)[PD][4], cons
         cur[c] = pf[PS][c];
         pf[PS][c] = in[2 * ((int64_t)c * g.ps + (int64_t)row_next * g.Lx + xcol)];
     }
+    R eL = xs.b[RB][xs_index<K>(0, wave, 0)], eR = xs.b[RB][xs_index<K>(0, wave + 2, 1)];
 #pragma unroll
     for (int s = 0; s < K; ++s) {
+        R nL = eL, nR = eR;
+        if (s + 1 < K) {  // the next level's edge values, requested a level ahead
+            nL = xs.b[RB][xs_index<K>(s + 1, wave, 0)];
+            nR = xs.b[RB][xs_index<K>(s + 1, wave + 2, 1)];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             st.v[s][NEW][c] = cur[c];
-            if (wg_ex(TABLE, c) > 0 && lane == 63) xs[xs_index<K>(WB, s, wave + 1, 0)] = cur[c];
-            if (wg_ex(TABLE, c) < 0 && lane == 0) xs[xs_index<K>(WB, s, wave + 1, 1)] = cur[c];
+            if (wg_ex(TABLE, c) > 0 && lane == 63) xs.b[WB][xs_index<K>(s, wave + 1, 0)] = cur[c];
+            if (wg_ex(TABLE, c) < 0 && lane == 0) xs.b[WB][xs_index<K>(s, wave + 1, 1)] = cur[c];
         }
         R gi[4], go[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int ex = wg_ex(TABLE, c), ey = wg_ey(TABLE, c);
-            if (ex > 0) gi[c] = shift_or<true>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave, 0)]);
-            else if (ex < 0) gi[c] = shift_or<false>(st.v[s][MID][c], xs[xs_index<K>(RB, s, wave + 2, 1)]);
+            if (ex > 0) gi[c] = shift_or<true>(st.v[s][MID][c], eL);
+            else if (ex < 0) gi[c] = shift_or<false>(st.v[s][MID][c], eR);
             else gi[c] = st.v[s][ey > 0 ? OLD : (ey < 0 ? NEW : MID)][c];
         }
         real_coin_x2<R, COIN>(gi, go);
 #pragma unroll
         for (int c = 0; c < 4; ++c) cur[c] = go[c];
+        eL = nL;
+        eR = nR;
     }
     if (do_store && store_col) {
         const R unscale = (R)1 / (R)(1u << K);  // 2^-K, exact
@@ -299,14 +325,14 @@ __global__ __launch_bounds__(kRLanes) void k_stream2d_wgr(const R *__restrict__ 
                                                           Box b, int seg_rows, int nstrips, int xcd_order) {
     static_assert(COIN == COIN_GROVER4 || COIN == COIN_HH4, "real coins only");
     constexpr int TW = kWgLanes - 2 * K;
-    constexpr int NXS = 3 * K * (kNW + 2) * 2;  // per half
-    __shared__ R xs_all[2 * NXS];
-    for (int i = threadIdx.x; i < 2 * NXS; i += kRLanes) xs_all[i] = (R)0;
+    constexpr int NX1 = K * (kNW + 2) * 2;  // one exchange buffer of one half
+    __shared__ R xs0[2 * NX1], xs1[2 * NX1], xs2[2 * NX1];
+    for (int i = threadIdx.x; i < 2 * NX1; i += kRLanes) xs0[i] = xs1[i] = xs2[i] = (R)0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int half = wv >> 2, wave = wv & 3;  // half 0: real parts, 1: imaginary parts
-    R *xs = xs_all + half * NXS;
+    const XBufs<R> xs{{xs0 + half * NX1, xs1 + half * NX1, xs2 + half * NX1}};
     int lb = blockIdx.x;
     if (xcd_order) {
         const int nb = gridDim.x, xcd = lb & 7, i = lb >> 3, per = nb >> 3, rem = nb & 7;
@@ -416,12 +442,14 @@ void wg_launch(const void *in, void *out, const Geom &g, const Box &b, const Coi
                hipStream_t s, LaunchInfo *info) {
     constexpr int TW = kWgLanes - 2 * K;
     // real coins split each complex number over two lanes: by default in
-    // complex128 (4096^2 Grover walk at K = 12: 35.4 against 40.0 ms per walk);
-    // complex64 keeps complex lanes unless asked (the split's 4-byte strided
-    // loads cost more than the registers it frees: 16384^2 H(x)H at K = 12 178.6
-    // against 156.5 ms)
+    // complex128 (4096^2 Grover walk at K = 12: 35.4 against 40.0 ms per walk,
+    // the complex lanes hold one wave per SIMD); complex64 keeps complex lanes
+    // while they hold two waves per SIMD (the split's 4-byte strided loads cost
+    // more than the registers it frees: 16384^2 H(x)H at K = 12 178.6 against
+    // 156.5 ms), else splits too (H(x)H at K = 16: 134.0 against 205 ms)
     constexpr bool kRealCoin = COIN == COIN_GROVER4 || COIN == COIN_HH4;
-    const bool real = kRealCoin && (tu.kernel == 2 || (tu.kernel == 0 && sizeof(R) == 8));
+    bool real = kRealCoin && (tu.kernel == 2 || (tu.kernel == 0 && sizeof(R) == 8));
+    if (kRealCoin && tu.kernel == 0 && sizeof(R) == 4) real = wg_per_cu<R, K, TABLE, COIN, PD, false>() < 2;
     const int nstrips = (b.wx + TW - 1) / TW;
     const int wave_per_block = real ? kRW : kNW;
     int per_cu = 0;

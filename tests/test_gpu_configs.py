@@ -93,7 +93,7 @@ def test_hh_16384_as_configured_t512_vs_oracle():
     (Lx, Ly), x0 = cfg["extent"], cfg["x0"]
     T = 512
     w = qwalk.Walk(cfg["extent"], cfg["disp"], qwalk.HADAMARD2, cfg["psi0"], x0, prec=qwalk.QW_C64)
-    assert w.get_options().block_depth == 0          # library default (12 in complex64)
+    assert w.get_options().block_depth == 0          # library default (16 with this coin and table)
     w.step(T)
     P = torch.empty((Ly, Lx), dtype=torch.float64, device="cuda")
     w.probabilities(out=P)
