@@ -150,3 +150,45 @@ def test_predict_device_output_matches_host_output():
         assert np.array_equal(dev.cpu().numpy(), host)
         assert np.array_equal(fb_h, fb_d) and st_h.failed_chunks == st_d.failed_chunks
     s.destroy()
+
+
+def test_trained_network_gain_over_the_plain_walk():
+    """What the trained network adds, on held-out walks: its binned answers are
+    far closer to the plain walk's than the best answer that ignores the coin
+    and the start state (the mean training distribution of the same T range),
+    and its pass costs a small fraction of the plain batch's time; at a loose
+    tolerance (TVD 0.3) surr_predict answers most walks with the network.  At
+    1e-3 every chunk falls back (the floor: tests/test_oracle_surrogate_floor.py)."""
+    torch = pytest.importorskip("torch")
+    n_tr, n_ev = 1 << 16, 8192
+    N, T, ang, psi0 = _walk_params(21, n_tr)
+    b = qwalk.Batch(N, T, ang, psi0, prec=qwalk.QW_C64, nbins=512)
+    b.run()
+    Y = b.binned()
+    b.destroy()
+    s = qwalk.Surrogate(seed=21)
+    X = s.features(N, T, ang, psi0)
+    Xd, Yd, Td = (torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
+                  torch.from_numpy(T.astype(np.int32)).cuda())
+    hist = s.train(Xd, Yd, Td, n_tr, batch=1024, epochs=12, lr=1e-3, seed=21)
+    assert np.all(np.isfinite(hist)) and hist[-1] < 0.5 * hist[0]
+    Ne, Te, Ae, Pe = _walk_params(22, n_ev)
+    b = qwalk.Batch(Ne, Te, Ae, Pe, prec=qwalk.QW_C64, nbins=512)
+    b.run()
+    Ye = b.binned().astype(np.float64)
+    plain_ms = b.info().last_run_ms
+    b.destroy()
+    net = s.forward(s.features(Ne, Te, Ae, Pe), Te).astype(np.float64)
+    tvd_net = 0.5 * np.abs(net - Ye).sum(axis=1)
+    tvd_mean = 0.5 * np.abs(Y.astype(np.float64).mean(axis=0)[None, :] - Ye).sum(axis=1)
+    print(f"# held-out TVD median: network {np.median(tvd_net):.3f}, mean distribution "
+          f"{np.median(tvd_mean):.3f}", flush=True)
+    assert np.median(tvd_net) < 0.5 * np.median(tvd_mean)
+    out, fb, st = s.predict(Ne, Te, Ae, Pe, tvd_tol=0.3)
+    print(f"# tol 0.3: fallback {fb.mean():.3f}, network {st.ms_network:.2f} ms, plain batch {plain_ms:.2f} ms",
+          flush=True)
+    assert fb.mean() < 0.5
+    assert st.ms_network < 0.2 * plain_ms
+    _, fb3, st3 = s.predict(Ne, Te, Ae, Pe, tvd_tol=1e-3)
+    assert fb3.all() and st3.failed_chunks == (n_ev + 1023) // 1024
+    s.destroy()
