@@ -48,11 +48,17 @@ __host__ __device__ inline float bf2f(bf16_t h) { return __builtin_bit_cast(floa
 // ---------------------------------------------------------------- GEMM
 // C[m][n] = alpha * sum_k A[m][k] B[n][k] (+ bias[n]); optional mask (keep where
 // mask[m][n] > 0) and relu; store fp32 and/or bf16.  A: M x K, B: N x K, both
-// bf16 row-major with K contiguous; K % 32 == 0.  Tile 128 x 128 x 32 per
+// bf16 row-major with K contiguous; K % 32 == 0.  Tile 128 x 128 x 64 per
 // 256-thread block, each wave a 64 x 64 quarter as 2 x 2 MFMA 32x32x16 tiles
-// (gfx950's double-K bf16 MFMA).  The next K tile is fetched into registers
-// while the current one is multiplied, and the LDS tiles are double-buffered:
-// one barrier per K tile.
+// (gfx950's double-K bf16 MFMA).  Two K tiles are in flight in registers
+// while the current one, staged in LDS, is multiplied; the LDS tiles are
+// double-buffered, one barrier per K tile.  The operands are read through
+// buffer descriptors whose range ends at row M (A) and row N (B): rows past
+// the end, columns past K and the tile that pads the K loop to an even count
+// read as zero without a branch, so every K tile issues the same loads and
+// the compiler's waits count exactly the tiles in flight (a load under a
+// branch makes it wait for all of them, and each K tile would pay a memory
+// round trip).
 struct GemmArgs {
     const bf16_t *A;
     int lda;
@@ -70,8 +76,17 @@ struct GemmArgs {
     int ldcb;
 };
 
-constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsRow = kBK + 8;  // +8 bf16: 16-byte aligned, spread rows
+constexpr int kBM = 128, kBN = 128, kBK = 64, kLdsRow = kBK + 8;  // +8 bf16: 16-byte aligned, spread rows
+constexpr int kPF = 2;                                           // K tiles in flight
+constexpr int kKAlign = 32;                                      // K must be a multiple of this
+constexpr unsigned kNoLoad = 0x80000000u;                        // an offset past any operand's range
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const bf16_t *p, int rows, int ld) {
+    // descriptor word 3 of the gfx9 family: 32-bit data format, no swizzle, no stride
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(p), (short)0, rows * ld * 2, 0x00020000);
+}
 
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     __shared__ bf16_t sA[2][kBM * kLdsRow];
@@ -86,33 +101,37 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    // staging: each thread moves 2 x 16 bytes of A and of B per K tile
-    const int lrow = tid >> 2, lk = (tid & 3) * 8;
-    uint4 va[2], vb[2];
-    auto fetch = [&](int k0) {
+    // staging: each thread moves 4 x 16 bytes of A and of B per K tile (rows
+    // lrow + 32 h, columns lk .. lk + 7)
+    const int lrow = tid >> 3, lk = (tid & 7) * 8;
+    const __amdgpu_buffer_rsrc_t ra = operand_rsrc(g.A, g.M, g.lda), rb = operand_rsrc(g.B, g.N, g.ldb);
+    unsigned oa[4], ob[4];  // byte offsets of this thread's rows at k = 0
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = lrow + 64 * h;
-            const int ma = m0 + r, nb = n0 + r;
-            va[h] = ma < g.M ? *(const uint4 *)(g.A + (int64_t)ma * g.lda + k0 + lk) : make_uint4(0, 0, 0, 0);
-            vb[h] = nb < g.N ? *(const uint4 *)(g.B + (int64_t)nb * g.ldb + k0 + lk) : make_uint4(0, 0, 0, 0);
+    for (int h = 0; h < 4; ++h) {
+        oa[h] = ((unsigned)(m0 + lrow + 32 * h) * (unsigned)g.lda + (unsigned)lk) * 2u;
+        ob[h] = ((unsigned)(n0 + lrow + 32 * h) * (unsigned)g.ldb + (unsigned)lk) * 2u;
+    }
+    const int nk = (g.K + kBK - 1) / kBK, nkp = (nk + kPF - 1) / kPF * kPF;
+    uint4 va[kPF][4], vb[kPF][4];
+    auto fetch = [&](int p, int kt) {
+        const bool in = kt * kBK + lk < g.K;  // K % 8 == 0: a thread's 8 columns are all in or all out
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            va[p][h] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, in ? oa[h] + (unsigned)kt * (kBK * 2) : kNoLoad, 0, 0));
+            vb[p][h] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, in ? ob[h] + (unsigned)kt * (kBK * 2) : kNoLoad, 0, 0));
         }
     };
-    auto stage = [&](int buf) {
+    auto stage = [&](int buf, int p) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = lrow + 64 * h;
-            *(uint4 *)(sA[buf] + r * kLdsRow + lk) = va[h];
-            *(uint4 *)(sB[buf] + r * kLdsRow + lk) = vb[h];
+        for (int h = 0; h < 4; ++h) {
+            const int r = lrow + 32 * h;
+            *(uint4 *)(sA[buf] + r * kLdsRow + lk) = va[p][h];
+            *(uint4 *)(sB[buf] + r * kLdsRow + lk) = vb[p][h];
         }
     };
-    fetch(0);
-    stage(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        const bool more = k0 + kBK < g.K;
-        if (more) fetch(k0 + kBK);  // in flight while this tile is multiplied
+    auto multiply = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 16) {
             // lane l supplies row (l % 32) of the 32 x 16 operand, k = kk + 8 (l / 32) .. + 7
@@ -130,31 +149,74 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        // the other buffer was last read before the previous barrier
-        if (more) stage(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
+    };
+#pragma unroll
+    for (int p = 0; p < kPF; ++p) fetch(p, p);
+    stage(0, 0);
+    __syncthreads();
+    // K tile k: its registers take tile k + kPF, LDS buffer k % 2 is multiplied,
+    // tile k + 1 is staged into the other buffer (read before the last barrier)
+    for (int kt = 0; kt < nkp; kt += kPF) {
+#pragma unroll
+        for (int p = 0; p < kPF; ++p) {
+            fetch(p, kt + p + kPF);
+            __builtin_amdgcn_sched_barrier(0);  // the loads go out before the multiply, not after it
+            multiply(p & 1);
+            stage((p + 1) & 1, (p + 1) % kPF);
+            __syncthreads();
+        }
     }
     // result layout of a 32x32 tile: lane l holds column l % 32, rows
-    // 8 (r / 4) + 4 (l / 32) + (r % 4) for r = 0 .. 15
+    // 8 (r / 4) + 4 (l / 32) + (r % 4) for r = 0 .. 15.  The epilogue has no
+    // branch: its inputs (bias per column, mask per element) are requested
+    // together, and its results stored, through buffer descriptors (elements
+    // outside the matrix read as zero and are not written; an absent bias,
+    // mask or output has an empty range), so the latency of the loads is paid
+    // once and no store waits for another.
+    const __amdgpu_buffer_rsrc_t rbias =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(g.bias), (short)0, g.bias ? g.N * 4 : 0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rmask = operand_rsrc(g.mask, g.mask ? g.M : 0, g.ldm);
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc(g.C, (short)0, g.C ? g.M * g.ldc * 4 : 0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rcb =
+        __builtin_amdgcn_make_buffer_rsrc(g.Cb, (short)0, g.Cb ? g.M * g.ldcb * 2 : 0, 0x00020000);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        float bn[2];
+        unsigned mk[2][16];  // the aligned 4 bytes holding each mask element (its own register: 2-byte
+                             // loads would share registers and wait for each other)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int n = n0 + wn * 64 + j * 32 + (lane & 31);
-            if (n >= g.N) continue;
-            const float bn = g.bias ? g.bias[n] : 0.0f;
+            bn[j] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rbias, n < g.N ? (unsigned)n * 4u : kNoLoad, 0, 0));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (m >= g.M) continue;
-                float v = g.alpha * acc[i][j][r] + bn;
-                if (g.mask && !(bf2f(g.mask[(int64_t)m * g.ldm + n]) > 0.0f)) v = 0.0f;
-                if (g.relu) v = v > 0.0f ? v : 0.0f;
-                if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
-                if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = f2bf(v);
+                const unsigned off = n < g.N ? ((unsigned)m * (unsigned)g.ldm + (unsigned)n) * 2u : kNoLoad;
+                mk[j][r] = __builtin_amdgcn_raw_buffer_load_b32(rmask, off & ~3u, 0, 0);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const bool in = m < g.M && n < g.N;
+                float v = g.alpha * acc[i][j][r] + bn[j];
+                const bf16_t mv = (bf16_t)(n & 1 ? mk[j][r] >> 16 : mk[j][r] & 0xffffu);
+                if (g.mask && !(bf2f(mv) > 0.0f)) v = 0.0f;
+                if (g.relu) v = v > 0.0f ? v : 0.0f;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rc,
+                                                      in ? ((unsigned)m * (unsigned)g.ldc + (unsigned)n) * 4u : kNoLoad,
+                                                      0, 0);
+                __builtin_amdgcn_raw_buffer_store_b16(f2bf(v), rcb,
+                                                      in ? ((unsigned)m * (unsigned)g.ldcb + (unsigned)n) * 2u : kNoLoad,
+                                                      0, 0);
+            }
+        }
+    }
 }
 
 // out[c][r] = in[r][c] (bf16, R x C -> C x R), 32 x 32 tiles through LDS
@@ -637,7 +699,12 @@ void free_surr(qw_surr *s) {
 
 hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
                 const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
-    if (K % kBK) return hipErrorInvalidValue;
+    if (K % kKAlign) return hipErrorInvalidValue;
+    // operand byte offsets (padded rows included) fit the descriptors' 31 bits
+    if ((int64_t)(M + kBM) * lda * 2 >= (int64_t)kNoLoad || (int64_t)(N + kBN) * ldb * 2 >= (int64_t)kNoLoad ||
+        (int64_t)(M + kBM) * ldm * 2 >= (int64_t)kNoLoad || (int64_t)(M + kBM) * ldc * 4 >= (int64_t)kNoLoad ||
+        (int64_t)(M + kBM) * ldcb * 2 >= (int64_t)kNoLoad)
+        return hipErrorInvalidValue;
     GemmArgs a{A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb};
     dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
     hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, a);
