@@ -88,12 +88,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const bf16_t *p, 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(p), (short)0, rows * ld * 2, 0x00020000);
 }
 
-__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+// One launch runs one product, or two independent ones side by side (blocks
+// [0, nb0) the first, gx0 blocks per row of tiles; the rest the second): the
+// batch-1024 training products have 64 tiles each, a quarter of the chip.
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int nb0, int gx0, int gx1) {
     __shared__ bf16_t sA[2][kBM * kLdsRow];
     __shared__ bf16_t sB[2][kBN * kLdsRow];
+    const bool second = (int)blockIdx.x >= nb0;
+    const GemmArgs g = second ? g1 : g0;
+    const int bl = second ? (int)blockIdx.x - nb0 : (int)blockIdx.x, gx = second ? gx1 : gx0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int m0 = (bl / gx) * kBM, n0 = (bl % gx) * kBN;
     float16_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -220,19 +226,27 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 }
 
 // out[c][r] = in[r][c] (bf16, R x C -> C x R), 32 x 32 tiles through LDS
-__global__ __launch_bounds__(256) void k_transpose(const bf16_t *__restrict__ in, int R, int C, int ldi,
-                                                   bf16_t *__restrict__ out, int ldo) {
+// (blockIdx.z picks one of two independent transposes, so a layer's two run in one launch)
+struct TrArgs {
+    const bf16_t *in;
+    int R, C, ldi;
+    bf16_t *out;
+    int ldo;
+};
+__global__ __launch_bounds__(256) void k_transpose(TrArgs a0, TrArgs a1) {
     __shared__ bf16_t t[32][33];
+    const TrArgs a = blockIdx.z ? a1 : a0;
     const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    if (c0 >= a.C || r0 >= a.R) return;  // the larger of the two grids: the whole block leaves
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int y = ty; y < 32; y += 8) {
         const int r = r0 + y, c = c0 + tx;
-        t[y][tx] = (r < R && c < C) ? in[(int64_t)r * ldi + c] : (bf16_t)0;
+        t[y][tx] = (r < a.R && c < a.C) ? a.in[(int64_t)r * a.ldi + c] : (bf16_t)0;
     }
     __syncthreads();
     for (int y = ty; y < 32; y += 8) {
         const int c = c0 + y, r = r0 + tx;
-        if (c < C && r < R) out[(int64_t)c * ldo + r] = t[tx][y];
+        if (c < a.C && r < a.R) a.out[(int64_t)c * a.ldo + r] = t[tx][y];
     }
 }
 
@@ -697,17 +711,34 @@ void free_surr(qw_surr *s) {
     delete s;
 }
 
-hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
-                const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
+hipError_t gemm_args(GemmArgs &a, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
+                     const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
     if (K % kKAlign) return hipErrorInvalidValue;
     // operand byte offsets (padded rows included) fit the descriptors' 31 bits
     if ((int64_t)(M + kBM) * lda * 2 >= (int64_t)kNoLoad || (int64_t)(N + kBN) * ldb * 2 >= (int64_t)kNoLoad ||
         (int64_t)(M + kBM) * ldm * 2 >= (int64_t)kNoLoad || (int64_t)(M + kBM) * ldc * 4 >= (int64_t)kNoLoad ||
         (int64_t)(M + kBM) * ldcb * 2 >= (int64_t)kNoLoad)
         return hipErrorInvalidValue;
-    GemmArgs a{A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb};
-    dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, a);
+    a = GemmArgs{A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb};
+    return hipSuccess;
+}
+inline int gemm_gx(const GemmArgs &a) { return (a.N + kBN - 1) / kBN; }
+inline int gemm_blocks(const GemmArgs &a) { return gemm_gx(a) * ((a.M + kBM - 1) / kBM); }
+
+hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
+                const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
+    GemmArgs a;
+    hipError_t e = gemm_args(a, A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb);
+    if (e != hipSuccess) return e;
+    const int nb = gemm_blocks(a);
+    hipLaunchKernelGGL(k_gemm_nt, dim3(nb), dim3(256), 0, st, a, a, nb, gemm_gx(a), gemm_gx(a));
+    return hipGetLastError();
+}
+
+// two independent products in one launch
+hipError_t gemm_pair(hipStream_t st, const GemmArgs &a, const GemmArgs &b) {
+    const int na = gemm_blocks(a), nb = gemm_blocks(b);
+    hipLaunchKernelGGL(k_gemm_nt, dim3(na + nb), dim3(256), 0, st, a, b, na, gemm_gx(a), gemm_gx(b));
     return hipGetLastError();
 }
 
@@ -720,8 +751,15 @@ hipError_t colsum(hipStream_t st, const float *dz, int B, int N, float *part, fl
 }
 
 hipError_t transpose(hipStream_t st, const bf16_t *in, int R, int C, int ldi, bf16_t *out, int ldo) {
+    const TrArgs a{in, R, C, ldi, out, ldo};
     dim3 grid((C + 31) / 32, (R + 31) / 32);
-    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, in, R, C, ldi, out, ldo);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, a, a);
+    return hipGetLastError();
+}
+
+hipError_t transpose_pair(hipStream_t st, const TrArgs &a, const TrArgs &b) {
+    dim3 grid((std::max(a.C, b.C) + 31) / 32, (std::max(a.R, b.R) + 31) / 32, 2);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, a, b);
     return hipGetLastError();
 }
 
@@ -815,21 +853,19 @@ hipError_t backward(qw_surr *s, int B) {
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, s->dzb, (int64_t)B * ly.kout);
         e = hipGetLastError();
-        if (e == hipSuccess) e = transpose(st, s->dzb, B, ly.kout, ly.kout, s->dzT, B);
-        if (e == hipSuccess) e = transpose(st, ly.hin, B, ly.kin, ly.kin, s->hT, B);
-        // dW[n][k] = sum_b dZ[b][n] Hin[b][k]
         if (e == hipSuccess)
-            e = gemm(st, s->dzT, B, s->hT, B, ly.kout, ly.kin, B, 1.0f, nullptr, nullptr, 0, 0, s->g + ly.W, ly.kin,
-                     nullptr, 0);
+            e = transpose_pair(st, TrArgs{s->dzb, B, ly.kout, ly.kout, s->dzT, B}, TrArgs{ly.hin, B, ly.kin, ly.kin, s->hT, B});
+        // dW[n][k] = sum_b dZ[b][n] Hin[b][k], and (below the first layer) dZ_prev = (dZ W)
+        // masked by the previous activation > 0: independent products, one launch
+        GemmArgs dw, dx;
+        if (e == hipSuccess)
+            e = gemm_args(dw, s->dzT, B, s->hT, B, ly.kout, ly.kin, B, 1.0f, nullptr, nullptr, 0, 0, s->g + ly.W, ly.kin,
+                          nullptr, 0);
+        if (e == hipSuccess && li > 0)
+            e = gemm_args(dx, s->dzb, ly.kout, ly.WT, ly.kout, B, ly.kin, ly.kout, 1.0f, nullptr, ly.hin, ly.kin, 0, s->dz,
+                          ly.kin, nullptr, 0);
+        if (e == hipSuccess) e = li > 0 ? gemm_pair(st, dw, dx) : gemm_pair(st, dw, GemmArgs{});
         if (e != hipSuccess) return e;
-        if (li > 0) {
-            // dZ_prev = (dZ W) masked by the previous activation > 0
-            const Lay &pv = lays[li - 1];
-            e = gemm(st, s->dzb, ly.kout, ly.WT, ly.kout, B, ly.kin, ly.kout, 1.0f, nullptr, ly.hin, ly.kin, 0, s->dz,
-                     ly.kin, nullptr, 0);
-            (void)pv;
-            if (e != hipSuccess) return e;
-        }
     }
     return hipSuccess;
 }
