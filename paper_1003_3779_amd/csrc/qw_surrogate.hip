@@ -689,7 +689,7 @@ struct qw_surr {
     bf16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;
     float *z4 = nullptr, *q = nullptr, *yb = nullptr, *dl = nullptr, *lrow = nullptr, *part = nullptr;
     float *dz = nullptr;                       // fp32 dz (bmax x 1024)
-    bf16_t *dzb = nullptr, *dzT = nullptr, *hT = nullptr;
+    bf16_t *dzb = nullptr, *dzb2 = nullptr, *dzT = nullptr, *hT = nullptr;  // dzb, dzb2: bf16 dZ of alternate layers
     int32_t *idx = nullptr;
     int32_t *tb = nullptr;                     // steps of the batch rows
     float *colpart = nullptr;                  // kColChunks x 1024 partial column sums
@@ -704,7 +704,7 @@ namespace {
 void free_surr(qw_surr *s) {
     if (!s) return;
     void *bufs[] = {s->p, s->m, s->v, s->g, s->pb, s->W2T, s->W3T, s->W4T, s->xb, s->h1, s->h2, s->h3,
-                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzT, s->hT, s->idx, s->tb,
+                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzb2, s->dzT, s->hT, s->idx, s->tb,
                     s->colpart};
     for (void *b : bufs) (void)hipFree(b);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -767,8 +767,9 @@ hipError_t transpose_pair(hipStream_t st, const TrArgs &a, const TrArgs &b) {
 hipError_t refresh_weights(qw_surr *s) {
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(2048), dim3(256), 0, s->stream, (const float *)s->p, s->pb, L.total);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2);
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3);
+    if (e == hipSuccess)
+        e = transpose_pair(s->stream, TrArgs{s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2},
+                           TrArgs{s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3});
     if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4);
     return e;
 }
@@ -848,13 +849,17 @@ hipError_t backward(qw_surr *s, int B) {
     };
     for (int li = 3; li >= 0; --li) {
         const Lay &ly = lays[li];
-        // s->dz holds dZ of this layer (fp32, B x kout)
+        // s->dz holds dZ of this layer (fp32, B x kout) and dzb its bf16 copy: made
+        // here for the top layer (from the head), else by the product below
+        bf16_t *dzb = (li & 1) ? s->dzb : s->dzb2, *dzb_next = (li & 1) ? s->dzb2 : s->dzb;
         e = colsum(st, (const float *)s->dz, B, ly.kout, s->colpart, s->g + ly.b);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, s->dzb, (int64_t)B * ly.kout);
-        e = hipGetLastError();
+        if (li == 3) {
+            hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, dzb, (int64_t)B * ly.kout);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess)
-            e = transpose_pair(st, TrArgs{s->dzb, B, ly.kout, ly.kout, s->dzT, B}, TrArgs{ly.hin, B, ly.kin, ly.kin, s->hT, B});
+            e = transpose_pair(st, TrArgs{dzb, B, ly.kout, ly.kout, s->dzT, B}, TrArgs{ly.hin, B, ly.kin, ly.kin, s->hT, B});
         // dW[n][k] = sum_b dZ[b][n] Hin[b][k], and (below the first layer) dZ_prev = (dZ W)
         // masked by the previous activation > 0: independent products, one launch
         GemmArgs dw, dx;
@@ -862,8 +867,8 @@ hipError_t backward(qw_surr *s, int B) {
             e = gemm_args(dw, s->dzT, B, s->hT, B, ly.kout, ly.kin, B, 1.0f, nullptr, nullptr, 0, 0, s->g + ly.W, ly.kin,
                           nullptr, 0);
         if (e == hipSuccess && li > 0)
-            e = gemm_args(dx, s->dzb, ly.kout, ly.WT, ly.kout, B, ly.kin, ly.kout, 1.0f, nullptr, ly.hin, ly.kin, 0, s->dz,
-                          ly.kin, nullptr, 0);
+            e = gemm_args(dx, dzb, ly.kout, ly.WT, ly.kout, B, ly.kin, ly.kout, 1.0f, nullptr, ly.hin, ly.kin, 0, s->dz,
+                          ly.kin, dzb_next, ly.kin);
         if (e == hipSuccess) e = li > 0 ? gemm_pair(st, dw, dx) : gemm_pair(st, dw, GemmArgs{});
         if (e != hipSuccess) return e;
     }
@@ -900,6 +905,7 @@ int alloc_surr(qw_surr *s) {
         {(void **)&s->yb, sizeof(float) * B * kBins}, {(void **)&s->dl, sizeof(float) * B * kBins},
         {(void **)&s->lrow, sizeof(float) * B}, {(void **)&s->part, sizeof(float) * B * 19},
         {(void **)&s->dz, sizeof(float) * B * 1024}, {(void **)&s->dzb, sizeof(bf16_t) * B * 1024},
+        {(void **)&s->dzb2, sizeof(bf16_t) * B * 1024},
         {(void **)&s->dzT, sizeof(bf16_t) * B * 1024}, {(void **)&s->hT, sizeof(bf16_t) * B * 1024},
         {(void **)&s->idx, sizeof(int32_t) * B}, {(void **)&s->tb, sizeof(int32_t) * B},
         {(void **)&s->colpart, sizeof(float) * kColChunks * 1024},
