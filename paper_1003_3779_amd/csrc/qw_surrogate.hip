@@ -365,17 +365,19 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     int T = Tst[b];
     T = T < 0 ? 0 : (T > kMaxSites - 1 ? kMaxSites - 1 : T);
     const int ns = T + 1;
-    const double clen = (double)ns / kCells;
     __syncthreads();
-    // site masses: m_k = sum over the cells overlapping [k, k+1) of q_j * overlap / clen
+    // site masses: m_k = sum over the cells overlapping [k, k+1) of q_j * overlap / clen,
+    // clen = ns / kCells sites.  In units of 1 / kCells site, cell j is [j ns, (j + 1) ns)
+    // and site k [kCells k, kCells (k + 1)): the overlaps are exact integers, and
+    // m_k = sum_j q_j ov_jk / ns with one division per site
     for (int k = t; k < ns; k += 256) {
-        const int j0 = (int)floor(k / clen);
+        const int s0 = kCells * k, s1 = s0 + kCells;
         double acc = 0.0;
-        for (int j = j0; j < kCells && j * clen < k + 1; ++j) {
-            const double lo = fmax(j * clen, (double)k), hi = fmin((j + 1) * clen, (double)(k + 1));
-            if (hi > lo) acc += (double)sq[j] * (hi - lo) / clen;
+        for (int j = s0 / ns; j < kCells && j * ns < s1; ++j) {
+            const int ov = min((j + 1) * ns, s1) - max(j * ns, s0);
+            if (ov > 0) acc += (double)sq[j] * (double)ov;
         }
-        sm[k] = (float)acc;
+        sm[k] = (float)(acc / ns);
     }
     __syncthreads();
     // bins: each bin gathers its sites (offsets of the parity of T) in a fixed order
@@ -428,18 +430,19 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
         sm[k] = gk;
     }
     __syncthreads();
-    // dq_j = sum over the sites overlapping cell j of g_k * overlap / clen
+    // dq_j = sum over the sites overlapping cell j of g_k * overlap / clen (integer
+    // overlaps in units of 1 / kCells site, as for the masses)
     float dq[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
         const int j = t + 256 * hh;
-        const double a0 = j * clen, a1 = (j + 1) * clen;
+        const int a0 = j * ns, a1 = a0 + ns;
         double acc = 0.0;
-        for (int k = (int)floor(a0); k < ns && k < a1; ++k) {
-            const double lo = fmax(a0, (double)k), hi = fmin(a1, (double)(k + 1));
-            if (hi > lo) acc += (double)sm[k] * (hi - lo) / clen;
+        for (int k = a0 / kCells; k < ns && kCells * k < a1; ++k) {
+            const int ov = min(a1, kCells * (k + 1)) - max(a0, kCells * k);
+            if (ov > 0) acc += (double)sm[k] * (double)ov;
         }
-        dq[hh] = (float)acc;
+        dq[hh] = (float)(acc / ns);
     }
     red[t] = q0 * dq[0] + q1 * dq[1];
     __syncthreads();
