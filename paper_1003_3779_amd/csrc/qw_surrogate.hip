@@ -255,28 +255,27 @@ __global__ void k_f32_to_bf16(const float *__restrict__ in, bf16_t *__restrict__
         out[i] = f2bf(in[i]);
 }
 
-// db[n] = sum_b dz[b][n] in two passes (fixed order, so deterministic): pass 1 sums
-// chunk r of ceil(B / kColChunks) rows of every column into part[r][n] over a
-// grid of (columns / 256) x kColChunks blocks; pass 2 adds the chunks in order
-constexpr int kColChunks = 64;
-__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ dz, int B, int N,
-                                                     float *__restrict__ part) {
-    const int n = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
-    if (n >= N) return;
-    const int rows = (B + kColChunks - 1) / kColChunks;
-    const int b0 = r * rows, b1 = min(B, b0 + rows);
+// db[n] = sum_b dz[b][n] in one pass with a fixed order (deterministic): a block
+// of 256 threads takes CW columns, G = 256 / CW row groups per column; group g
+// sums rows g, g + G, ... in order, then the G group sums are added in order
+template <int CW>
+__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ dz, int B, int N, float *__restrict__ db) {
+    constexpr int G = 256 / CW;
+    __shared__ float ps[G][CW];
+    const int c = threadIdx.x % CW, g = threadIdx.x / CW;
+    const int n = blockIdx.x * CW + c;
     float s = 0.0f;
-    for (int b = b0; b < b1; ++b) s += dz[(int64_t)b * N + n];
-    part[(int64_t)r * N + n] = s;
-}
-
-__global__ __launch_bounds__(256) void k_colsum_final(const float *__restrict__ part, int N,
-                                                      float *__restrict__ db) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int r = 0; r < kColChunks; ++r) s += part[(int64_t)r * N + n];
-    db[n] = s;
+    if (n < N) {
+#pragma unroll 16
+        for (int b = g; b < B; b += G) s += dz[(int64_t)b * N + n];
+    }
+    ps[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = 0.0f;
+        for (int q = 0; q < G; ++q) t += ps[q][c];
+        db[n] = t;
+    }
 }
 
 // ---------------------------------------------------------------- conv head
@@ -695,7 +694,6 @@ struct qw_surr {
     bf16_t *dzb = nullptr, *dzb2 = nullptr, *dzT = nullptr, *hT = nullptr;  // dzb, dzb2: bf16 dZ of alternate layers
     int32_t *idx = nullptr;
     int32_t *tb = nullptr;                     // steps of the batch rows
-    float *colpart = nullptr;                  // kColChunks x 1024 partial column sums
     int64_t adam_t = 0;
     uint64_t seed = 0;
     int64_t train_n = 4097;   // the ring size the network was trained on
@@ -707,8 +705,7 @@ namespace {
 void free_surr(qw_surr *s) {
     if (!s) return;
     void *bufs[] = {s->p, s->m, s->v, s->g, s->pb, s->W2T, s->W3T, s->W4T, s->xb, s->h1, s->h2, s->h3,
-                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzb2, s->dzT, s->hT, s->idx, s->tb,
-                    s->colpart};
+                    s->z4, s->q, s->yb, s->dl, s->lrow, s->part, s->dz, s->dzb, s->dzb2, s->dzT, s->hT, s->idx, s->tb};
     for (void *b : bufs) (void)hipFree(b);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -745,11 +742,11 @@ hipError_t gemm_pair(hipStream_t st, const GemmArgs &a, const GemmArgs &b) {
     return hipGetLastError();
 }
 
-// db[n] = sum_b dz[b][n] for N <= 1024 columns (two deterministic passes)
-hipError_t colsum(hipStream_t st, const float *dz, int B, int N, float *part, float *db) {
-    if (N > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_colsum_part, dim3((N + 255) / 256, kColChunks), dim3(256), 0, st, dz, B, N, part);
-    hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, st, (const float *)part, N, db);
+// db[n] = sum_b dz[b][n] (one deterministic pass; 16 columns per block, or one for a
+// single column so that its rows still spread over the block)
+hipError_t colsum(hipStream_t st, const float *dz, int B, int N, float *db) {
+    if (N >= 16) hipLaunchKernelGGL(k_colsum<16>, dim3((N + 15) / 16), dim3(256), 0, st, dz, B, N, db);
+    else hipLaunchKernelGGL(k_colsum<1>, dim3(N), dim3(256), 0, st, dz, B, N, db);
     return hipGetLastError();
 }
 
@@ -837,7 +834,7 @@ hipError_t backward(qw_surr *s, int B) {
     // their gradients, which follow each other in the parameter vector
     static_assert(2 * kTaps + 1 == 19, "conv head: 18 taps and one bias");
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = colsum(st, (const float *)s->part, B, 19, s->colpart, s->g + L.cw);
+    if (e == hipSuccess) e = colsum(st, (const float *)s->part, B, 19, s->g + L.cw);
     if (e != hipSuccess) return e;
     struct Lay {
         const bf16_t *hin;  // layer input activation (B x kin)
@@ -855,7 +852,7 @@ hipError_t backward(qw_surr *s, int B) {
         // s->dz holds dZ of this layer (fp32, B x kout) and dzb its bf16 copy: made
         // here for the top layer (from the head), else by the product below
         bf16_t *dzb = (li & 1) ? s->dzb : s->dzb2, *dzb_next = (li & 1) ? s->dzb2 : s->dzb;
-        e = colsum(st, (const float *)s->dz, B, ly.kout, s->colpart, s->g + ly.b);
+        e = colsum(st, (const float *)s->dz, B, ly.kout, s->g + ly.b);
         if (e != hipSuccess) return e;
         if (li == 3) {
             hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, dzb, (int64_t)B * ly.kout);
@@ -911,7 +908,6 @@ int alloc_surr(qw_surr *s) {
         {(void **)&s->dzb2, sizeof(bf16_t) * B * 1024},
         {(void **)&s->dzT, sizeof(bf16_t) * B * 1024}, {(void **)&s->hT, sizeof(bf16_t) * B * 1024},
         {(void **)&s->idx, sizeof(int32_t) * B}, {(void **)&s->tb, sizeof(int32_t) * B},
-        {(void **)&s->colpart, sizeof(float) * kColChunks * 1024},
     };
     for (auto &a : list) {
         hipError_t e = hipMalloc(a.p, a.bytes);
@@ -1125,7 +1121,7 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int
             if (e == hipSuccess) e = forward(s, B, B, s->yb);
             if (e == hipSuccess) e = backward(s, B);
             if (e == hipSuccess) e = adam_step(s, lr, o->weight_decay);
-            if (e == hipSuccess) e = colsum(s->stream, (const float *)s->lrow, B, 1, s->colpart, eloss + k);
+            if (e == hipSuccess) e = colsum(s->stream, (const float *)s->lrow, B, 1, eloss + k);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), eloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
