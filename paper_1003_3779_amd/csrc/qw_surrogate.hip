@@ -714,6 +714,9 @@ void free_surr(qw_surr *s) {
 hipError_t gemm_args(GemmArgs &a, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
                      const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
     if (K % kKAlign) return hipErrorInvalidValue;
+    // the mask is read as the aligned 4 bytes holding each element: with an even
+    // row stride the last element's 4 bytes lie inside the matrix
+    if (mask && (ldm & 1)) return hipErrorInvalidValue;
     // operand byte offsets (padded rows included) fit the descriptors' 31 bits
     if ((int64_t)(M + kBM) * lda * 2 >= (int64_t)kNoLoad || (int64_t)(N + kBN) * ldb * 2 >= (int64_t)kNoLoad ||
         (int64_t)(M + kBM) * ldm * 2 >= (int64_t)kNoLoad || (int64_t)(M + kBM) * ldc * 4 >= (int64_t)kNoLoad ||
