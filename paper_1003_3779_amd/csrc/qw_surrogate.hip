@@ -311,12 +311,42 @@ __device__ __forceinline__ void site_bins(int dx, int w, int &b0, float &s0, int
 // One block (256 threads) per sample: l = conv(z4) + cb, q = softmax(l),
 // p = the binned distribution; with targets y: the per-sample KL(y || p) and
 // dl = dL/dl (already divided by Bscale).
+// Reductions over a 256-thread block: inside each wave by lane exchanges (a
+// butterfly: every lane ends with the same value, added in the same order every
+// time), then the four wave values in order.  red4: four floats of LDS.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float block_sum(float v, float *red4) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+    __syncthreads();  // red4 free for the next reduction
+    return r;
+}
+__device__ __forceinline__ float block_max(float v, float *red4) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = fmaxf(fmaxf(red4[0], red4[1]), fmaxf(red4[2], red4[3]));
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, const float *__restrict__ cw,
                                                   const float *__restrict__ cb, const int32_t *__restrict__ Tst,
                                                   int w, float *__restrict__ pout, const float *__restrict__ y,
                                                   float *__restrict__ dl, float *__restrict__ loss_row, int Bscale) {
     __shared__ float sz[2][kBins + 2 * kPad];
-    __shared__ float red[256];
+    __shared__ float red4[4];
     __shared__ float sq[kCells];
     __shared__ float sm[kMaxSites];   // site masses, then site gradients
     __shared__ float sg[kBins];       // bin gradients
@@ -341,23 +371,9 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
         l[h] = v;
         mx = fmaxf(mx, v);
     }
-    red[t] = mx;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] = fmaxf(red[t], red[t + s]);
-        __syncthreads();
-    }
-    mx = red[0];
-    __syncthreads();
+    mx = block_max(mx, red4);
     const float e0 = expf(l[0] - mx), e1 = expf(l[1] - mx);
-    red[t] = e0 + e1;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const float den = red[0];
-    __syncthreads();
+    const float den = block_sum(e0 + e1, red4);
     const float q0 = e0 / den, q1 = e1 / den;
     sq[t] = q0;
     sq[t + 256] = q1;
@@ -412,13 +428,8 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     if (y1 > 0.0f) lv += y1 * (logf(y1) - logf(fmaxf(pb[1], 1e-30f)));
     sg[t] = y0 > 0.0f ? -y0 / fmaxf(pb[0], 1e-30f) / (float)Bscale : 0.0f;
     sg[t + 256] = y1 > 0.0f ? -y1 / fmaxf(pb[1], 1e-30f) / (float)Bscale : 0.0f;
-    red[t] = lv;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    if (t == 0) loss_row[b] = red[0];
+    const float lsum = block_sum(lv, red4);  // (its barriers also publish sg)
+    if (t == 0) loss_row[b] = lsum;
     // site gradients (a site lies in one bin, the start site half in each middle bin)
     for (int k = t; k < ns; k += 256) {
         int b0, b1;
@@ -443,13 +454,7 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
         }
         dq[hh] = (float)(acc / ns);
     }
-    red[t] = q0 * dq[0] + q1 * dq[1];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const float qdq = red[0];
+    const float qdq = block_sum(q0 * dq[0] + q1 * dq[1], red4);
     dl[(int64_t)b * kBins + t] = q0 * (dq[0] - qdq);
     dl[(int64_t)b * kBins + t + 256] = q1 * (dq[1] - qdq);
 }
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, 
                                                   float *__restrict__ part /* B x 19 */) {
     __shared__ float sdl[kBins + 2 * kPad];
     __shared__ float sz[2][kBins + 2 * kPad];
-    __shared__ float red[19][256];
+    __shared__ float red4[19][4];
     const int b = blockIdx.x, t = threadIdx.x;
     for (int i = t; i < kBins + 2 * kPad; i += 256) {
         const int p = i - kPad;
@@ -493,15 +498,12 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, 
         g[18] += d;
     }
 #pragma unroll
-    for (int k = 0; k < 19; ++k) red[k][t] = g[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s)
-#pragma unroll
-            for (int k = 0; k < 19; ++k) red[k][t] += red[k][t + s];
-        __syncthreads();
+    for (int k = 0; k < 19; ++k) {
+        const float v = wave_sum(g[k]);
+        if ((t & 63) == 0) red4[k][t >> 6] = v;
     }
-    if (t < 19) part[(int64_t)b * 19 + t] = red[t][0];
+    __syncthreads();
+    if (t < 19) part[(int64_t)b * 19 + t] = ((red4[t][0] + red4[t][1]) + red4[t][2]) + red4[t][3];
 }
 
 // Adam on fp32 master weights; writes the bf16 copy used by the GEMMs
