@@ -341,6 +341,25 @@ __device__ __forceinline__ float block_max(float v, float *red4) {
     return r;
 }
 
+// sum_j q_j ov_j over the cells overlapping [u0, u1) (units of 1 / kCells site;
+// cell j is [j ns, (j + 1) ns)), the overlaps exact integers
+__device__ __forceinline__ double cell_overlap_sum(const float *sq, int u0, int u1, int ns, float rns) {
+    // first cell floor(u0 / ns): a single-precision estimate is within one of it
+    // (u0 < 2^21), then set exactly in integers
+    int j = (int)((float)u0 * rns);
+    j -= j * ns > u0;
+    j += (j + 1) * ns <= u0;
+    double acc = 0.0;
+    for (; j < kCells && j * ns < u1; ++j) {
+        const int ov = min((j + 1) * ns, u1) - max(j * ns, u0);
+        acc += (double)sq[j] * (double)ov;
+    }
+    return acc;
+}
+
+// TRAIN: with targets y (loss and dl; the site gradients need a site array),
+// else the prediction pass only
+template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, const float *__restrict__ cw,
                                                   const float *__restrict__ cb, const int32_t *__restrict__ Tst,
                                                   int w, float *__restrict__ pout, const float *__restrict__ y,
@@ -348,8 +367,8 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     __shared__ float sz[2][kBins + 2 * kPad];
     __shared__ float red4[4];
     __shared__ float sq[kCells];
-    __shared__ float sm[kMaxSites];   // site masses, then site gradients
-    __shared__ float sg[kBins];       // bin gradients
+    __shared__ float sm[TRAIN ? kMaxSites : 1];  // site gradients
+    __shared__ float sg[TRAIN ? kBins : 1];      // bin gradients
     const int b = blockIdx.x, t = threadIdx.x;
     const float *zr = z4 + (int64_t)b * kZ4;
     for (int i = t; i < kBins + 2 * kPad; i += 256) {
@@ -380,48 +399,29 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     int T = Tst[b];
     T = T < 0 ? 0 : (T > kMaxSites - 1 ? kMaxSites - 1 : T);
     const int ns = T + 1;
+    const double inv_ns = 1.0 / (double)ns;
+    const float rns = 1.0f / (float)ns;
     __syncthreads();
-    // site masses: m_k = sum over the cells overlapping [k, k+1) of q_j * overlap / clen,
-    // clen = ns / kCells sites.  In units of 1 / kCells site, cell j is [j ns, (j + 1) ns)
-    // and site k [kCells k, kCells (k + 1)): the overlaps are exact integers, and
-    // m_k = sum_j q_j ov_jk / ns with one division per site
-    for (int k = t; k < ns; k += 256) {
-        const int s0 = kCells * k, s1 = s0 + kCells;
-        double acc = 0.0;
-        for (int j = s0 / ns; j < kCells && j * ns < s1; ++j) {
-            const int ov = min((j + 1) * ns, s1) - max(j * ns, s0);
-            if (ov > 0) acc += (double)sq[j] * (double)ov;
-        }
-        sm[k] = (float)(acc / ns);
-    }
-    __syncthreads();
-    // bins: each bin gathers its sites (offsets of the parity of T) in a fixed order
+    // bins: p = R(T) q.  The sites of bin b (offsets dx = 2k - T in its range, of
+    // the parity of T) are a run k = ka..kb, i.e. [kCells ka, kCells (kb + 1)) in
+    // units of 1 / kCells site, so p_b = sum_j q_j ov_j / ns over the cells the run
+    // overlaps; the start site (dx = 0, T even) gives half its mass to each middle bin
     const int hb = kBins / 2;
     float pb[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
         const int bin = t + 256 * hh;
-        int lo, hi;
-        if (bin < hb) {
-            lo = -(hb - bin) * w;
-            hi = -(hb - bin - 1) * w - 1;
-        } else {
-            lo = (bin - hb) * w + 1;
-            hi = (bin - hb + 1) * w;
-        }
-        float acc = 0.0f;
-        if (bin == hb - 1 || bin == hb) {  // half of the start site
-            if ((T & 1) == 0) acc += 0.5f * sm[T / 2];
-        }
-        for (int dx = lo; dx <= hi; ++dx) {
-            const int kk = T + dx;
-            if ((kk & 1) || kk < 0 || kk > 2 * T) continue;
-            acc += sm[kk >> 1];
-        }
-        pb[hh] = acc;
-        if (pout) pout[(int64_t)b * kBins + bin] = acc;
+        const int lo = bin < hb ? -(hb - bin) * w : (bin - hb) * w + 1;
+        const int hi = bin < hb ? -(hb - bin - 1) * w - 1 : (bin - hb + 1) * w;
+        const int ka = max((T + lo + 1) >> 1, 0), kb = min((T + hi) >> 1, T);  // ceil, floor
+        double acc = ka <= kb ? cell_overlap_sum(sq, kCells * ka, kCells * (kb + 1), ns, rns) : 0.0;
+        if ((bin == hb - 1 || bin == hb) && (T & 1) == 0)
+            acc += 0.5 * cell_overlap_sum(sq, kCells * (T / 2), kCells * (T / 2 + 1), ns, rns);
+        const float v = (float)(acc * inv_ns);
+        pb[hh] = v;
+        if (pout) pout[(int64_t)b * kBins + bin] = v;
     }
-    if (!y) return;  // uniform across the block
+    if constexpr (!TRAIN) return;
     const float y0 = y[(int64_t)b * kBins + t], y1 = y[(int64_t)b * kBins + t + 256];
     float lv = 0.0f;
     if (y0 > 0.0f) lv += y0 * (logf(y0) - logf(fmaxf(pb[0], 1e-30f)));
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
             const int ov = min(a1, kCells * (k + 1)) - max(a0, kCells * k);
             if (ov > 0) acc += (double)sm[k] * (double)ov;
         }
-        dq[hh] = (float)(acc / ns);
+        dq[hh] = (float)(acc * inv_ns);
     }
     const float qdq = block_sum(q0 * dq[0] + q1 * dq[1], red4);
     dl[(int64_t)b * kBins + t] = q0 * (dq[0] - qdq);
@@ -797,8 +797,14 @@ hipError_t forward(qw_surr *s, int B, int Bscale, const float *y, const bf16_t *
         e = gemm(st, s->h3, kH3, s->pb + L.W4, kH3, B, kZ4, kH3, 1.0f, s->p + L.b4, nullptr, 0, 0, s->z4, kZ4, nullptr, 0);
     if (e != hipSuccess) return e;
     const int w = (int)(((s->train_n - 1) / 2) / (kBins / 2));
-    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
-                       (const float *)(s->p + L.cb), tin, w < 1 ? 1 : w, qout, y, s->dl, s->lrow, Bscale);
+    if (y)
+        hipLaunchKernelGGL(k_head_fwd<true>, dim3(B), dim3(256), 0, st, (const float *)s->z4,
+                           (const float *)(s->p + L.cw), (const float *)(s->p + L.cb), tin, w < 1 ? 1 : w, qout, y,
+                           s->dl, s->lrow, Bscale);
+    else
+        hipLaunchKernelGGL(k_head_fwd<false>, dim3(B), dim3(256), 0, st, (const float *)s->z4,
+                           (const float *)(s->p + L.cw), (const float *)(s->p + L.cb), tin, w < 1 ? 1 : w, qout,
+                           nullptr, nullptr, nullptr, Bscale);
     return hipGetLastError();
 }
 
