@@ -233,11 +233,12 @@ struct TrArgs {
     bf16_t *out;
     int ldo;
 };
-__global__ __launch_bounds__(256) void k_transpose(TrArgs a0, TrArgs a1) {
+// one 32 x 32 tile (bx, by) of out = in^T; tiles past the matrix leave at once
+// (uniform over the block)
+__device__ __forceinline__ void transpose_tile(const TrArgs &a, int bx, int by) {
     __shared__ bf16_t t[32][33];
-    const TrArgs a = blockIdx.z ? a1 : a0;
-    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-    if (c0 >= a.C || r0 >= a.R) return;  // the larger of the two grids: the whole block leaves
+    const int c0 = bx * 32, r0 = by * 32;
+    if (c0 >= a.C || r0 >= a.R) return;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int y = ty; y < 32; y += 8) {
         const int r = r0 + y, c = c0 + tx;
@@ -250,32 +251,64 @@ __global__ __launch_bounds__(256) void k_transpose(TrArgs a0, TrArgs a1) {
     }
 }
 
+// up to three independent transposes, blockIdx.z choosing (the grid covers the
+// largest)
+__global__ __launch_bounds__(256) void k_transpose(TrArgs a0, TrArgs a1, TrArgs a2) {
+    transpose_tile(blockIdx.z == 0 ? a0 : (blockIdx.z == 1 ? a1 : a2), blockIdx.x, blockIdx.y);
+}
+
 __global__ void k_f32_to_bf16(const float *__restrict__ in, bf16_t *__restrict__ out, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = f2bf(in[i]);
 }
 
-// db[n] = sum_b dz[b][n] in one pass with a fixed order (deterministic): a block
+// db[n] = sum_b dz[b][n] in one pass with a fixed order (deterministic): block bx
 // of 256 threads takes CW columns, G = 256 / CW row groups per column; group g
 // sums rows g, g + G, ... in order, then the G group sums are added in order
+// (CW = 1 for a single column, so that its rows still spread over the block)
+struct ColArgs {
+    const float *dz;  // B x N, row-major
+    int B, N;
+    float *db;        // N
+};
 template <int CW>
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ dz, int B, int N, float *__restrict__ db) {
+__device__ __forceinline__ void colsum_block(const ColArgs &a, int bx) {
     constexpr int G = 256 / CW;
     __shared__ float ps[G][CW];
     const int c = threadIdx.x % CW, g = threadIdx.x / CW;
-    const int n = blockIdx.x * CW + c;
+    const int n = bx * CW + c;
     float s = 0.0f;
-    if (n < N) {
+    if (n < a.N) {
 #pragma unroll 16
-        for (int b = g; b < B; b += G) s += dz[(int64_t)b * N + n];
+        for (int b = g; b < a.B; b += G) s += a.dz[(int64_t)b * a.N + n];
     }
     ps[g][c] = s;
     __syncthreads();
-    if (g == 0 && n < N) {
+    if (g == 0 && n < a.N) {
         float t = 0.0f;
         for (int q = 0; q < G; ++q) t += ps[q][c];
-        db[n] = t;
+        a.db[n] = t;
     }
+}
+// What one layer of the backward pass needs before its two products, in one
+// launch: the transposes of its bf16 dZ and of its input activation (2 gx gy
+// tile blocks), the column sums of its fp32 dZ (its bias gradient) and,
+// optionally, of a second matrix (16 columns per block, at least 16 columns)
+// and of a third (one block per column)
+__global__ __launch_bounds__(256) void k_layer_prep(TrArgs t0, TrArgs t1, int gx, int gy, ColArgs c0, ColArgs c1,
+                                                    ColArgs c2) {
+    int lb = blockIdx.x;
+    const int ntr = gx * gy;
+    if (lb < 2 * ntr) {
+        const int z = lb >= ntr, r = lb - z * ntr;
+        transpose_tile(z ? t1 : t0, r % gx, r / gx);
+        return;
+    }
+    lb -= 2 * ntr;
+    const int n0 = (c0.N + 15) / 16, n1 = (c1.N + 15) / 16;
+    if (lb < n0) colsum_block<16>(c0, lb);
+    else if (lb < n0 + n1) colsum_block<16>(c1, lb - n0);
+    else colsum_block<1>(c2, lb - n0 - n1);
 }
 
 // ---------------------------------------------------------------- conv head
@@ -459,11 +492,12 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float *__restrict__ z4, 
     dl[(int64_t)b * kBins + t + 256] = q1 * (dq[1] - qdq);
 }
 
-// Backward of the head for one sample: dz4[c][p] = sum_j cw[c][j] dl[p - j + pad];
-// per-sample partial gradients of the 18 taps and the bias (reduced later).
+// Backward of the head for one sample: dz4[c][p] = sum_j cw[c][j] dl[p - j + pad]
+// (fp32, and its bf16 rounding dz4b for the top layer's products); per-sample
+// partial gradients of the 18 taps and the bias (reduced later).
 __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, const float *__restrict__ cw,
                                                   const float *__restrict__ dl, float *__restrict__ dz4,
-                                                  float *__restrict__ part /* B x 19 */) {
+                                                  bf16_t *__restrict__ dz4b, float *__restrict__ part /* B x 19 */) {
     __shared__ float sdl[kBins + 2 * kPad];
     __shared__ float sz[2][kBins + 2 * kPad];
     __shared__ float red4[19][4];
@@ -489,6 +523,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, 
 #pragma unroll
             for (int j = 0; j < kTaps; ++j) v += cw[c * kTaps + j] * sdl[p - j + 2 * kPad];
             dz4[(int64_t)b * kZ4 + c * kBins + p] = v;
+            dz4b[(int64_t)b * kZ4 + c * kBins + p] = f2bf(v);
         }
         const float d = sdl[p + kPad];
 #pragma unroll
@@ -747,35 +782,42 @@ hipError_t gemm_pair(hipStream_t st, const GemmArgs &a, const GemmArgs &b) {
     return hipGetLastError();
 }
 
-// db[n] = sum_b dz[b][n] (one deterministic pass; 16 columns per block, or one for a
-// single column so that its rows still spread over the block)
-hipError_t colsum(hipStream_t st, const float *dz, int B, int N, float *db) {
-    if (N >= 16) hipLaunchKernelGGL(k_colsum<16>, dim3((N + 15) / 16), dim3(256), 0, st, dz, B, N, db);
-    else hipLaunchKernelGGL(k_colsum<1>, dim3(N), dim3(256), 0, st, dz, B, N, db);
+// n (1 to 3) independent transposes in one launch
+hipError_t transposes(hipStream_t st, const TrArgs *a, int n) {
+    int mc = 0, mr = 0;
+    for (int i = 0; i < n; ++i) {
+        mc = std::max(mc, a[i].C);
+        mr = std::max(mr, a[i].R);
+    }
+    const dim3 grid((mc + 31) / 32, (mr + 31) / 32, n);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, a[0], a[n > 1 ? 1 : 0], a[n > 2 ? 2 : 0]);
     return hipGetLastError();
 }
 
-hipError_t transpose(hipStream_t st, const bf16_t *in, int R, int C, int ldi, bf16_t *out, int ldo) {
-    const TrArgs a{in, R, C, ldi, out, ldo};
-    dim3 grid((C + 31) / 32, (R + 31) / 32);
-    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, a, a);
+// one backward layer's transposes and column sums (k_layer_prep); c1.N, c2.N = 0:
+// none
+hipError_t layer_prep(hipStream_t st, const TrArgs &t0, const TrArgs &t1, const ColArgs &c0, const ColArgs &c1,
+                      const ColArgs &c2) {
+    if (c0.N < 16 || (c1.N != 0 && c1.N < 16) || c2.N < 0) return hipErrorInvalidValue;
+    const int gx = (std::max(t0.C, t1.C) + 31) / 32, gy = (std::max(t0.R, t1.R) + 31) / 32;
+    const int blocks = 2 * gx * gy + (c0.N + 15) / 16 + (c1.N + 15) / 16 + c2.N;
+    hipLaunchKernelGGL(k_layer_prep, dim3(blocks), dim3(256), 0, st, t0, t1, gx, gy, c0, c1, c2);
     return hipGetLastError();
 }
 
-hipError_t transpose_pair(hipStream_t st, const TrArgs &a, const TrArgs &b) {
-    dim3 grid((std::max(a.C, b.C) + 31) / 32, (std::max(a.R, b.R) + 31) / 32, 2);
-    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, a, b);
-    return hipGetLastError();
+// the transposed bf16 weights the input-gradient products read
+hipError_t weight_transposes(qw_surr *s) {
+    const TrArgs t[3] = {TrArgs{s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2},
+                         TrArgs{s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3},
+                         TrArgs{s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4}};
+    return transposes(s->stream, t, 3);
 }
 
 // refresh the bf16 mirror (from p) and the transposed weights
 hipError_t refresh_weights(qw_surr *s) {
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(2048), dim3(256), 0, s->stream, (const float *)s->p, s->pb, L.total);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess)
-        e = transpose_pair(s->stream, TrArgs{s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2},
-                           TrArgs{s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3});
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4);
+    if (e == hipSuccess) e = weight_transposes(s);
     return e;
 }
 
@@ -837,15 +879,19 @@ struct NetBufs {
 };
 
 // backward of the batch of the last forward (with targets): gradients into s->g
-hipError_t backward(qw_surr *s, int B) {
+// loss_sum (device, optional): receives the sum of the per-sample losses the
+// forward pass left in s->lrow
+hipError_t backward(qw_surr *s, int B, float *loss_sum = nullptr) {
     hipStream_t st = s->stream;
+    // dZ of the top layer, fp32 and the bf16 copy its products read (the buffer
+    // the loop below takes for layer 3)
     hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, st, (const float *)s->z4, (const float *)(s->p + L.cw),
-                       (const float *)s->dl, s->dz, s->part);
+                       (const float *)s->dl, s->dz, s->dzb, s->part);
     // per-sample conv-head partials (B x 19: 18 tap weights, then the bias) ->
-    // their gradients, which follow each other in the parameter vector
+    // their gradients, which follow each other in the parameter vector: summed
+    // with the top layer's bias gradient
     static_assert(2 * kTaps + 1 == 19, "conv head: 18 taps and one bias");
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = colsum(st, (const float *)s->part, B, 19, s->g + L.cw);
     if (e != hipSuccess) return e;
     struct Lay {
         const bf16_t *hin;  // layer input activation (B x kin)
@@ -861,16 +907,12 @@ hipError_t backward(qw_surr *s, int B) {
     for (int li = 3; li >= 0; --li) {
         const Lay &ly = lays[li];
         // s->dz holds dZ of this layer (fp32, B x kout) and dzb its bf16 copy: made
-        // here for the top layer (from the head), else by the product below
+        // by the head's backward for the top layer, else by the product below
         bf16_t *dzb = (li & 1) ? s->dzb : s->dzb2, *dzb_next = (li & 1) ? s->dzb2 : s->dzb;
-        e = colsum(st, (const float *)s->dz, B, ly.kout, s->g + ly.b);
-        if (e != hipSuccess) return e;
-        if (li == 3) {
-            hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, (const float *)s->dz, dzb, (int64_t)B * ly.kout);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess)
-            e = transpose_pair(st, TrArgs{dzb, B, ly.kout, ly.kout, s->dzT, B}, TrArgs{ly.hin, B, ly.kin, ly.kin, s->hT, B});
+        e = layer_prep(st, TrArgs{dzb, B, ly.kout, ly.kout, s->dzT, B}, TrArgs{ly.hin, B, ly.kin, ly.kin, s->hT, B},
+                       ColArgs{s->dz, B, ly.kout, s->g + ly.b},
+                       li == 3 ? ColArgs{s->part, B, 19, s->g + L.cw} : ColArgs{nullptr, 0, 0, nullptr},
+                       li == 3 && loss_sum ? ColArgs{s->lrow, B, 1, loss_sum} : ColArgs{nullptr, 0, 0, nullptr});
         // dW[n][k] = sum_b dZ[b][n] Hin[b][k], and (below the first layer) dZ_prev = (dZ W)
         // masked by the previous activation > 0: independent products, one launch
         GemmArgs dw, dx;
@@ -893,9 +935,7 @@ hipError_t adam_step(qw_surr *s, float lr, float wd) {
     hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, s->stream, s->p, s->m, s->v, (const float *)s->g, s->pb,
                        L.total, lr, b1, b2, eps, c1, c2, wd);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W2, kH2, kH1, kH1, s->W2T, kH2);
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W3, kH3, kH2, kH2, s->W3T, kH3);
-    if (e == hipSuccess) e = transpose(s->stream, s->pb + L.W4, kZ4, kH3, kH3, s->W4T, kZ4);
+    if (e == hipSuccess) e = weight_transposes(s);
     return e;
 }
 
@@ -1130,9 +1170,8 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int
                                s->xb, s->yb, s->tb);
             e = hipGetLastError();
             if (e == hipSuccess) e = forward(s, B, B, s->yb);
-            if (e == hipSuccess) e = backward(s, B);
+            if (e == hipSuccess) e = backward(s, B, eloss + k);
             if (e == hipSuccess) e = adam_step(s, lr, o->weight_decay);
-            if (e == hipSuccess) e = colsum(s->stream, (const float *)s->lrow, B, 1, eloss + k);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), eloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
