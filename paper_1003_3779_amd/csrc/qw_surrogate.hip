@@ -541,11 +541,36 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ z4, 
     if (t < 19) part[(int64_t)b * 19 + t] = ((red4[t][0] + red4[t][1]) + red4[t][2]) + red4[t][3];
 }
 
-// Adam on fp32 master weights; writes the bf16 copy used by the GEMMs
+// rows idx[i] of X (n x 32 fp32), Y (n x 512 fp32) and Ts (n) -> batch buffers (X as bf16)
+struct GatherArgs {
+    const float *X, *Y;
+    const int32_t *Ts, *idx;
+    int B;  // 0: nothing to gather
+    bf16_t *xb;
+    float *yb;
+    int32_t *tb;
+};
+__device__ __forceinline__ void gather_row(const GatherArgs &a, int b) {
+    if (b >= a.B) return;
+    const int64_t r = a.idx[b];
+    if (threadIdx.x == 0) a.tb[b] = a.Ts[r];
+    for (int i = threadIdx.x; i < kF; i += blockDim.x) a.xb[(int64_t)b * kF + i] = f2bf(a.X[r * kF + i]);
+    if (a.Y)
+        for (int i = threadIdx.x; i < kBins; i += blockDim.x) a.yb[(int64_t)b * kBins + i] = a.Y[r * kBins + i];
+}
+__global__ void k_gather(GatherArgs a) { gather_row(a, blockIdx.x); }
+
+// Adam on fp32 master weights over blocks [0, na); writes the bf16 copy used by
+// the GEMMs.  Blocks past na gather the next training batch (its rows are not
+// read by anything this step still has to do).
 __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ g, bf16_t *__restrict__ pb, int64_t n, float lr, float b1,
-                       float b2, float eps, float c1, float c2, float wd) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+                       float b2, float eps, float c1, float c2, float wd, int na, GatherArgs next) {
+    if ((int)blockIdx.x >= na) {
+        gather_row(next, (int)blockIdx.x - na);
+        return;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)na * blockDim.x) {
         const float gi = g[i] + wd * p[i];
         const float mi = b1 * m[i] + (1.0f - b1) * gi;
         const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -555,19 +580,6 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
         p[i] = pi;
         if (pb) pb[i] = f2bf(pi);
     }
-}
-
-// rows idx[i] of X (n x 32 fp32), Y (n x 512 fp32) and Ts (n) -> batch buffers (X as bf16)
-__global__ void k_gather(const float *__restrict__ X, const float *__restrict__ Y, const int32_t *__restrict__ Ts,
-                         const int32_t *__restrict__ idx, int B, bf16_t *__restrict__ xb, float *__restrict__ yb,
-                         int32_t *__restrict__ tb) {
-    const int b = blockIdx.x;
-    if (b >= B) return;
-    const int64_t r = idx[b];
-    if (threadIdx.x == 0) tb[b] = Ts[r];
-    for (int i = threadIdx.x; i < kF; i += blockDim.x) xb[(int64_t)b * kF + i] = f2bf(X[r * kF + i]);
-    if (Y)
-        for (int i = threadIdx.x; i < kBins; i += blockDim.x) yb[(int64_t)b * kBins + i] = Y[r * kBins + i];
 }
 
 // features of a walk: sin/cos of (theta, phi, chi); the start state with its
@@ -928,12 +940,14 @@ hipError_t backward(qw_surr *s, int B, float *loss_sum = nullptr) {
     return hipSuccess;
 }
 
-hipError_t adam_step(qw_surr *s, float lr, float wd) {
+// next.B > 0: the same launch gathers the next training batch
+hipError_t adam_step(qw_surr *s, float lr, float wd, const GatherArgs &next) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     s->adam_t += 1;
     const float c1 = 1.0f - powf(b1, (float)s->adam_t), c2 = 1.0f - powf(b2, (float)s->adam_t);
-    hipLaunchKernelGGL(k_adam, dim3(2048), dim3(256), 0, s->stream, s->p, s->m, s->v, (const float *)s->g, s->pb,
-                       L.total, lr, b1, b2, eps, c1, c2, wd);
+    constexpr int na = 2048;
+    hipLaunchKernelGGL(k_adam, dim3(na + std::max(next.B, 0)), dim3(256), 0, s->stream, s->p, s->m, s->v,
+                       (const float *)s->g, s->pb, L.total, lr, b1, b2, eps, c1, c2, wd, na, next);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = weight_transposes(s);
     return e;
@@ -1166,12 +1180,19 @@ int surr_train(qw_surr_t s, int64_t n, const float *X, const float *Y, const int
         for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
             const double prog = std::min(1.0, ((double)(o->epoch_offset + ep) * steps + k) / ((double)sched * steps));
             const float lr = (float)(o->lr * (o->lr_floor + (1.0 - o->lr_floor) * 0.5 * (1.0 + cos(3.14159265358979 * prog))));
-            hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, X, Y, T, (const int32_t *)(perm + k * B), B,
-                               s->xb, s->yb, s->tb);
-            e = hipGetLastError();
+            // the batch of step k: gathered here for the first step of the epoch, else by
+            // the previous step's Adam launch
+            auto batch = [&](int64_t kk) {
+                return GatherArgs{X, Y, T, (const int32_t *)(perm + kk * B), B, s->xb, s->yb, s->tb};
+            };
+            if (k == 0) {
+                hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s->stream, batch(0));
+                e = hipGetLastError();
+            }
             if (e == hipSuccess) e = forward(s, B, B, s->yb);
             if (e == hipSuccess) e = backward(s, B, eloss + k);
-            if (e == hipSuccess) e = adam_step(s, lr, o->weight_decay);
+            if (e == hipSuccess)
+                e = adam_step(s, lr, o->weight_decay, k + 1 < steps ? batch(k + 1) : GatherArgs{});
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), eloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
