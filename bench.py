@@ -292,7 +292,12 @@ def ragged_rings(args):
         "walks_per_s": args.rings * args.steps / (t1 - t0),
         "kernel_ms": ms, "grid": info.grid, "whole_ring_walks": info.whole_ring_walks,
         "tiled_variant_per_bucket": [[info.bucket_tile_sites[k], info.bucket_depth[k]] for k in range(3)],
+        # performed updates (value, roofline): rings whose cone never wraps run on the
+        # live sublattice, half of their light cone; the light cone's count (the
+        # method's window, both parities) beside it
         "est_updates_per_run": info.est_updates,
+        "est_cone_updates_per_run": info.est_cone_updates,
+        "cone_updates_per_s": info.est_cone_updates * args.steps / (t1 - t0),
         # the batch kernel is bound by its fp32 arithmetic: per site and step the
         # rotation coin, factored as f [[1, t], [-t, 1]], costs 4 FMAs (8 flops),
         # 4 per site*coin update; peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
@@ -917,7 +922,8 @@ def extra_ragged(args):
     a = argparse.Namespace(**vars(args))
     a.steps, a.warmup, a.tune, a.rings, a.nmax = 1, 0, False, 4096, 999999
     r = ragged_rings(a)
-    keep = ("walks_per_s", "kernel_ms", "est_updates_per_run", "norm_error_max", "second_moment_vs_limit_max",
+    keep = ("walks_per_s", "kernel_ms", "est_updates_per_run", "cone_updates_per_s", "norm_error_max",
+            "second_moment_vs_limit_max",
             "tiled_variant_per_bucket")
     out = {"workload": r["config"]["workload"], "updates_per_s": r["value"], "ms_per_run": r["ms_per_step"],
            **{k: r[k] for k in keep}, "roofline": r["roofline"]}

@@ -349,7 +349,10 @@ typedef struct {
     int32_t walls;               /* 1: reflecting ends, a segment of N sites (the segment walk
                                     of Sec. 3 and Fig. 3): the link between sites N-1 and 0 is
                                     broken at every step */
-    int32_t reserved;
+    int32_t full_lattice;        /* tiled rings whose light cone never wraps keep, by default
+                                    (0), only the sites of the live parity (after t steps from
+                                    x0 every amplitude at the other parity of x - x0 is exactly
+                                    zero); 1: every site of the cone, as before (same results) */
     double link_p;               /* random broken links (Sec. 3, Eqs. (9)-(10)): each link
                                     breaks with this probability at every step; 0 = none */
     uint64_t link_seed;          /* generator key of the links */
@@ -367,12 +370,15 @@ typedef struct {
     int32_t grid;              /* persistent workgroups */
     int32_t graph;             /* 1 once a hipGraph has been captured */
     int64_t whole_ring_walks;  /* walks held whole in one workgroup's registers */
-    double est_updates;        /* site*coin updates of one run (light cone; whole rings in full) */
+    double est_updates;        /* site*coin updates one run performs (light cone, or its live
+                                  half on the live sublattice; whole rings in full) */
     double last_run_ms;        /* HIP-event time of the latest walk_batch_run */
     int32_t bucket_cfg[3];     /* tiled variant (0..3) per size bucket N <= 1e4, <= 1e5, larger */
     int32_t bucket_tile_sites[3];
     int32_t bucket_depth[3];
     int32_t reserved;
+    double est_cone_updates;   /* site*coin updates of the walks' light cones (both parities;
+                                  whole rings in full): the updates of the method's window */
 } qw_batch_info;
 
 /* Validate and upload the walk table; allocate per-walk outputs and the slot

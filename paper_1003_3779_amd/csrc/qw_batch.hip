@@ -74,6 +74,7 @@ struct BatchArgs {
     int32_t walls;          // 1: the link (N-1, 0) is broken at every step
     uint64_t link_thr;      // a link is broken when its Philox word < link_thr (0: none at random)
     uint32_t key0, key1;    // generator key (seed)
+    int32_t full_lattice;   // 1: tiled rings update both parities of their cone
 };
 
 // fp64 norm of per-wave partial sums: lane 0 of each wave has written its sum
@@ -470,6 +471,194 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     }
 }
 
+// The live sublattice.  Every step moves each component by one site, so the
+// pre-shift state a_t of a walk started at x0 lives only on the offsets
+// d = x - x0 of parity 1 + t (both components alike); the other half of the
+// cone holds exact zeros.  A walk whose cone never wraps the ring (the
+// rotation-frame walks) can keep just the live half: slot j of a buffer holds
+// offset d = 2 j + q - O, q the parity it holds (O even).  One step from parity
+// q to 1 - q takes (a0(d - 1), a1(d + 1)) to the new a(d): from parity 0 that is
+// slots (j, j + 1) -> j, from parity 1 slots (j - 1, j) -> j, so each step moves
+// one component by one slot (alternately), where the full lattice moves both.
+// Each live value is the same expression as on the full lattice.
+
+// k steps of a live-sublattice tile held by one wave: lane l holds slots
+// l M .. l M + M - 1; q: parity of the slots before the first step.  Steps
+// from parity 0 spoil one more slot on the right of the tile, steps from
+// parity 1 one more on the left.
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_step_from0(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
+    const cv<R> right = from_right<R>(c1[0]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {  // ascending: c1[m + 1] is still the old value
+        const cv<R> g0 = c0[m], g1 = m == M - 1 ? right : c1[m == M - 1 ? m : m + 1];
+        cn.apply(g0, g1, c0[m], c1[m]);
+    }
+}
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_step_from1(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
+    const cv<R> left = from_left<R>(c0[M - 1]);
+#pragma unroll
+    for (int m = M - 1; m >= 0; --m) {  // descending: c0[m - 1] is still the old value
+        const cv<R> g0 = m == 0 ? left : c0[m == 0 ? 0 : m - 1], g1 = c1[m];
+        cn.apply(g0, g1, c0[m], c1[m]);
+    }
+}
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_tile_steps(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn, int k, int q) {
+    if (k > 0 && q == 1) {
+        sub_step_from1<R, M, CN>(c0, c1, cn);
+        --k;
+    }
+    for (; k >= 2; k -= 2) {
+        sub_step_from0<R, M, CN>(c0, c1, cn);
+        sub_step_from1<R, M, CN>(c0, c1, cn);
+    }
+    if (k > 0) sub_step_from0<R, M, CN>(c0, c1, cn);
+}
+
+// Slots of the live-sublattice layout a walk needs (offsets up to T + K + 2
+// either side, as the full-lattice path reaches), and the even origin O.
+__host__ __device__ inline int sub_origin(const WalkDesc &w, int K) { return (w.T + K + 2 + 3) & ~1; }
+__host__ __device__ inline int64_t sub_slots(const WalkDesc &w, int K) {
+    return (int64_t)(sub_origin(w, K) + w.T + K + 2) / 2 + 2;
+}
+
+// walk_tiled on the live sublattice (a rotation-frame walk whose sub_slots fit
+// the slot buffers): the same values at every live site, the same P, moments
+// and bins (the blocks' norm checks sum the same values in another order).
+template <typename R, int MT, typename CN>
+__device__ __forceinline__ void walk_tiled_sub(const WalkDesc &w, const BatchArgs &A, const int K, BinAcc *s_bins,
+                                               double (*s_norm)[kWaves], SiteAcc &acc) {
+    const int N = w.N;
+    const int64_t se = A.slot_elems;
+    cv<R> *const base = (cv<R> *)A.slots + (int64_t)blockIdx.x * 4 * se;  // [buffer][plane][slot]
+    CN cn;
+    load_coin<R>(w, cn);
+    const R f16 = (R)block_factor(cn, kFactorEvery);
+    const int O = sub_origin(w, K);
+    const int ns = (int)sub_slots(w, K);
+    // zero both buffers over every slot the walk uses (reads past them read zero)
+    for (int i = threadIdx.x; i < ns; i += kBT) {
+        const cv<R> z = czero<R>();
+        base[i] = z;
+        base[se + i] = z;
+        base[2 * se + i] = z;
+        base[3 * se + i] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // a0 at d = -1, a1 at d = +1: parity 1
+        cv<R> v;
+        v.x = (R)w.pre[0]; v.y = (R)w.pim[0];
+        base[(O - 2) / 2] = v;
+        v.x = (R)w.pre[1]; v.y = (R)w.pim[1];
+        base[se + O / 2] = v;
+    }
+    __syncthreads();
+    int cur = 0;
+    int half = 1;  // the support of a_t: |d| <= half = 1 + t
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int t = 0;
+    int npar = 0;
+    R sc = (R)1;  // pending scale of the current buffer (coin factor, renormalisation), applied as it is read
+    double nacc = 0.0;
+    while (t < w.T) {
+        const int k = (w.T - t) >= K ? K : w.T - t;
+        const int q = (1 + t) & 1;                       // parity of the input slots
+        const int hl = q == 1 ? (k + 1) / 2 : k / 2;     // steps from parity 1: spoilt slots on the left
+        const int hr = k - hl;                            // and on the right
+        const int TW = 64 * MT - k;
+        half += k;
+        const int qo = (1 + t + k) & 1;
+        const int jlo = (O - half - qo) / 2, jhi = (O + half - qo) / 2;  // the output's live slots
+        const cv<R> *i0 = base + (int64_t)cur * 2 * se, *i1 = i0 + se;
+        cv<R> *o0 = base + (int64_t)(cur ^ 1) * 2 * se, *o1 = o0 + se;
+        const int ntiles = (jhi - jlo + 1 + TW - 1) / TW;
+        for (int tile = wave; tile < ntiles; tile += kWaves) {
+            const int tb = jlo + tile * TW - hl + lane * MT;  // slot of this lane's first register
+            cv<R> c0[MT], c1[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int j = tb + m;
+                const bool in = j >= 0 && j < ns;
+                c0[m] = in ? cscale<R>(i0[in ? j : 0], sc) : czero<R>();
+                c1[m] = in ? cscale<R>(i1[in ? j : 0], sc) : czero<R>();
+            }
+            if constexpr (Factored<CN>::value) {
+                int left = k;
+                for (; left >= kFactorEvery; left -= kFactorEvery) {  // an even count: the parity returns
+                    sub_tile_steps<R, MT, CN>(c0, c1, cn, kFactorEvery, q);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        c0[m] = cscale<R>(c0[m], f16);
+                        c1[m] = cscale<R>(c1[m], f16);
+                    }
+                }
+                if (left > 0) sub_tile_steps<R, MT, CN>(c0, c1, cn, left, q);
+            } else {
+                sub_tile_steps<R, MT, CN>(c0, c1, cn, k, q);
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int r = lane * MT + m, j = tb + m;
+                if (r >= hl && r < 64 * MT - hr && j <= jhi) {
+                    o0[j] = c0[m];
+                    o1[j] = c1[m];
+                    if (A.renorm_every > 0) nacc += abs2d<R>(c0[m]) + abs2d<R>(c1[m]);
+                }
+            }
+        }
+        const double fk = block_factor(cn, k % kFactorEvery);
+        if (A.renorm_every > 0) {
+            const double part = wave_sum64(nacc);
+            if (lane == 0) s_norm[npar][wave] = part;
+            __syncthreads();
+            const double nrm = sum_waves(s_norm[npar]) * fk * fk;
+            npar ^= 1;
+            sc = (R)(fabs(nrm - 1.0) > A.renorm_tol ? fk / sqrt(nrm) : fk);
+        } else {
+            __syncthreads();
+            sc = (R)fk;
+        }
+        nacc = 0.0;
+        cur ^= 1;
+        t += k;
+    }
+    // P over the box of psi, site by site as on the full lattice: psi_T(d) =
+    // (a0(d - 1), a1(d + 1)), live where d - 1 has the parity 1 + T
+    const int qT = (1 + w.T) & 1;
+    const int ph = half + 1;
+    const int pw = (int)std::min<int64_t>(N, 2 * (int64_t)ph + 1);
+    const int ps = pw == N ? 0 : wrapN((int64_t)w.x0 - ph, N);
+    const cv<R> *a0 = base + (int64_t)cur * 2 * se, *a1 = a0 + se;
+    for (int i = threadIdx.x; i < pw; i += kBT) {
+        int x = ps + i;
+        x = x >= N ? x - N : x;
+        const int d = ring_offset(x, w.x0, N);
+        double pr = 0.0;
+        if (d >= -ph && d <= ph && ((d - 1 + O - qT) & 1) == 0) {
+            const int j0 = (d - 1 + O - qT) / 2;
+            pr = abs2d<R>(cscale<R>(a0[j0], sc)) + abs2d<R>(cscale<R>(a1[j0 + 1], sc));
+        }
+        acc.add(pr, d, N, A.nbins, s_bins);
+        if (A.P) A.P[w.p_off + x] = pr;
+    }
+    if (A.P && pw < N) {
+        for (int i = threadIdx.x; i < N - pw; i += kBT) {
+            int x = ps + pw + i;
+            x = x >= N ? x - N : x;
+            A.P[w.p_off + x] = 0.0;
+        }
+    }
+}
+
+template <typename R, int MT, typename CN>
+__device__ __forceinline__ void run_tiled(bool sub, const WalkDesc &w, const BatchArgs &A, int K, BinAcc *s_bins,
+                                          double (*s_norm)[kWaves], SiteAcc &acc) {
+    if (sub) walk_tiled_sub<R, MT, CN>(w, A, K, s_bins, s_norm, acc);
+    else walk_tiled<R, MT, CN>(w, A, K, s_bins, s_norm, acc);
+}
+
 template <typename R> __device__ __forceinline__ void finish_walk(const BatchArgs &A, int wi, SiteAcc &acc,
                                                                    BinAcc *s_bins, double (*s_red)[kWaves]) {
     wg_reduce3(acc, s_red);  // contains the barrier that orders the bin atomics
@@ -508,21 +697,24 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         const int wi = A.order[q];
         const WalkDesc w = A.walks[wi];
         SiteAcc acc;
+        // rotation-frame walks (cones that never wrap) keep only the live sublattice
+        // when its slots fit the workgroup's buffers
+        const bool sub = w.rot && !A.full_lattice && sub_slots(w, kCfgK[w.cfg]) <= A.slot_elems;
         if (!w.rot) {
             // a walk whose light cone wraps the ring: full SU(2) coin, one variant
             walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
         } else if (kCfgMT[w.cfg] == 4) {
             // short cones: small tiles keep more of the workgroup's waves busy
-            if (w.rswap) walk_tiled<R, 4, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else walk_tiled<R, 4, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            if (w.rswap) run_tiled<R, 4, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else run_tiled<R, 4, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         } else if (kCfgMT[w.cfg] == 8) {
-            if (w.rswap) walk_tiled<R, 8, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else walk_tiled<R, 8, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            if (w.rswap) run_tiled<R, 8, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else run_tiled<R, 8, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         } else {
             // 16 sites per lane in complex64; complex128 keeps 8 (register budget)
             constexpr int MT = sizeof(R) == 8 ? 8 : 16;
-            if (w.rswap) walk_tiled<R, MT, CoinRotS<R, true>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else walk_tiled<R, MT, CoinRotS<R, false>>(w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            if (w.rswap) run_tiled<R, MT, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else run_tiled<R, MT, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         }
         finish_walk<R>(A, wi, acc, s_bins, s_red);
     }
@@ -665,6 +857,7 @@ struct qw_batch {
     int32_t renorm_every = 0;
     double renorm_tol = 1e-7;
     int32_t links = 0, walls = 0;  // broken links / reflecting ends
+    int32_t full_lattice = 0;      // tiled rings: both parities of the cone
     uint64_t link_thr = 0;
     uint32_t key0 = 0, key1 = 0;
     WalkDesc *d_walks = nullptr;
@@ -726,6 +919,7 @@ BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, in
     A.link_thr = b->link_thr;
     A.key0 = b->key0;
     A.key1 = b->key1;
+    A.full_lattice = b->full_lattice;
     return A;
 }
 
@@ -757,12 +951,25 @@ int persistent_grid(int prec, int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, n));
 }
 
-// estimated site*coin updates of one walk (whole ring: every site every step)
+// estimated site*coin updates of one walk's light cone (whole ring: every site
+// every step)
 double walk_work(const WalkDesc &w) {
     if (w.cfg < 0) return 2.0 * w.N * (double)w.T;
     const double T = w.T, N = w.N;
     const double tc = std::max(0.0, std::min(T, (N - 3.0) / 2.0));  // steps before the cone wraps
     return 2.0 * ((tc * (tc + 4.0)) + (T - tc) * N);
+}
+
+// whether k_batch runs the walk on its live sublattice (the test it makes)
+bool walk_sub(const qw_batch *b, const WalkDesc &w) {
+    return w.cfg >= 0 && w.rot && !b->full_lattice && sub_slots(w, kCfgK[w.cfg]) <= b->slot_elems;
+}
+
+// the updates the kernel performs: on the live sublattice half of the cone's
+// (at step t, t + 2 of its 2t + 3 offsets are live: counting half is low by at
+// most one site per step)
+double walk_performed(const qw_batch *b, const WalkDesc &w) {
+    return walk_sub(b, w) ? 0.5 * walk_work(w) : walk_work(w);
 }
 
 }  // namespace
@@ -788,6 +995,8 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         return bfail(QW_EINVAL, "tiled_variant must be 0 (tuned) or 1..%d", kNumCfg);
     if (o.whole_max_sites < 0) return bfail(QW_EINVAL, "whole_max_sites must be >= 0");
     if (o.walls != 0 && o.walls != 1) return bfail(QW_EINVAL, "walls must be 0 or 1 (got %d)", o.walls);
+    if (o.full_lattice != 0 && o.full_lattice != 1)
+        return bfail(QW_EINVAL, "full_lattice must be 0 or 1 (got %d)", o.full_lattice);
     if (!(o.link_p >= 0.0 && o.link_p <= 1.0))
         return bfail(QW_EINVAL, "link_p must be in [0, 1] (got %g)", o.link_p);
     if (o.realization0 > 0xFFFFFFFFull || (uint64_t)(n - 1) > 0xFFFFFFFFull - o.realization0)
@@ -804,6 +1013,7 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
     b->renorm_every = o.renorm_every > 0 ? o.renorm_every : (o.renorm_every < 0 ? 0 : (prec == QW_C64 ? 64 : 0));
     b->links = links ? 1 : 0;
     b->walls = o.walls;
+    b->full_lattice = o.full_lattice;
     // a link breaks when its 32-bit draw is below floor(p 2^32) (p = 1: always)
     b->link_thr = o.link_p >= 1.0 ? (1ull << 32) : (uint64_t)floor(o.link_p * 4294967296.0);
     b->key0 = (uint32_t)o.link_seed;
@@ -1052,13 +1262,15 @@ int walk_batch_info(qw_batch_t b, qw_batch_info *out) {
     out->grid = b->grid;
     out->graph = b->gexec != nullptr;
     int64_t whole = 0;
-    double work = 0.0;
+    double work = 0.0, cone = 0.0;
     for (auto &w : b->walks) {
         whole += w.cfg < 0;
-        work += walk_work(w);
+        work += walk_performed(b, w);
+        cone += walk_work(w);
     }
     out->whole_ring_walks = whole;
     out->est_updates = work;
+    out->est_cone_updates = cone;
     out->last_run_ms = ms;
     for (int k = 0; k < 3; ++k) {
         out->bucket_cfg[k] = b->bucket_cfg[k];

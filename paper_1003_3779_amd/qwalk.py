@@ -81,7 +81,7 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int32), ("keep_probabilities", ctypes.c_int32),
                 ("tiled_variant", ctypes.c_int32), ("no_graph", ctypes.c_int32),
                 ("renorm_every", ctypes.c_int32), ("whole_max_sites", ctypes.c_int32),
-                ("walls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("walls", ctypes.c_int32), ("full_lattice", ctypes.c_int32),
                 ("link_p", ctypes.c_double), ("link_seed", ctypes.c_uint64),
                 ("realization0", ctypes.c_uint64)]
 
@@ -91,7 +91,7 @@ class BatchInfo(ctypes.Structure):
                 ("whole_ring_walks", ctypes.c_int64), ("est_updates", ctypes.c_double),
                 ("last_run_ms", ctypes.c_double), ("bucket_cfg", ctypes.c_int32 * 3),
                 ("bucket_tile_sites", ctypes.c_int32 * 3), ("bucket_depth", ctypes.c_int32 * 3),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("est_cone_updates", ctypes.c_double)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -446,7 +446,7 @@ class Batch:
     def __init__(self, N, T, angles, psi0, x0=None, prec: int = QW_C64, nbins: int = 0,
                  keep_probabilities: bool = False, tiled_variant: int = 0, no_graph: bool = False,
                  renorm_every: int = 0, stream=None, whole_max_sites: int = 0, walls: bool = False,
-                 link_p: float = 0.0, link_seed: int = 0, realization0: int = 0):
+                 link_p: float = 0.0, link_seed: int = 0, realization0: int = 0, full_lattice: bool = False):
         lib = load()
         self._lib = lib
         self.N = np.ascontiguousarray(np.asarray(N, dtype=np.int64))
@@ -457,7 +457,8 @@ class Batch:
         xa = None if x0 is None else np.ascontiguousarray(np.asarray(x0, dtype=np.int64))
         self.n, self.nbins, self.keep = n, nbins, keep_probabilities
         o = BatchOpts(nbins, int(bool(keep_probabilities)), int(tiled_variant), int(bool(no_graph)),
-                      int(renorm_every), int(whole_max_sites), int(bool(walls)), 0, float(link_p),
+                      int(renorm_every), int(whole_max_sites), int(bool(walls)), int(bool(full_lattice)),
+                      float(link_p),
                       int(link_seed), int(realization0))
         h = ctypes.c_void_p()
         _bcheck(lib.walk_batch_create(n, self.N.ctypes.data, self.T.ctypes.data, ang.ctypes.data, p0.ctypes.data,

@@ -108,6 +108,41 @@ def test_batch_variants_and_graph_replay_bitwise():
         b.destroy()
 
 
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+def test_batch_live_sublattice_bitwise(prec):
+    """Tiled rings whose cone never wraps keep only the live parity of their cone
+    (the default) or every site of it (full_lattice): each live value is the same
+    expression either way, so P, moments and bins agree bit for bit for every
+    tiled variant (norm checks off: they sum the same values in another order).
+    Long cones, odd step counts and a last block shorter than the rest; walks
+    whose cone wraps keep the full lattice in both."""
+    rng = np.random.default_rng(77)
+    N = np.array([2049, 4097, 4097, 6001, 9999, 20001, 65537, 100001, 3001, 2501], dtype=np.int64)
+    T = np.array([1024, 2048, 1337, 2999, 4000, 7777, 20000, 45001, 1500, 1800], dtype=np.int64)
+    ang = inputs.su2_angles(rng, N.size)
+    psi0 = np.stack([inputs.haar_state(rng, 2) for _ in range(N.size)])
+    x0 = np.array([int(rng.integers(0, k)) for k in N], dtype=np.int64)
+    for variant in (0, 1, 3, 5, 6):
+        res = []
+        for full in (True, False):
+            b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True,
+                            tiled_variant=variant, renorm_every=-1, full_lattice=full)
+            b.run()
+            res.append((np.concatenate(b.probabilities()), b.moments(), b.binned()))
+            b.destroy()
+        for g, r in zip(res[1], res[0]):
+            assert np.array_equal(g, r), (prec, variant)
+    if prec == qwalk.QW_C128:  # and against the oracle on the shorter rings
+        Ps = None
+        b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, keep_probabilities=True)
+        b.run()
+        Ps = b.probabilities()
+        b.destroy()
+        for i in (0, 1, 8, 9):
+            ref = _oracle_P(N[i], T[i], ang[i], psi0[i], x0[i])
+            assert np.max(np.abs(Ps[i] - ref)) <= 1e-12, i
+
+
 def test_batch_autotuner(tmp_path, monkeypatch):
     monkeypatch.setenv("QWALK_TUNE_CACHE", str(tmp_path / "tune.txt"))
     rng = np.random.default_rng(3)
