@@ -331,10 +331,11 @@ typedef struct {
     int32_t nbins;               /* bins per walk: 0 (none) or even and <= 1024 */
     int32_t keep_probabilities;  /* 1: keep every walk's full P(x) for walk_batch_probabilities */
     int32_t tiled_variant;       /* rings too long for one workgroup's registers: 0 = tuned
-                                    (cache) or default; 1..6 = force (tile sites, steps per
+                                    (cache) or default; 1..8 = force (tile sites, steps per
                                     block) = (512, 16), (512, 32), (1024, 32), (1024, 64),
-                                    (256, 16), (256, 32) (complex128 tiles are at most 512
-                                    sites) */
+                                    (256, 16), (256, 32), (128, 16), (128, 32) (complex128
+                                    tiles are at most 512 sites; on the live sublattice a tile
+                                    holds that many slots, twice as many sites) */
     int32_t no_graph;            /* 1: launch directly instead of replaying a hipGraph */
     int32_t renorm_every;        /* fp64 norm check (rescale by 1/sqrt(n) when |n - 1| > 1e-7):
                                     0 = default (every 64 steps in QW_C64, never in QW_C128),

@@ -38,9 +38,9 @@ namespace {
 constexpr int kBT = 512;          // threads per batch workgroup
 constexpr int kWaves = kBT / 64;
 constexpr int kMaxBins = 1024;
-constexpr int kNumCfg = 6;        // tiled-path variants (sites per lane MT, steps per block K)
-constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16, 4, 4};
-constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64, 16, 32};
+constexpr int kNumCfg = 8;        // tiled-path variants (sites per lane MT, steps per block K)
+constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16, 4, 4, 2, 2};
+constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64, 16, 32, 16, 32};
 
 struct WalkDesc {
     int32_t N, T, x0, cfg;  // cfg < 0: whole-ring path with m sites per thread; else tiled variant
@@ -340,7 +340,8 @@ __device__ __forceinline__ double block_factor(const CoinRotS<R, SWAP> &cn, int 
 // pending, applied by the next reads.
 constexpr int kFactorEvery = 16;
 static_assert(kCfgK[0] % kFactorEvery == 0 && kCfgK[1] % kFactorEvery == 0 && kCfgK[2] % kFactorEvery == 0 &&
-                  kCfgK[3] % kFactorEvery == 0 && kCfgK[4] % kFactorEvery == 0 && kCfgK[5] % kFactorEvery == 0,
+                  kCfgK[3] % kFactorEvery == 0 && kCfgK[4] % kFactorEvery == 0 && kCfgK[5] % kFactorEvery == 0 &&
+                  kCfgK[6] % kFactorEvery == 0 && kCfgK[7] % kFactorEvery == 0,
               "every tiled block depth is a multiple of the factor period");
 
 // ---------------------------------------------------------------- tiled ring
@@ -703,6 +704,10 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
         if (!w.rot) {
             // a walk whose light cone wraps the ring: full SU(2) coin, one variant
             walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
+        } else if (kCfgMT[w.cfg] == 2) {
+            // the shortest cones (on the live sublattice a tile spans twice its slots)
+            if (w.rswap) run_tiled<R, 2, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else run_tiled<R, 2, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
         } else if (kCfgMT[w.cfg] == 4) {
             // short cones: small tiles keep more of the workgroup's waves busy
             if (w.rswap) run_tiled<R, 4, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
@@ -871,10 +876,11 @@ struct qw_batch {
     int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (256 sites, 32
-    // steps) for the short rings, whose cones span few tiles, (1024, 64) for the
-    // long ones
-    int bucket_cfg[3] = {5, 3, 3};
+    // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (128 slots, 32
+    // steps) for the short rings, whose cones span few tiles (on the live
+    // sublattice 65536 rings of 4097 sites: 29.4 ms against 31.9 with 256 slots),
+    // (1024, 64) for the long ones
+    int bucket_cfg[3] = {7, 3, 3};
     double last_ms = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool own_stream = false;

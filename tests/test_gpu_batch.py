@@ -57,7 +57,7 @@ def _check_walks(b, N, T, ang, psi0, x0, tolP, nbins):
 
 
 @pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_batch_mixed_sizes(prec, tol, variant):
     N, T, ang, psi0, x0 = _mixed(11 + variant)
     b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True, tiled_variant=variant)
@@ -69,7 +69,7 @@ def test_batch_mixed_sizes(prec, tol, variant):
 
 
 @pytest.mark.parametrize("prec,tol", [(qwalk.QW_C128, 1e-12), (qwalk.QW_C64, 2e-5)])
-@pytest.mark.parametrize("variant", [1, 4, 5])
+@pytest.mark.parametrize("variant", [1, 4, 5, 7])
 def test_batch_short_rings_tiled(prec, tol, variant):
     """whole_max_sites = 1: every ring of 2048 sites or more runs tiled over its
     light cone (rings 2048..4608 are otherwise held whole), shorter ones whole."""
@@ -94,7 +94,8 @@ def test_batch_short_rings_tiled(prec, tol, variant):
 def test_batch_variants_and_graph_replay_bitwise():
     N, T, ang, psi0, x0 = _mixed(5, n_extra=20)
     ref = None
-    for variant, no_graph in ((1, True), (2, False), (3, False), (4, False), (5, False), (6, False), (0, False)):
+    for variant, no_graph in ((1, True), (2, False), (3, False), (4, False), (5, False), (6, False), (7, False),
+                              (8, False), (0, False)):
         b = qwalk.Batch(N, T, ang, psi0, x0, prec=qwalk.QW_C64, nbins=32, keep_probabilities=True,
                         tiled_variant=variant, no_graph=no_graph, renorm_every=-1)
         for rep in range(3):
@@ -122,7 +123,7 @@ def test_batch_live_sublattice_bitwise(prec):
     ang = inputs.su2_angles(rng, N.size)
     psi0 = np.stack([inputs.haar_state(rng, 2) for _ in range(N.size)])
     x0 = np.array([int(rng.integers(0, k)) for k in N], dtype=np.int64)
-    for variant in (0, 1, 3, 5, 6):
+    for variant in (0, 1, 3, 5, 6, 8):
         res = []
         for full in (True, False):
             b = qwalk.Batch(N, T, ang, psi0, x0, prec=prec, nbins=64, keep_probabilities=True,
