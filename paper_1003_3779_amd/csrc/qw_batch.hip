@@ -345,6 +345,26 @@ static_assert(kCfgK[0] % kFactorEvery == 0 && kCfgK[1] % kFactorEvery == 0 && kC
               "every tiled block depth is a multiple of the factor period");
 
 // ---------------------------------------------------------------- tiled ring
+// End of a tiled block (after its barrier every output is stored): the block's
+// output is the state divided by fk (factored coin); with norm checks on, the
+// fp64 norm of the output (this thread's sum nacc, then the waves in fixed
+// order) decides the rescale.  Returns the scale the next reads of the buffer
+// apply.
+template <typename R>
+__device__ __forceinline__ R block_scale(const BatchArgs &A, double fk, double nacc, double (*s_norm)[kWaves],
+                                         int &npar, int lane, int wave) {
+    if (A.renorm_every > 0) {
+        const double part = wave_sum64(nacc);
+        if (lane == 0) s_norm[npar][wave] = part;
+        __syncthreads();
+        const double nrm = sum_waves(s_norm[npar]) * fk * fk;
+        npar ^= 1;
+        return (R)(fabs(nrm - 1.0) > A.renorm_tol ? fk / sqrt(nrm) : fk);
+    }
+    __syncthreads();
+    return (R)fk;
+}
+
 template <typename R, int MT, typename CN>
 __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A, const int K, BinAcc *s_bins,
                                            double (*s_norm)[kWaves], SiteAcc &acc) {
@@ -431,21 +451,7 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
                 }
             }
         }
-        // the block's output is the state divided by fk (factored coin)
-        const double fk = block_factor(cn, k % kFactorEvery);
-        if (A.renorm_every > 0) {
-            // fp64 norm of the block's output, in fixed wave order; the rescale
-            // (if any) is applied by the next reads of this buffer
-            const double part = wave_sum64(nacc);
-            if (lane == 0) s_norm[npar][wave] = part;
-            __syncthreads();
-            const double nrm = sum_waves(s_norm[npar]) * fk * fk;
-            npar ^= 1;
-            sc = (R)(fabs(nrm - 1.0) > A.renorm_tol ? fk / sqrt(nrm) : fk);
-        } else {
-            __syncthreads();
-            sc = (R)fk;
-        }
+        sc = block_scale<R>(A, block_factor(cn, k % kFactorEvery), nacc, s_norm, npar, lane, wave);
         nacc = 0.0;
         cur ^= 1;
         t += k;
@@ -609,18 +615,7 @@ __device__ __forceinline__ void walk_tiled_sub(const WalkDesc &w, const BatchArg
                 }
             }
         }
-        const double fk = block_factor(cn, k % kFactorEvery);
-        if (A.renorm_every > 0) {
-            const double part = wave_sum64(nacc);
-            if (lane == 0) s_norm[npar][wave] = part;
-            __syncthreads();
-            const double nrm = sum_waves(s_norm[npar]) * fk * fk;
-            npar ^= 1;
-            sc = (R)(fabs(nrm - 1.0) > A.renorm_tol ? fk / sqrt(nrm) : fk);
-        } else {
-            __syncthreads();
-            sc = (R)fk;
-        }
+        sc = block_scale<R>(A, block_factor(cn, k % kFactorEvery), nacc, s_norm, npar, lane, wave);
         nacc = 0.0;
         cur ^= 1;
         t += k;
