@@ -198,6 +198,10 @@ struct qw_walk {
     // support of the pre-shift state a_t, relative to x0, per axis; full[] once it covers the axis
     int64_t lo[2] = {0, 0}, hi[2] = {0, 0};
     bool full[2] = {false, false};
+    // the state grew from the single site x0 by forward steps (so it is non-zero only
+    // at one parity of x - x0 on a ring): set by create and reset, cleared by
+    // walk_set_state and inverse steps
+    bool pure = false;
     int emin[2] = {0, 0}, emax[2] = {0, 0};
     qw_options opt;
     // random broken links (walk_set_broken_links); rbl.step is filled per launch
@@ -536,15 +540,26 @@ int run_forward(qw_walk *w, int64_t n) {
     int depth = w->opt.block_depth ? w->opt.block_depth : default_depth(w);
     if (w->dim == 1 && w->ring_std && depth > 1 && w->g.Lx <= ring_whole_max_sites(w->prec)) {
         // the whole ring in one workgroup: all n steps in one launch (every
-        // site is computed; the light-cone box stays exact bookkeeping)
+        // site is computed, or, for a walk from one site whose support stays
+        // clear of itself, every site of its live parity; the light-cone box
+        // stays exact bookkeeping)
+        const int64_t t0 = w->t;
         grow_forward(w, n);
         LaunchInfo li;
         Timed tm(w);
-        QW_HIP(launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li), "ring kernel");
-        tm.done(QW_KERNEL_RING_WHOLE, li, (double)w->g.Lx * w->d * n, state_bytes_of(w, 2 * w->g.Lx));
+        int64_t sites = w->g.Lx;
+        hipError_t e = hipErrorNotSupported;
+        if (w->pure && !w->rbl_on)
+            e = launch_ring_sub(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->x0[0], t0, w->stream, &li, &sites);
+        if (e == hipErrorNotSupported) {
+            sites = w->g.Lx;
+            e = launch_ring_whole(w->prec, cur_buf(w), oth_buf(w), w->g, w->C, n, w->stream, &li);
+        }
+        QW_HIP(e, "ring kernel");
+        tm.done(QW_KERNEL_RING_WHOLE, li, (double)sites * w->d * n, state_bytes_of(w, 2 * w->g.Lx));
         w->cur ^= 1;
         w->launches++;
-        w->updates += (int64_t)w->g.Lx * w->d * n;
+        w->updates += sites * w->d * n;
         return QW_OK;
     }
     // ---- torus launch choice: begin ----
@@ -584,6 +599,7 @@ int norm_check(qw_walk *w) {
 // a_0 is psi_0 placed at x0 - e_c
 void set_origin(qw_walk *w, const int64_t *x0) {
     const int64_t L[2] = {w->g.Lx, w->g.Ly};
+    w->pure = true;
     for (int ax = 0; ax < 2; ++ax) {
         int64_t v = x0[ax] % L[ax];
         w->x0[ax] = v < 0 ? v + L[ax] : v;
@@ -849,6 +865,7 @@ int walk_step_inverse(qw_walk_t w, int64_t T) {
     if (T < 0) return fail(QW_EINVAL, "step count must be >= 0 (got %lld)", (long long)T);
     if (w->rbl_on) return fail(QW_EINVAL, "inverse steps are not available while links break at random");
     DeviceGuard dg(w->device);
+    w->pure = false;
     for (int64_t s = 0; s < T; ++s) {
         grow_inverse(w, 1);
         const Box b = state_box(w);
@@ -962,6 +979,7 @@ int walk_set_state(qw_walk_t w, const double *in, int32_t in_on_device) {
         return fail(QW_ENOTNORM, "state is not normalised (||psi||^2 = %.17g)", nn);
     }
     w->cur ^= 1;
+    w->pure = false;
     w->full[0] = w->full[1] = true;
     w->since_check = 0;
     return QW_OK;

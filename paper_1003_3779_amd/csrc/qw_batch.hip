@@ -478,51 +478,10 @@ __device__ __forceinline__ void walk_tiled(const WalkDesc &w, const BatchArgs &A
     }
 }
 
-// The live sublattice.  Every step moves each component by one site, so the
-// pre-shift state a_t of a walk started at x0 lives only on the offsets
-// d = x - x0 of parity 1 + t (both components alike); the other half of the
-// cone holds exact zeros.  A walk whose cone never wraps the ring (the
-// rotation-frame walks) can keep just the live half: slot j of a buffer holds
-// offset d = 2 j + q - O, q the parity it holds (O even).  One step from parity
-// q to 1 - q takes (a0(d - 1), a1(d + 1)) to the new a(d): from parity 0 that is
-// slots (j, j + 1) -> j, from parity 1 slots (j - 1, j) -> j, so each step moves
-// one component by one slot (alternately), where the full lattice moves both.
-// Each live value is the same expression as on the full lattice.
-
-// k steps of a live-sublattice tile held by one wave: lane l holds slots
-// l M .. l M + M - 1; q: parity of the slots before the first step.  Steps
-// from parity 0 spoil one more slot on the right of the tile, steps from
-// parity 1 one more on the left.
-template <typename R, int M, typename CN>
-__device__ __forceinline__ void sub_step_from0(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
-    const cv<R> right = from_right<R>(c1[0]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) {  // ascending: c1[m + 1] is still the old value
-        const cv<R> g0 = c0[m], g1 = m == M - 1 ? right : c1[m == M - 1 ? m : m + 1];
-        cn.apply(g0, g1, c0[m], c1[m]);
-    }
-}
-template <typename R, int M, typename CN>
-__device__ __forceinline__ void sub_step_from1(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
-    const cv<R> left = from_left<R>(c0[M - 1]);
-#pragma unroll
-    for (int m = M - 1; m >= 0; --m) {  // descending: c0[m - 1] is still the old value
-        const cv<R> g0 = m == 0 ? left : c0[m == 0 ? 0 : m - 1], g1 = c1[m];
-        cn.apply(g0, g1, c0[m], c1[m]);
-    }
-}
-template <typename R, int M, typename CN>
-__device__ __forceinline__ void sub_tile_steps(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn, int k, int q) {
-    if (k > 0 && q == 1) {
-        sub_step_from1<R, M, CN>(c0, c1, cn);
-        --k;
-    }
-    for (; k >= 2; k -= 2) {
-        sub_step_from0<R, M, CN>(c0, c1, cn);
-        sub_step_from1<R, M, CN>(c0, c1, cn);
-    }
-    if (k > 0) sub_step_from0<R, M, CN>(c0, c1, cn);
-}
+// The live sublattice (sub_tile_steps): a walk whose cone never wraps the ring
+// (the rotation-frame walks) keeps only the offsets d = x - x0 of parity 1 + t
+// -- the other half of its cone holds exact zeros -- with offset d = 2 j + q - O
+// in slot j of a buffer (q the parity it holds, O even).
 
 // Slots of the live-sublattice layout a walk needs (offsets up to T + K + 2
 // either side, as the full-lattice path reaches), and the even origin O.

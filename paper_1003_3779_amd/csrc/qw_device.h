@@ -274,6 +274,49 @@ __device__ __forceinline__ void ring_tile_steps_pp(cv<R> (&a0)[M], cv<R> (&a1)[M
     }
 }
 
+// The live sublattice of a ring walk started at one site x0: every step moves
+// each component by one site, so the pre-shift state after t steps is non-zero
+// only at offsets x - x0 of parity 1 + t.  A layout that keeps only those holds
+// offset 2 j + q - O in slot j (q the parity, O even); one step from parity 0
+// takes slots (j, j + 1) to j, from parity 1 slots (j - 1, j) to j: each step
+// moves one component by one slot, alternately, and every live value is the
+// same expression as on the full lattice.
+
+// k steps of a live-sublattice tile held by one wave: lane l holds slots
+// l M .. l M + M - 1; q: parity of the slots before the first step.  Steps
+// from parity 0 spoil one more slot on the right of the tile, steps from
+// parity 1 one more on the left.
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_step_from0(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
+    const cv<R> right = from_right<R>(c1[0]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {  // ascending: c1[m + 1] is still the old value
+        const cv<R> g0 = c0[m], g1 = m == M - 1 ? right : c1[m == M - 1 ? m : m + 1];
+        cn.apply(g0, g1, c0[m], c1[m]);
+    }
+}
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_step_from1(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn) {
+    const cv<R> left = from_left<R>(c0[M - 1]);
+#pragma unroll
+    for (int m = M - 1; m >= 0; --m) {  // descending: c0[m - 1] is still the old value
+        const cv<R> g0 = m == 0 ? left : c0[m == 0 ? 0 : m - 1], g1 = c1[m];
+        cn.apply(g0, g1, c0[m], c1[m]);
+    }
+}
+template <typename R, int M, typename CN>
+__device__ __forceinline__ void sub_tile_steps(cv<R> (&c0)[M], cv<R> (&c1)[M], const CN &cn, int k, int q) {
+    if (k > 0 && q == 1) {
+        sub_step_from1<R, M, CN>(c0, c1, cn);
+        --k;
+    }
+    for (; k >= 2; k -= 2) {
+        sub_step_from0<R, M, CN>(c0, c1, cn);
+        sub_step_from1<R, M, CN>(c0, c1, cn);
+    }
+    if (k > 0) sub_step_from0<R, M, CN>(c0, c1, cn);
+}
+
 // As ring_tile_steps with a run-time step count k (the step loop is not
 // unrolled, so deep blocks cost no code size); sites k .. 64M-k-1 are exact.
 template <typename R, int M, typename CN>

@@ -88,6 +88,14 @@ hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g,
                              const CoinF64 &C, int64_t K, hipStream_t s, LaunchInfo *info,
                              const Links *links = nullptr, int64_t t0 = 0);
 
+// K steps of a ring walk started at the single site x0, now at time t0, on its
+// live sublattice (offsets x - x0 of parity 1 + t; the rest of the state is
+// exactly zero), one workgroup; slots (optional) receives the slots it steps.
+// hipErrorNotSupported (nothing launched) unless g is a ring the kernel holds
+// and t0 + K <= (N - 1) / 2.
+hipError_t launch_ring_sub(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
+                           int64_t x0, int64_t t0, hipStream_t s, LaunchInfo *info, int64_t *slots);
+
 // launch shape of the torus streaming kernel
 struct StreamTune {
     int prefetch;  // input rows read ahead, in registers: 1 or 3

@@ -300,6 +300,101 @@ __global__ __launch_bounds__(256) void k_ring_halo(const cv<R> *__restrict__ in,
     }
 }
 
+// The ring coin as k_ring_halo applies it (the same expressions, so the same
+// roundings): real entries (REALC) or complex ones.
+template <typename R, bool REALC> struct HaloCoin {
+    R c00r, c00i, c01r, c01i, c10r, c10i, c11r, c11i;
+    __device__ __forceinline__ void apply(cv<R> g0, cv<R> g1, cv<R> &o0, cv<R> &o1) const {
+        if constexpr (REALC) {
+            o0.x = fmaR(c01r, g1.x, c00r * g0.x);
+            o0.y = fmaR(c01r, g1.y, c00r * g0.y);
+            o1.x = fmaR(c11r, g1.x, c10r * g0.x);
+            o1.y = fmaR(c11r, g1.y, c10r * g0.y);
+        } else {
+            o0 = cmac<R>(cmul<R>(c00r, c00i, g0), c01r, c01i, g1);
+            o1 = cmac<R>(cmul<R>(c10r, c10i, g0), c11r, c11i, g1);
+        }
+    }
+};
+
+// K steps of a ring walk on its live sublattice, one workgroup: the walk was
+// started at x0 and is at time t0, so its pre-shift state is non-zero only at
+// offsets d = x - x0 of parity 1 + t, and |d| <= t + 1.  The launcher asks for
+// t0 + K <= (N - 1) / 2: the support never meets itself around the ring, so
+// the walk is the walk on the line of offsets [-H, H], H = (N + 1) / 2, held
+// as slots (offset 2 j + q - O in slot j, O even) in LDS and, as in
+// k_ring_halo, stepped in four wave windows that meet in LDS every 32 steps
+// (16 halo slots a side: a step spoils one slot on one side of a window,
+// alternately).  Half the sites per step of k_ring_halo, bitwise the same
+// values; the dead offsets are written as zeros.
+template <typename R, int M, bool REALC>
+__global__ __launch_bounds__(256) void k_ring_sub(const cv<R> *__restrict__ in, cv<R> *__restrict__ out, int N,
+                                                  int64_t ps, int x0, int64_t t0, int64_t K, CoinR<R> C) {
+    constexpr int kMax = 32768 / (int)sizeof(cv<R>);  // 2 planes: 64 KiB of LDS
+    constexpr int kHS = kRingHalo / 2;               // halo slots a side per exchange
+    __shared__ cv<R> S0[kMax];
+    __shared__ cv<R> S1[kMax];
+    const int H = (N + 1) / 2, O = (H + 1) & ~1;
+    const int ns = (O + H) / 2 + 2;  // slots (the launcher checks ns <= kMax)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q0 = (int)((1 + t0) & 1);
+    for (int j = threadIdx.x; j < ns; j += 256) {
+        const int d = 2 * j + q0 - O;
+        cv<R> v0 = czero<R>(), v1 = czero<R>();
+        if (d >= -(t0 + 1) && d <= t0 + 1) {  // the support, 2 t0 + 3 <= N offsets: no two share a site
+            int x = (x0 + d) % N;
+            x = x < 0 ? x + N : x;
+            v0 = in[x];
+            v1 = in[ps + x];
+        }
+        S0[j] = v0;
+        S1[j] = v1;
+    }
+    __syncthreads();
+    HaloCoin<R, REALC> cn;
+    cn.c00r = C.re[0]; cn.c00i = C.im[0]; cn.c01r = C.re[1]; cn.c01i = C.im[1];
+    cn.c10r = C.re[2]; cn.c10i = C.im[2]; cn.c11r = C.re[3]; cn.c11i = C.im[3];
+    const int I = (ns + 3) / 4;
+    const int own0 = w * I, own1 = min(ns, own0 + I);
+    const int ws = own0 - kHS;  // first slot of this wave's window (may lie before slot 0)
+    cv<R> c0[M], c1[M];
+    for (int64_t done = 0; done < K; done += kRingHalo) {
+        const int h = K - done < kRingHalo ? (int)(K - done) : kRingHalo;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int j = ws + lane * M + m;
+            const bool inr = j >= 0 && j < ns;  // past the line's ends: zeros (the cone never gets there)
+            c0[m] = inr ? S0[inr ? j : 0] : czero<R>();
+            c1[m] = inr ? S1[inr ? j : 0] : czero<R>();
+        }
+        sub_tile_steps<R, M, HaloCoin<R, REALC>>(c0, c1, cn, h, (int)((1 + t0 + done) & 1));
+        __syncthreads();  // every window read before any owned slot is overwritten
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int j = ws + lane * M + m;
+            if (j >= own0 && j < own1) {
+                S0[j] = c0[m];
+                S1[j] = c1[m];
+            }
+        }
+        __syncthreads();
+    }
+    const int qT = (int)((1 + t0 + K) & 1);
+    for (int x = threadIdx.x; x < N; x += 256) {
+        int d = x - x0;  // the offset of x in (-N/2, N/2]
+        d = d < 0 ? d + N : d;
+        d = d > N / 2 ? d - N : d;
+        cv<R> v0 = czero<R>(), v1 = czero<R>();
+        if (((d + O - qT) & 1) == 0) {
+            const int j = (d + O - qT) / 2;
+            v0 = S0[j];
+            v1 = S1[j];
+        }
+        out[x] = v0;
+        out[ps + x] = v1;
+    }
+}
+
 // =====================================================================
 // a long ring: K steps per launch in wave-sized register tiles
 // =====================================================================
@@ -995,6 +1090,64 @@ static bool ring_halo_t(int m, const void *in, void *out, const Geom &g, const C
     default: return false;
     }
 #undef QW_RING_HALO
+}
+
+// slots per lane of k_ring_sub: the smallest listed M whose window holds a
+// quarter of the slots plus both halos (0: the ring is too long)
+static int ring_sub_m(int prec, int64_t N) {
+    static const int mc128[] = {2, 3, 5}, mc64[] = {2, 3, 5, 9};
+    const int64_t kmax = prec == C128 ? 2048 : 4096;  // slots in 64 KiB of LDS
+    const int64_t H = (N + 1) / 2, O = (H + 1) & ~1LL, ns = (O + H) / 2 + 2;
+    if (N < 3 || ns > kmax) return 0;
+    const int64_t I = (ns + 3) / 4;
+    const int *ms = prec == C128 ? mc128 : mc64;
+    const int nm = prec == C128 ? 3 : 4;
+    for (int i = 0; i < nm; ++i)
+        if (64LL * ms[i] >= I + kRingHalo) return ms[i];
+    return 0;
+}
+
+template <typename R>
+static bool ring_sub_t(int m, const void *in, void *out, const Geom &g, const CoinF64 &C, int x0, int64_t t0,
+                       int64_t K, hipStream_t s) {
+    const bool real = C.im[0] == 0.0 && C.im[1] == 0.0 && C.im[2] == 0.0 && C.im[3] == 0.0;
+#define QW_RING_SUB(MV)                                                                                   \
+    do {                                                                                                  \
+        if (real)                                                                                         \
+            hipLaunchKernelGGL((k_ring_sub<R, MV, true>), dim3(1), dim3(256), 0, s, (const cv<R> *)in,    \
+                               (cv<R> *)out, g.Lx, g.ps, x0, t0, K, to_coin<R>(C));                       \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_ring_sub<R, MV, false>), dim3(1), dim3(256), 0, s, (const cv<R> *)in,   \
+                               (cv<R> *)out, g.Lx, g.ps, x0, t0, K, to_coin<R>(C));                       \
+    } while (0)
+    switch (m) {
+    case 2: QW_RING_SUB(2); return true;
+    case 3: QW_RING_SUB(3); return true;
+    case 5: QW_RING_SUB(5); return true;
+    case 9: if constexpr (sizeof(R) == 4) { QW_RING_SUB(9); return true; } return false;
+    default: return false;
+    }
+#undef QW_RING_SUB
+}
+
+hipError_t launch_ring_sub(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,
+                           int64_t x0, int64_t t0, hipStream_t s, LaunchInfo *info, int64_t *slots) {
+    const int64_t N = g.Lx;
+    const int m = ring_sub_m(prec, N);
+    if (m == 0 || g.Ly != 1 || t0 < 0 || K < 1 || t0 + K > (N - 1) / 2 || x0 < 0 || x0 >= N)
+        return hipErrorNotSupported;
+    if (info) {
+        const double bytes = (double)N * 2 * (prec == C128 ? 16.0 : 8.0);
+        info->bytes_read = bytes;
+        info->bytes_written = bytes;
+    }
+    if (slots) {
+        const int64_t H = (N + 1) / 2, O = (H + 1) & ~1LL;
+        *slots = (O + H) / 2 + 2;
+    }
+    const bool ok = prec == C128 ? ring_sub_t<double>(m, in, out, g, C, (int)x0, t0, K, s)
+                                 : ring_sub_t<float>(m, in, out, g, C, (int)x0, t0, K, s);
+    return ok ? hipGetLastError() : hipErrorNotSupported;
 }
 
 hipError_t launch_ring_whole(int prec, const void *in, void *out, const Geom &g, const CoinF64 &C, int64_t K,

@@ -451,6 +451,60 @@ def test_small_ring_halo_kernel_bitwise(prec, real):
 
 
 @pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
+def test_ring_live_sublattice_bitwise(prec):
+    """A ring walk from one site whose support stays clear of itself runs on its
+    live parity only (half the sites per step): bit for bit the one-step kernel's
+    amplitudes, stepped in pieces (odd and even start times), up to t = (N - 1) / 2
+    and past it (the full-lattice kernel takes over), after walk_set_state (no
+    longer from one site: the full lattice; complex128) and for odd and even
+    rings; the updates counted are the live ones."""
+    rng = np.random.default_rng(40 + prec)
+    for N in (7, 64, 101, 1000, 2001, 2048) + ((3001, 4095) if prec == qwalk.QW_C64 else ()):
+        U = inputs.haar_unitary(rng, 2)
+        psi0 = inputs.haar_state(rng, 2)
+        x0 = (int(rng.integers(0, N)), 0)
+        half = (N - 1) // 2
+        pieces = (1, 2, 13, 32, 33, half // 3, half - (81 + half // 3)) if half > 120 else (1, 2, max(half - 3, 0))
+        pieces = tuple(p for p in pieces if p > 0) + (5, 64)  # the last two cross t = (N - 1) / 2
+        res, upd = [], []
+        for depth in (1, 0):
+            w = qwalk.Walk((N,), inputs.RING, qwalk.DENSE, psi0, x0, prec=prec, dense=U)
+            w.set_options(block_depth=depth, renorm_every=0)
+            states = []
+            for k, n in enumerate(pieces):
+                w.step(n)
+                states.append(w.get_state())
+                if k == 2:
+                    upd.append(w.stats().updates)
+            w.destroy()
+            res.append(states)
+        for k, (a, b) in enumerate(zip(res[0], res[1])):
+            assert np.array_equal(a, b), (N, k)
+        if N >= 64:  # live slots only while t <= (N - 1) / 2: about half the ring per step
+            assert upd[1] <= 0.55 * N * 2 * sum(pieces[:3]), (N, upd)
+        if prec != qwalk.QW_C128:  # (set_state wants a state normalised to fp64 accuracy)
+            continue
+        # a state set from outside runs on the full lattice
+        w = qwalk.Walk((N,), inputs.RING, qwalk.DENSE, psi0, x0, prec=prec, dense=U)
+        w.set_options(renorm_every=0)
+        w.step(3)
+        st = w.get_state()
+        w.set_state(st)
+        u0 = w.stats().updates
+        w.step(4)
+        assert w.stats().updates - u0 == N * 2 * 4
+        got = w.get_state()
+        w.destroy()
+        w = qwalk.Walk((N,), inputs.RING, qwalk.DENSE, psi0, x0, prec=prec, dense=U)
+        w.set_options(block_depth=1, renorm_every=0)
+        w.step(7)
+        assert np.array_equal(got, w.get_state()), N
+        w.destroy()
+        _, psir = _oracle_run((N,), inputs.RING, U, psi0, x0, sum(pieces))
+        assert np.max(np.abs(_as_oracle_layout(res[1][-1]) - psir)) <= TOL64, N
+
+
+@pytest.mark.parametrize("prec", [qwalk.QW_C128, qwalk.QW_C64])
 def test_ring_real_coin_bitwise(prec):
     """Real coins (Hadamard, real rotations) take a real-arithmetic path in the
     whole-ring kernel: the same amplitudes as one step per launch (complex
