@@ -441,7 +441,10 @@ def _bcheck(rc: int):
 
 
 class Batch:
-    """Independent ring walks in one persistent launch (walk_batch_*)."""
+    """Independent ring walks in one persistent launch (walk_batch_*).  The options
+    are those of qw_batch_opts; full_lattice=True makes the tiled rings update both
+    parities of their light cone (by default a ring whose cone never wraps keeps
+    only the live parity: the same results, half the work)."""
 
     def __init__(self, N, T, angles, psi0, x0=None, prec: int = QW_C64, nbins: int = 0,
                  keep_probabilities: bool = False, tiled_variant: int = 0, no_graph: bool = False,
