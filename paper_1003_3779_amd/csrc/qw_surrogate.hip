@@ -91,38 +91,45 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const bf16_t *p, 
 // One launch runs one product, or two independent ones side by side (blocks
 // [0, nb0) the first, gx0 blocks per row of tiles; the rest the second): the
 // batch-1024 training products have 64 tiles each, a quarter of the chip.
-__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int nb0, int gx0, int gx1) {
+// NW waves per 128 x 128 tile: 8 (each 64 x 32 outputs, two per SIMD: one's LDS
+// reads under the other's MFMAs) as launched; 4 (each 64 x 64, one per SIMD, fewer
+// LDS reads per MFMA) measured slower at every launch size the network uses.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int nb0, int gx0, int gx1) {
+    static_assert(NW == 4 || NW == 8, "four or eight waves per tile");
+    constexpr int TJ = NW == 4 ? 2 : 1, WN = 32 * TJ, NWN = kBN / WN;  // 32-column tiles per wave, wave width
+    constexpr int RPP = 8 * NW, NH = kBM / RPP;                       // staging rows per pass, passes
     __shared__ bf16_t sA[2][kBM * kLdsRow];
     __shared__ bf16_t sB[2][kBN * kLdsRow];
     const bool second = (int)blockIdx.x >= nb0;
     const GemmArgs g = second ? g1 : g0;
     const int bl = second ? (int)blockIdx.x - nb0 : (int)blockIdx.x, gx = second ? gx1 : gx0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / NWN, wn = wave % NWN;
     const int m0 = (bl / gx) * kBM, n0 = (bl % gx) * kBN;
-    float16_t acc[2][2];
+    float16_t acc[2][TJ];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    // staging: each thread moves 4 x 16 bytes of A and of B per K tile (rows
-    // lrow + 32 h, columns lk .. lk + 7)
+    // staging: each thread moves NH x 16 bytes of A and of B per K tile (rows
+    // lrow + RPP h, columns lk .. lk + 7)
     const int lrow = tid >> 3, lk = (tid & 7) * 8;
     const __amdgpu_buffer_rsrc_t ra = operand_rsrc(g.A, g.M, g.lda), rb = operand_rsrc(g.B, g.N, g.ldb);
-    unsigned oa[4], ob[4];  // byte offsets of this thread's rows at k = 0
+    unsigned oa[NH], ob[NH];  // byte offsets of this thread's rows at k = 0
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        oa[h] = ((unsigned)(m0 + lrow + 32 * h) * (unsigned)g.lda + (unsigned)lk) * 2u;
-        ob[h] = ((unsigned)(n0 + lrow + 32 * h) * (unsigned)g.ldb + (unsigned)lk) * 2u;
+    for (int h = 0; h < NH; ++h) {
+        oa[h] = ((unsigned)(m0 + lrow + RPP * h) * (unsigned)g.lda + (unsigned)lk) * 2u;
+        ob[h] = ((unsigned)(n0 + lrow + RPP * h) * (unsigned)g.ldb + (unsigned)lk) * 2u;
     }
     const int nk = (g.K + kBK - 1) / kBK, nkp = (nk + kPF - 1) / kPF * kPF;
-    uint4 va[kPF][4], vb[kPF][4];
+    uint4 va[kPF][NH], vb[kPF][NH];
     auto fetch = [&](int p, int kt) {
         const bool in = kt * kBK + lk < g.K;  // K % 8 == 0: a thread's 8 columns are all in or all out
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int h = 0; h < NH; ++h) {
             va[p][h] = __builtin_bit_cast(
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, in ? oa[h] + (unsigned)kt * (kBK * 2) : kNoLoad, 0, 0));
             vb[p][h] = __builtin_bit_cast(
@@ -131,8 +138,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int n
     };
     auto stage = [&](int buf, int p) {
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int r = lrow + 32 * h;
+        for (int h = 0; h < NH; ++h) {
+            const int r = lrow + RPP * h;
             *(uint4 *)(sA[buf] + r * kLdsRow + lk) = va[p][h];
             *(uint4 *)(sB[buf] + r * kLdsRow + lk) = vb[p][h];
         }
@@ -143,16 +150,17 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int n
             // lane l supplies row (l % 32) of the 32 x 16 operand, k = kk + 8 (l / 32) .. + 7
             // (A and B alike, so each product pairs equal k)
             const int kof = kk + 8 * (lane >> 5);
-            bf16x8_t a[2], b[2];
+            bf16x8_t a[2], b[TJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 2; ++i)
                 a[i] = *(const bf16x8_t *)(sA[buf] + (wm * 64 + i * 32 + (lane & 31)) * kLdsRow + kof);
-                b[i] = *(const bf16x8_t *)(sB[buf] + (wn * 64 + i * 32 + (lane & 31)) * kLdsRow + kof);
-            }
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                b[j] = *(const bf16x8_t *)(sB[buf] + (wn * WN + j * 32 + (lane & 31)) * kLdsRow + kof);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     };
@@ -188,12 +196,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int n
         __builtin_amdgcn_make_buffer_rsrc(g.Cb, (short)0, g.Cb ? g.M * g.ldcb * 2 : 0, 0x00020000);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        float bn[2];
-        unsigned mk[2][16];  // the aligned 4 bytes holding each mask element (its own register: 2-byte
+        float bn[TJ];
+        unsigned mk[TJ][16];  // the aligned 4 bytes holding each mask element (its own register: 2-byte
                              // loads would share registers and wait for each other)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < TJ; ++j) {
+            const int n = n0 + wn * WN + j * 32 + (lane & 31);
             bn[j] = __builtin_bit_cast(
                 float, __builtin_amdgcn_raw_buffer_load_b32(rbias, n < g.N ? (unsigned)n * 4u : kNoLoad, 0, 0));
 #pragma unroll
@@ -204,8 +212,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int n
             }
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < TJ; ++j) {
+            const int n = n0 + wn * WN + j * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -777,20 +785,25 @@ hipError_t gemm_args(GemmArgs &a, const bf16_t *A, int lda, const bf16_t *B, int
 inline int gemm_gx(const GemmArgs &a) { return (a.N + kBN - 1) / kBN; }
 inline int gemm_blocks(const GemmArgs &a) { return gemm_gx(a) * ((a.M + kBM - 1) / kBM); }
 
+// a launch of nb blocks (na of them the first product)
+void launch_gemm(hipStream_t st, int nb, const GemmArgs &a, const GemmArgs &b, int na) {
+    hipLaunchKernelGGL(k_gemm_nt<8>, dim3(nb), dim3(512), 0, st, a, b, na, gemm_gx(a), gemm_gx(b));
+}
+
 hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
                 const float *bias, const bf16_t *mask, int ldm, int relu, float *C, int ldc, bf16_t *Cb, int ldcb) {
     GemmArgs a;
     hipError_t e = gemm_args(a, A, lda, B, ldb, M, N, K, alpha, bias, mask, ldm, relu, C, ldc, Cb, ldcb);
     if (e != hipSuccess) return e;
     const int nb = gemm_blocks(a);
-    hipLaunchKernelGGL(k_gemm_nt, dim3(nb), dim3(256), 0, st, a, a, nb, gemm_gx(a), gemm_gx(a));
+    launch_gemm(st, nb, a, a, nb);
     return hipGetLastError();
 }
 
 // two independent products in one launch
 hipError_t gemm_pair(hipStream_t st, const GemmArgs &a, const GemmArgs &b) {
     const int na = gemm_blocks(a), nb = gemm_blocks(b);
-    hipLaunchKernelGGL(k_gemm_nt, dim3(na + nb), dim3(256), 0, st, a, b, na, gemm_gx(a), gemm_gx(b));
+    launch_gemm(st, na + nb, a, b, na);
     return hipGetLastError();
 }
 
