@@ -91,12 +91,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const bf16_t *p, 
 // One launch runs one product, or two independent ones side by side (blocks
 // [0, nb0) the first, gx0 blocks per row of tiles; the rest the second): the
 // batch-1024 training products have 64 tiles each, a quarter of the chip.
-// NW waves per 128 x 128 tile: 8 (each 64 x 32 outputs, two per SIMD: one's LDS
-// reads under the other's MFMAs) as launched; 4 (each 64 x 64, one per SIMD, fewer
-// LDS reads per MFMA) measured slower at every launch size the network uses.
+// NW waves per 128 x 128 tile: 16 (each 32 x 32 outputs, four per SIMD: some
+// waves' LDS reads run under the others' MFMAs) as launched; 8 (64 x 32, two per
+// SIMD) and 4 (64 x 64, one per SIMD; fewer LDS reads per MFMA) measured slower
+// at every launch size the network uses.
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, int nb0, int gx0, int gx1) {
-    static_assert(NW == 4 || NW == 8, "four or eight waves per tile");
+    static_assert(NW == 4 || NW == 8 || NW == 16, "four, eight or sixteen waves per tile");
+    constexpr int TI = NW == 16 ? 1 : 2, WM = 32 * TI;                 // 32-row tiles per wave, wave height
     constexpr int TJ = NW == 4 ? 2 : 1, WN = 32 * TJ, NWN = kBN / WN;  // 32-column tiles per wave, wave width
     constexpr int RPP = 8 * NW, NH = kBM / RPP;                       // staging rows per pass, passes
     __shared__ bf16_t sA[2][kBM * kLdsRow];
@@ -107,9 +109,9 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, i
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / NWN, wn = wave % NWN;
     const int m0 = (bl / gx) * kBM, n0 = (bl % gx) * kBN;
-    float16_t acc[2][TJ];
+    float16_t acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j)
 #pragma unroll
@@ -150,15 +152,15 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, i
             // lane l supplies row (l % 32) of the 32 x 16 operand, k = kk + 8 (l / 32) .. + 7
             // (A and B alike, so each product pairs equal k)
             const int kof = kk + 8 * (lane >> 5);
-            bf16x8_t a[2], b[TJ];
+            bf16x8_t a[TI], b[TJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *(const bf16x8_t *)(sA[buf] + (wm * 64 + i * 32 + (lane & 31)) * kLdsRow + kof);
+            for (int i = 0; i < TI; ++i)
+                a[i] = *(const bf16x8_t *)(sA[buf] + (wm * WM + i * 32 + (lane & 31)) * kLdsRow + kof);
 #pragma unroll
             for (int j = 0; j < TJ; ++j)
                 b[j] = *(const bf16x8_t *)(sB[buf] + (wn * WN + j * 32 + (lane & 31)) * kLdsRow + kof);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, i
     const __amdgpu_buffer_rsrc_t rcb =
         __builtin_amdgcn_make_buffer_rsrc(g.Cb, (short)0, g.Cb ? g.M * g.ldcb * 2 : 0, 0x00020000);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TI; ++i) {
         float bn[TJ];
         unsigned mk[TJ][16];  // the aligned 4 bytes holding each mask element (its own register: 2-byte
                              // loads would share registers and wait for each other)
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, i
                 float, __builtin_amdgcn_raw_buffer_load_b32(rbias, n < g.N ? (unsigned)n * 4u : kNoLoad, 0, 0));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const unsigned off = n < g.N ? ((unsigned)m * (unsigned)g.ldm + (unsigned)n) * 2u : kNoLoad;
                 mk[j][r] = __builtin_amdgcn_raw_buffer_load_b32(rmask, off & ~3u, 0, 0);
             }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nt(GemmArgs g0, GemmArgs g1, i
             const int n = n0 + wn * WN + j * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const bool in = m < g.M && n < g.N;
                 float v = g.alpha * acc[i][j][r] + bn[j];
                 const bf16_t mv = (bf16_t)(n & 1 ? mk[j][r] >> 16 : mk[j][r] & 0xffffu);
@@ -787,7 +789,7 @@ inline int gemm_blocks(const GemmArgs &a) { return gemm_gx(a) * ((a.M + kBM - 1)
 
 // a launch of nb blocks (na of them the first product)
 void launch_gemm(hipStream_t st, int nb, const GemmArgs &a, const GemmArgs &b, int na) {
-    hipLaunchKernelGGL(k_gemm_nt<8>, dim3(nb), dim3(512), 0, st, a, b, na, gemm_gx(a), gemm_gx(b));
+    hipLaunchKernelGGL(k_gemm_nt<16>, dim3(nb), dim3(1024), 0, st, a, b, na, gemm_gx(a), gemm_gx(b));
 }
 
 hipError_t gemm(hipStream_t st, const bf16_t *A, int lda, const bf16_t *B, int ldb, int M, int N, int K, float alpha,
