@@ -38,6 +38,7 @@ namespace {
 constexpr int kBT = 512;          // threads per batch workgroup
 constexpr int kWaves = kBT / 64;
 constexpr int kMaxBins = 1024;
+constexpr int kSlimSlots = 8192;  // slots per plane of a slim-kernel buffer (walks needing more run in the other)
 constexpr int kNumCfg = 8;        // tiled-path variants (sites per lane MT, steps per block K)
 constexpr int kCfgMT[kNumCfg] = {8, 8, 16, 16, 4, 4, 2, 2};
 constexpr int kCfgK[kNumCfg] = {16, 32, 32, 64, 16, 32, 16, 32};
@@ -60,8 +61,9 @@ struct BatchArgs {
     const int32_t *order;   // queue position -> walk index (tiled walks first)
     int32_t n;
     int32_t n_tiled;
+    int32_t n_slim;         // positions [0, n_slim): tiled walks of the slim kernel (k_batch<..., true>)
     int32_t nbins;
-    unsigned int *queue;    // [0], [1]: next position in the tiled / whole part
+    unsigned int *queue;    // [0], [1], [2]: next position in the tiled / whole / slim part
     void *slots;            // per-workgroup slot buffers: 2 buffers x 2 planes x slot_elems
     int64_t slot_elems;
     double *moments;        // n x 3
@@ -75,6 +77,7 @@ struct BatchArgs {
     uint64_t link_thr;      // a link is broken when its Philox word < link_thr (0: none at random)
     uint32_t key0, key1;    // generator key (seed)
     int32_t full_lattice;   // 1: tiled rings update both parities of their cone
+    void *slim_slots;       // the slim kernel's slot buffers: 2 buffers x 2 planes x kSlimSlots
 };
 
 // fp64 norm of per-wave partial sums: lane 0 of each wave has written its sum
@@ -630,85 +633,108 @@ template <typename R> __device__ __forceinline__ void finish_walk(const BatchArg
     __syncthreads();
 }
 
-// The queue holds the tiled walks first (positions [0, n_tiled)), then the
-// walks held whole (positions [n_tiled, n)), each part longest-first.  A
-// workgroup drains the first part, then the second: two loops in sequence, so
-// the register budgets of the two paths never overlap.
-template <typename R, int MMAX>
+// The queue holds the slim kernel's walks first (positions [0, n_slim)), then
+// the other tiled walks ([n_slim, n_tiled)), then the walks held whole
+// ([n_tiled, n)), each part longest-first.  SLIM: rings on their live
+// sublattice with 128-slot tiles only, whose registers (about 100) let two
+// workgroups share a compute unit -- two narrow cones in flight at once.  Else a
+// workgroup drains the other tiled walks, then the whole ones: two loops in
+// sequence, so the register budgets of the two paths never overlap.
+template <typename R, int MMAX, bool SLIM = false>
 __global__ __launch_bounds__(kBT) void k_batch(BatchArgs A) {
     __shared__ int s_q;
-    __shared__ cv<R> L0[2][kBT];
-    __shared__ cv<R> L1[2][kBT];
     __shared__ BinAcc s_bins[kMaxBins];
     __shared__ double s_red[3][kWaves];
     __shared__ double s_norm[2][kWaves];
     for (int i = threadIdx.x; i < A.nbins; i += kBT) s_bins[i] = 0;
-    for (;;) {
-        if (threadIdx.x == 0) s_q = (int)atomicAdd(&A.queue[0], 1u);
-        __syncthreads();
-        const int q = s_q;
-        __syncthreads();
-        if (q >= A.n_tiled) break;  // uniform across the workgroup
-        const int wi = A.order[q];
-        const WalkDesc w = A.walks[wi];
-        SiteAcc acc;
-        // rotation-frame walks (cones that never wrap) keep only the live sublattice
-        // when its slots fit the workgroup's buffers
-        const bool sub = w.rot && !A.full_lattice && sub_slots(w, kCfgK[w.cfg]) <= A.slot_elems;
-        if (!w.rot) {
-            // a walk whose light cone wraps the ring: full SU(2) coin, one variant
-            walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
-        } else if (kCfgMT[w.cfg] == 2) {
-            // the shortest cones (on the live sublattice a tile spans twice its slots)
-            if (w.rswap) run_tiled<R, 2, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else run_tiled<R, 2, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-        } else if (kCfgMT[w.cfg] == 4) {
-            // short cones: small tiles keep more of the workgroup's waves busy
-            if (w.rswap) run_tiled<R, 4, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else run_tiled<R, 4, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-        } else if (kCfgMT[w.cfg] == 8) {
-            if (w.rswap) run_tiled<R, 8, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else run_tiled<R, 8, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-        } else {
-            // 16 sites per lane in complex64; complex128 keeps 8 (register budget)
-            constexpr int MT = sizeof(R) == 8 ? 8 : 16;
-            if (w.rswap) run_tiled<R, MT, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
-            else run_tiled<R, MT, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+    if constexpr (SLIM) {
+        for (;;) {
+            if (threadIdx.x == 0) s_q = (int)atomicAdd(&A.queue[2], 1u);
+            __syncthreads();
+            const int q = s_q;
+            __syncthreads();
+            if (q >= A.n_slim) break;  // uniform across the workgroup
+            const int wi = A.order[q];
+            const WalkDesc w = A.walks[wi];
+            SiteAcc acc;
+            BatchArgs As = A;  // its own slot buffers, kSlimSlots slots each
+            As.slots = A.slim_slots;
+            As.slot_elems = kSlimSlots;
+            if (w.rswap) walk_tiled_sub<R, 2, CoinRotS<R, true>>(w, As, kCfgK[w.cfg], s_bins, s_norm, acc);
+            else walk_tiled_sub<R, 2, CoinRotS<R, false>>(w, As, kCfgK[w.cfg], s_bins, s_norm, acc);
+            finish_walk<R>(A, wi, acc, s_bins, s_red);
         }
-        finish_walk<R>(A, wi, acc, s_bins, s_red);
-    }
-    for (;;) {
-        if (threadIdx.x == 0) s_q = A.n_tiled + (int)atomicAdd(&A.queue[1], 1u);
-        __syncthreads();
-        const int q = s_q;
-        __syncthreads();
-        if (q >= A.n) break;
-        const int wi = A.order[q];
-        const WalkDesc w = A.walks[wi];
-        SiteAcc acc;
-        switch (w.m) {
+    } else {
+        __shared__ cv<R> L0[2][kBT];
+        __shared__ cv<R> L1[2][kBT];
+        for (;;) {
+            if (threadIdx.x == 0) s_q = A.n_slim + (int)atomicAdd(&A.queue[0], 1u);
+            __syncthreads();
+            const int q = s_q;
+            __syncthreads();
+            if (q >= A.n_tiled) break;  // uniform across the workgroup
+            const int wi = A.order[q];
+            const WalkDesc w = A.walks[wi];
+            SiteAcc acc;
+            // rotation-frame walks (cones that never wrap) keep only the live sublattice
+            // when its slots fit the workgroup's buffers
+            const bool sub = w.rot && !A.full_lattice && sub_slots(w, kCfgK[w.cfg]) <= A.slot_elems;
+            if (!w.rot) {
+                // a walk whose light cone wraps the ring: full SU(2) coin, one variant
+                walk_tiled<R, 8, Coin2<R>>(w, A, 16, s_bins, s_norm, acc);
+            } else if (kCfgMT[w.cfg] == 2) {
+                // the shortest cones (on the live sublattice a tile spans twice its slots)
+                if (w.rswap) run_tiled<R, 2, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+                else run_tiled<R, 2, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            } else if (kCfgMT[w.cfg] == 4) {
+                // short cones: small tiles keep more of the workgroup's waves busy
+                if (w.rswap) run_tiled<R, 4, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+                else run_tiled<R, 4, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            } else if (kCfgMT[w.cfg] == 8) {
+                if (w.rswap) run_tiled<R, 8, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+                else run_tiled<R, 8, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            } else {
+                // 16 sites per lane in complex64; complex128 keeps 8 (register budget)
+                constexpr int MT = sizeof(R) == 8 ? 8 : 16;
+                if (w.rswap) run_tiled<R, MT, CoinRotS<R, true>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+                else run_tiled<R, MT, CoinRotS<R, false>>(sub, w, A, kCfgK[w.cfg], s_bins, s_norm, acc);
+            }
+            finish_walk<R>(A, wi, acc, s_bins, s_red);
+        }
+        for (;;) {
+            if (threadIdx.x == 0) s_q = A.n_tiled + (int)atomicAdd(&A.queue[1], 1u);
+            __syncthreads();
+            const int q = s_q;
+            __syncthreads();
+            if (q >= A.n) break;
+            const int wi = A.order[q];
+            const WalkDesc w = A.walks[wi];
+            SiteAcc acc;
+            switch (w.m) {
 #define QW_WHOLE_CASE(MM)                                                                                  \
-        case MM:                                                                                           \
-            if (MM <= MMAX) {                                                                              \
-                if (A.links) walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>, true>(w, A, L0, L1, s_bins, s_norm, acc); \
-                else if (w.rot) walk_whole<R, (MM <= MMAX ? MM : 1), CoinRot<R>>(w, A, L0, L1, s_bins, s_norm, acc); \
-                else walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>>(w, A, L0, L1, s_bins, s_norm, acc);         \
-            }                                                                                              \
-            break;
-        QW_WHOLE_CASE(1) QW_WHOLE_CASE(2) QW_WHOLE_CASE(3) QW_WHOLE_CASE(4)
-        QW_WHOLE_CASE(5) QW_WHOLE_CASE(6) QW_WHOLE_CASE(7) QW_WHOLE_CASE(8)
-        QW_WHOLE_CASE(9) QW_WHOLE_CASE(10) QW_WHOLE_CASE(11) QW_WHOLE_CASE(12)
-        QW_WHOLE_CASE(13) QW_WHOLE_CASE(14) QW_WHOLE_CASE(15) QW_WHOLE_CASE(16)
+            case MM:                                                                                           \
+                if (MM <= MMAX) {                                                                              \
+                    if (A.links) walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>, true>(w, A, L0, L1, s_bins, s_norm, acc); \
+                    else if (w.rot) walk_whole<R, (MM <= MMAX ? MM : 1), CoinRot<R>>(w, A, L0, L1, s_bins, s_norm, acc); \
+                    else walk_whole<R, (MM <= MMAX ? MM : 1), Coin2<R>>(w, A, L0, L1, s_bins, s_norm, acc);         \
+                }                                                                                              \
+                break;
+            QW_WHOLE_CASE(1) QW_WHOLE_CASE(2) QW_WHOLE_CASE(3) QW_WHOLE_CASE(4)
+            QW_WHOLE_CASE(5) QW_WHOLE_CASE(6) QW_WHOLE_CASE(7) QW_WHOLE_CASE(8)
+            QW_WHOLE_CASE(9) QW_WHOLE_CASE(10) QW_WHOLE_CASE(11) QW_WHOLE_CASE(12)
+            QW_WHOLE_CASE(13) QW_WHOLE_CASE(14) QW_WHOLE_CASE(15) QW_WHOLE_CASE(16)
 #undef QW_WHOLE_CASE
-        default: break;
+            default: break;
+            }
+            finish_walk<R>(A, wi, acc, s_bins, s_red);
         }
-        finish_walk<R>(A, wi, acc, s_bins, s_red);
     }
 }
 
 __global__ void k_queue_reset(unsigned int *q) {
     q[0] = 0u;
     q[1] = 0u;
+    q[2] = 0u;
 }
 
 constexpr int kMinTiledSites = 2048;  // shorter rings are always held whole
@@ -813,6 +839,7 @@ struct qw_batch {
     std::vector<int64_t> p_off;
     int64_t total_sites = 0;
     int64_t n_tiled = 0;
+    int64_t n_slim = 0;  // tiled walks of the slim kernel (the first n_slim queue positions)
     int32_t renorm_every = 0;
     double renorm_tol = 1e-7;
     int32_t links = 0, walls = 0;  // broken links / reflecting ends
@@ -828,6 +855,8 @@ struct qw_batch {
     float *d_bins = nullptr;
     double *d_P = nullptr;
     int grid = 0;
+    int grid_slim = 0;  // workgroups of the slim kernel
+    void *d_slim_slots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     // untuned default per size bucket (N <= 1e4, <= 1e5, larger): (128 slots, 32
@@ -850,6 +879,7 @@ void free_batch(qw_batch *b) {
     (void)hipFree(b->d_order);
     (void)hipFree(b->d_queue);
     (void)hipFree(b->d_slots);
+    (void)hipFree(b->d_slim_slots);
     (void)hipFree(b->d_moments);
     (void)hipFree(b->d_bins);
     (void)hipFree(b->d_P);
@@ -859,12 +889,14 @@ void free_batch(qw_batch *b) {
     delete b;
 }
 
-BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, int32_t n, int32_t n_tiled) {
+BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, int32_t n, int32_t n_tiled,
+                    int32_t n_slim) {
     BatchArgs A;
     A.walks = walks;
     A.order = order;
     A.n = n;
     A.n_tiled = n_tiled;
+    A.n_slim = n_slim;
     A.nbins = b->nbins;
     A.queue = b->d_queue;
     A.slots = b->d_slots;
@@ -880,19 +912,31 @@ BatchArgs make_args(qw_batch *b, const WalkDesc *walks, const int32_t *order, in
     A.key0 = b->key0;
     A.key1 = b->key1;
     A.full_lattice = b->full_lattice;
+    A.slim_slots = b->d_slim_slots;
     return A;
 }
 
+// the slim kernel over queue positions [0, n_slim) (if any), then the general one
+// over the rest (if any); grid: the general kernel's workgroups
 hipError_t enqueue(qw_batch *b, const BatchArgs &A, int grid) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, b->stream, b->d_queue);
-    if (b->prec == QW_C128)
-        hipLaunchKernelGGL((k_batch<double, kMaxMC128>), dim3(grid), dim3(kBT), 0, b->stream, A);
-    else
-        hipLaunchKernelGGL((k_batch<float, kMaxMC64>), dim3(grid), dim3(kBT), 0, b->stream, A);
+    if (A.n_slim > 0) {
+        const int gs = std::max(1, std::min(b->grid_slim, (int)A.n_slim));
+        if (b->prec == QW_C128)
+            hipLaunchKernelGGL((k_batch<double, kMaxMC128, true>), dim3(gs), dim3(kBT), 0, b->stream, A);
+        else
+            hipLaunchKernelGGL((k_batch<float, kMaxMC64, true>), dim3(gs), dim3(kBT), 0, b->stream, A);
+    }
+    if (A.n > A.n_slim) {
+        if (b->prec == QW_C128)
+            hipLaunchKernelGGL((k_batch<double, kMaxMC128>), dim3(grid), dim3(kBT), 0, b->stream, A);
+        else
+            hipLaunchKernelGGL((k_batch<float, kMaxMC64>), dim3(grid), dim3(kBT), 0, b->stream, A);
+    }
     return hipGetLastError();
 }
 
-int persistent_grid(int prec, int64_t n) {
+int persistent_grid(int prec, int64_t n, bool slim = false) {
     int dev = 0, cus = 256, per = 1;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t p;
@@ -900,9 +944,11 @@ int persistent_grid(int prec, int64_t n) {
     }
     hipError_t e;
     if (prec == QW_C128)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<double, kMaxMC128>, kBT, 0);
+        e = slim ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<double, kMaxMC128, true>, kBT, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<double, kMaxMC128>, kBT, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<float, kMaxMC64>, kBT, 0);
+        e = slim ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<float, kMaxMC64, true>, kBT, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<float, kMaxMC64>, kBT, 0);
     if (e != hipSuccess || per < 1) {
         (void)hipGetLastError();
         per = 1;
@@ -930,6 +976,35 @@ bool walk_sub(const qw_batch *b, const WalkDesc &w) {
 // most one site per step)
 double walk_performed(const qw_batch *b, const WalkDesc &w) {
     return walk_sub(b, w) ? 0.5 * walk_work(w) : walk_work(w);
+}
+
+// whether the slim kernel runs the walk: on its live sublattice with 128-slot tiles,
+// its slots within the slim buffers
+bool walk_slim(const qw_batch *b, const WalkDesc &w) {
+    return walk_sub(b, w) && kCfgMT[w.cfg] == 2 && sub_slots(w, kCfgK[w.cfg]) <= kSlimSlots;
+}
+
+// the queue order: the slim kernel's walks, the other tiled walks, the walks held
+// whole, each part longest-first; sets n_tiled and n_slim
+void build_order(qw_batch *b) {
+    const int64_t n = b->n;
+    b->order.resize(n);
+    for (int64_t i = 0; i < n; ++i) b->order[i] = (int32_t)i;
+    std::vector<double> work(n);
+    std::vector<int> part(n);
+    for (int64_t i = 0; i < n; ++i) {
+        work[i] = walk_work(b->walks[i]);
+        part[i] = b->walks[i].cfg < 0 ? 2 : (walk_slim(b, b->walks[i]) ? 0 : 1);
+    }
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t a, int32_t c) {
+        if (part[a] != part[c]) return part[a] < part[c];
+        return work[a] > work[c];
+    });
+    b->n_tiled = b->n_slim = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        b->n_tiled += part[i] < 2;
+        b->n_slim += part[i] == 0;
+    }
 }
 
 }  // namespace
@@ -1091,23 +1166,11 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
         for (auto &w : b->walks)
             if (w.cfg >= 0) w.cfg = b->bucket_cfg[size_bucket(w.N)];
     }
-    // longest first
-    b->order.resize(n);
-    for (int64_t i = 0; i < n; ++i) b->order[i] = (int32_t)i;
-    std::vector<double> work(n);
-    for (int64_t i = 0; i < n; ++i) work[i] = walk_work(b->walks[i]);
-    // tiled walks first, then the walks held whole; each part longest-first
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t a, int32_t c) {
-        const bool ta = b->walks[a].cfg >= 0, tc = b->walks[c].cfg >= 0;
-        if (ta != tc) return ta;
-        return work[a] > work[c];
-    });
-    b->n_tiled = 0;
-    for (int64_t i = 0; i < n; ++i) b->n_tiled += b->walks[i].cfg >= 0;
     for (int64_t i = 0; i < n; ++i) b->walks[i].p_off = b->p_off[i];
-
-    b->grid = persistent_grid(prec, n);
     b->slot_elems = maxN_tiled;
+    build_order(b);
+    b->grid = persistent_grid(prec, n);
+    b->grid_slim = persistent_grid(prec, n, true);
     const size_t esz = prec == QW_C128 ? 16 : 8;
     hipError_t e = hipSuccess;
     auto alloc = [&](void **p, size_t bytes) {
@@ -1122,6 +1185,7 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
     };
     bool ok = alloc((void **)&b->d_walks, sizeof(WalkDesc) * n) && alloc((void **)&b->d_order, sizeof(int32_t) * n) &&
               alloc((void **)&b->d_queue, 256) && alloc(&b->d_slots, (size_t)b->grid * 4 * maxN_tiled * esz) &&
+              alloc(&b->d_slim_slots, (size_t)b->grid_slim * 4 * kSlimSlots * esz) &&
               alloc((void **)&b->d_moments, sizeof(double) * 3 * n) &&
               (b->nbins == 0 || alloc((void **)&b->d_bins, sizeof(float) * b->nbins * n)) &&
               (!b->keep || alloc((void **)&b->d_P, sizeof(double) * off));
@@ -1148,7 +1212,7 @@ int walk_batch_create(int64_t n, const int64_t *N, const int64_t *T, const doubl
 
 int walk_batch_run(qw_batch_t b) {
     if (!b) return bfail(QW_EINVAL, "batch handle is NULL");
-    const BatchArgs A = make_args(b, b->d_walks, b->d_order, (int32_t)b->n, (int32_t)b->n_tiled);
+    const BatchArgs A = make_args(b, b->d_walks, b->d_order, (int32_t)b->n, (int32_t)b->n_tiled, (int32_t)b->n_slim);
     QB_HIP(hipEventRecord(b->ev[0], b->stream), "hipEventRecord");
     if (b->use_graph) {
         if (!b->gexec) {
@@ -1278,7 +1342,7 @@ int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save) {
                 e = hipMemcpyAsync(dord, torder.data(), sizeof(int32_t) * torder.size(), hipMemcpyHostToDevice, b->stream);
             // the tuning runs write moments/bins/P of walk indices 0..ns-1 of the tuning table,
             // which alias the first walks of the batch: outputs are recomputed by the next run
-            const BatchArgs A = make_args(b, dw, dord, (int32_t)pick.size(), (int32_t)pick.size());
+            const BatchArgs A = make_args(b, dw, dord, (int32_t)pick.size(), (int32_t)pick.size(), 0);
             const int grid = std::min<int>(b->grid, (int)pick.size());
             float ms = 0.0f;
             if (cfg < 0) {
@@ -1311,9 +1375,22 @@ int walk_batch_tune(qw_batch_t b, int32_t samples, int32_t save) {
         b->bucket_cfg[bk] = best;
         for (auto i : v) b->walks[i].cfg = best;
     }
+    // the variants chosen decide which walks the slim kernel takes: new queue order,
+    // and a new graph at the next run (the old one holds the old part sizes)
+    build_order(b);
     QB_HIP(hipMemcpyAsync(b->d_walks, b->walks.data(), sizeof(WalkDesc) * b->n, hipMemcpyHostToDevice, b->stream),
            "upload of the walk table");
+    QB_HIP(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream),
+           "upload of the queue order");
     QB_HIP(hipStreamSynchronize(b->stream), "stream synchronise");
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
     if (save) {
         auto cache = read_cache();
         const std::string dk = device_key();

@@ -154,8 +154,8 @@ def test_batch_autotuner(tmp_path, monkeypatch):
     b.tune(samples=4, save=True)
     info = b.info()
     for k in range(3):
-        assert 0 <= info.bucket_cfg[k] < 6
-        assert info.bucket_tile_sites[k] in (256, 512, 1024) and info.bucket_depth[k] in (16, 32, 64)
+        assert 0 <= info.bucket_cfg[k] < 8
+        assert info.bucket_tile_sites[k] in (128, 256, 512, 1024) and info.bucket_depth[k] in (16, 32, 64)
     b.run()
     assert np.array_equal(b.moments(), before)      # every variant is the same arithmetic
     assert (tmp_path / "tune.txt").exists()
